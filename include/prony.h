@@ -1,0 +1,155 @@
+/*
+ * prony.h -- C ABI of the MI355X (gfx950) hot path of the multivariate
+ * matrix-pencil Prony method (N. Bosner, "Parallel Prony's method with
+ * multivariate matrix pencil approach and its numerical aspect",
+ * arXiv 2012.11430).
+ *
+ * The library computes, on one GPU, the data-parallel steps of Algorithm 1:
+ * the samples f(k) of the exponential sum (Sec. 1, eq. exp_sum), the
+ * multilevel Toeplitz matrices T = [f(k-h)] and T_l = [f(k-h+e_l)]
+ * (Sec. 1), the pencil matrices S_l = U^* T_l V Sigma^{-1}
+ * (Sec. 1, eq. generateSl) and the Vandermonde products of the coefficient
+ * least-squares problem A^T c = f (Sec. 1, eq. ls_probl). The SVD of T, the
+ * eigendecomposition of C_mu and the small least-squares solve stay on the
+ * host, as the paper assigns them (Sec. 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array pointers are DEVICE pointers unless stated otherwise; the
+ *    caller allocates and owns them. The library owns only its workspace.
+ *  - Complex numbers are interleaved {re, im} doubles (complex128).
+ *  - d in {1,2,3}, n >= 1, N = (n+1)^d. The index set I_n = {0..n}^d is
+ *    ordered row-major (last coordinate fastest): idx(k) = sum_l k_l (n+1)^(d-l).
+ *  - The sample grid holds f(p) for p in {-n..n+1}^d, row-major, flat:
+ *    g(p) = sum_l (p_l + n) (2n+2)^(d-l); it has (2n+2)^d entries and covers
+ *    every argument k-h and k-h+e_l.
+ *  - Calls enqueue work on the handle's stream and return without waiting.
+ *    Arguments are validated on the host before anything is launched; a bad
+ *    argument returns PRONY_EINVAL (or PRONY_ENOTSUP for a valid request the
+ *    kernels do not cover) and launches nothing. A failing HIP call returns
+ *    PRONY_EHIP; faults inside kernels surface at the next synchronising call.
+ *    prony_last_error() returns a text for the last failure on the handle.
+ *  - Documented preconditions that are not checked on the device: sigma_j > 0
+ *    and finite inputs. NaN inputs propagate to the outputs.
+ *  - A handle may be used by one host thread at a time.
+ */
+#ifndef PRONY_H
+#define PRONY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct prony_handle_s* prony_handle_t;
+
+typedef enum {
+    PRONY_OK = 0,
+    PRONY_EINVAL = 1,    /* invalid argument (nothing launched)             */
+    PRONY_ENOTSUP = 2,   /* valid but unsupported request (nothing launched) */
+    PRONY_EHIP = 3,      /* a HIP runtime call failed                        */
+    PRONY_ENOMEM = 4,    /* workspace allocation failed                      */
+    PRONY_ECAPTURE = 5,  /* workspace growth needed while the stream is being captured */
+    PRONY_ENODEV = 6     /* the handle has no device (validation-only handle) */
+} prony_status_t;
+
+typedef enum {
+    PRONY_FP64 = 0,      /* complex128 operands, FP64 MFMA, FP64 accumulation            */
+    PRONY_FP32 = 1       /* complex64 operands, FP32 MFMA with FP32 accumulation per tile,
+                            FP64 reduction of the tile partials and FP64 Sigma^{-1}       */
+} prony_prec_t;
+
+/* Flag of prony_build_S: also form S_0 = U^* T V Sigma^{-1} (equal to I for an
+   exact SVD of T) and store it in front of S_1..S_d. */
+#define PRONY_WITH_S0 1u
+
+/* ---- handle ---------------------------------------------------------------- */
+
+/* Create a handle bound to HIP device `device` (the device is made current for
+   every call on the handle). The stream is the null stream until set.
+   device = -1 creates a validation-only handle that touches no GPU: every call
+   validates its arguments as usual and then returns PRONY_ENODEV instead of
+   launching (for testing argument checks on machines without a GPU). */
+prony_status_t prony_create(prony_handle_t* handle, int device);
+
+/* Free the workspace and the handle. Waits for the handle's stream first. */
+prony_status_t prony_destroy(prony_handle_t handle);
+
+/* Enqueue all later work on `stream` (a hipStream_t owned by the caller). */
+prony_status_t prony_set_stream(prony_handle_t handle, void* stream);
+
+/* Wait for the handle's stream; reports asynchronous kernel faults as PRONY_EHIP. */
+prony_status_t prony_synchronize(prony_handle_t handle);
+
+/* Text describing the last failure on the handle (never NULL). */
+const char* prony_last_error(prony_handle_t handle);
+
+/* Pre-size the workspace for problems up to (d_max, n_max, m_max) so that later
+   calls allocate nothing (needed before capturing a stream into a HIP graph). */
+prony_status_t prony_reserve(prony_handle_t handle, int d_max, int n_max, int m_max);
+
+/* ---- Algorithm 1, GPU steps -------------------------------------------------- */
+
+/* Samples of the exponential sum (Sec. 1, eq. exp_sum), with the additive noise
+   model of Sec. 4:
+     f(p) = sum_{j<m} c_j exp(-2 pi i <t_j, p>) + noise(p),  p in {-n..n+1}^d.
+   The phase <t_j,p> is reduced by its nearest integer before the exponential.
+   t:     m x d doubles, row-major (t_j(l) at t[j*d + l]), nodes in [0,1)^d.
+   c:     m complex128.
+   noise: (2n+2)^d complex128 added to the samples, or NULL for none.
+   f:     (2n+2)^d complex128 output (the sample grid).
+   Requires 1 <= m <= 4096. */
+prony_status_t prony_samples(prony_handle_t handle, int d, int n, int m,
+                             const double* t, const double* c, const double* noise,
+                             double* f);
+
+/* Multilevel Toeplitz matrix (Sec. 1): which = 0 gives T[k,h] = f(k-h), which = l
+   in 1..d gives T_l[k,h] = f(k-h+e_l), for k, h in I_n.
+   f:   the sample grid ((2n+2)^d complex128).
+   out: N x N complex128, row k at out + 2*k*ld; ld >= N (elements). `out` may be
+        device memory or pinned host memory mapped for the device.
+   The write is N*N*16 bytes; it exists to feed the host SVD of T and to test the
+   index map. Requires N*ld < 2^62. */
+prony_status_t prony_build_T(prony_handle_t handle, int d, int n, int which,
+                             const double* f, double* out, int64_t ld);
+
+/* Pencil matrices (Sec. 1, eq. generateSl):
+     S_l = U^* T_l V Sigma^{-1},  l = 1..d,
+   with T_l generated on the fly from the sample grid (never stored).
+   f:      sample grid ((2n+2)^d complex128).
+   U, V:   N x m complex128; entry (k, j) at U + 2*(k*u_rs + j*u_cs) (strides in
+           complex elements, both >= 1). V is the right factor itself, not V^*.
+   sigma:  m doubles > 0 (device memory).
+   prec:   PRONY_FP64 or PRONY_FP32 (see prony_prec_t).
+   flags:  0 or PRONY_WITH_S0.
+   S:      output, (d or d+1) x m x m complex128, row-major per matrix: S_l(i,j)
+           at S + 2*((l*m + i)*m + j), l counted from the first stored matrix.
+   Requires 1 <= m <= min(N, 32). */
+prony_status_t prony_build_S(prony_handle_t handle, int d, int n, int m, const double* f,
+                             const double* U, int64_t u_rs, int64_t u_cs,
+                             const double* sigma,
+                             const double* V, int64_t v_rs, int64_t v_cs,
+                             prony_prec_t prec, unsigned flags, double* S);
+
+/* Vandermonde products of the least-squares step argmin_c ||A^T c - f||_2
+   (Sec. 1, eq. ls_probl; Algorithm 1, last line):
+     A^T[k, j] = prod_l z_j(l)^{k_l}  (k in I_n),
+     gram = (A^T)^* A^T  (m x m),  rhs = (A^T)^* f_I  (m),
+   where f_I is the sample grid restricted to I_n. The host then solves
+   gram c = rhs in FP64.
+   z:      m x d complex128, row-major (z_j(l) at z + 2*(j*d + l)).
+   f:      sample grid ((2n+2)^d complex128).
+   gram:   m x m complex128 output, row-major.
+   rhs:    m complex128 output.
+   AT_out: N x m complex128 output (row-major) or NULL to skip writing A^T.
+   Requires 1 <= m <= min(N, 64). */
+prony_status_t prony_coeffs(prony_handle_t handle, int d, int n, int m,
+                            const double* z, const double* f,
+                            double* gram, double* rhs, double* AT_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRONY_H */

@@ -1,0 +1,168 @@
+"""Python binding of libprony with torch tensors (device memory and streams only).
+
+The functions carry the C ABI's names without the `prony_` prefix. Each call
+checks dtypes, devices and shapes, passes raw device pointers and strides to the
+library on torch's current stream, and returns torch tensors. No arithmetic of
+the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import torch
+
+from . import _lib
+
+_handles: dict = {}
+_lock = threading.Lock()
+
+
+def _handle(device: torch.device):
+    """One library handle per device (created on first use)."""
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    with _lock:
+        h = _handles.get(idx)
+        if h is None:
+            lib = _lib.load()
+            hp = ctypes.c_void_p()
+            st = lib.prony_create(ctypes.byref(hp), idx)
+            if st != _lib.PRONY_OK:
+                raise _lib.PronyError(st, f"prony_create(device={idx}) failed")
+            h = hp
+            _handles[idx] = h
+    return h
+
+
+def _call(name: str, device: torch.device, *args):
+    lib = _lib.load()
+    h = _handle(device)
+    stream = torch.cuda.current_stream(device)
+    st = lib.prony_set_stream(h, ctypes.c_void_p(stream.cuda_stream))
+    if st != _lib.PRONY_OK:
+        raise _lib.PronyError(st, "prony_set_stream failed")
+    st = getattr(lib, name)(h, *args)
+    if st != _lib.PRONY_OK:
+        msg = lib.prony_last_error(h)
+        raise _lib.PronyError(st, f"{name}: {msg.decode() if msg else ''}")
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else ctypes.c_void_p(0)
+
+
+def _require(x: torch.Tensor, name: str, dtype, device=None, contiguous=True):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {x.dtype}")
+    if not x.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if device is not None and x.device != device:
+        raise ValueError(f"{name} is on {x.device}, expected {device}")
+    if contiguous and not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def grid_size(d: int, n: int) -> int:
+    return (2 * n + 2) ** d
+
+
+def samples(t: torch.Tensor, c: torch.Tensor, n: int, noise: torch.Tensor | None = None,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+    """Sample grid f(p), p in {-n..n+1}^d (prony_samples). t: (m, d) float64, c: (m,) complex128."""
+    _require(t, "t", torch.float64)
+    dev = t.device
+    _require(c, "c", torch.complex128, dev)
+    m, d = t.shape
+    if c.shape != (m,):
+        raise ValueError("c must have shape (m,)")
+    G = grid_size(d, n)
+    if noise is not None:
+        _require(noise, "noise", torch.complex128, dev)
+        if noise.numel() != G:
+            raise ValueError("noise must have (2n+2)^d entries")
+    if out is None:
+        out = torch.empty(G, dtype=torch.complex128, device=dev)
+    else:
+        _require(out, "out", torch.complex128, dev)
+        if out.numel() != G:
+            raise ValueError("out must have (2n+2)^d entries")
+    _call("prony_samples", dev, d, n, m, _ptr(t), _ptr(c), _ptr(noise), _ptr(out))
+    return out
+
+
+def build_T(f: torch.Tensor, d: int, n: int, which: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """T (which=0) or T_which as an N x N complex128 matrix (prony_build_T)."""
+    _require(f, "f", torch.complex128)
+    N = (n + 1) ** d
+    if f.numel() != grid_size(d, n):
+        raise ValueError("f must hold the (2n+2)^d sample grid")
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.complex128, device=f.device)
+    if out.dtype != torch.complex128 or out.dim() != 2 or out.shape[0] != N or out.shape[1] != N \
+            or out.stride(1) != 1:
+        raise ValueError("out must be an N x N complex128 matrix with unit column stride")
+    _call("prony_build_T", f.device, d, n, which, _ptr(f), _ptr(out), out.stride(0))
+    return out
+
+
+def build_S(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,
+            prec: str = "fp64", with_s0: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
+    """S_l = U^* T_l V Sigma^{-1}, l = 1..d (prony_build_S); shape (d[+1], m, m).
+
+    V is the right factor itself (torch.linalg.svd returns V^* as Vh: pass Vh.mH).
+    prec: 'fp64' or 'fp32'.
+    """
+    _require(f, "f", torch.complex128)
+    dev = f.device
+    if f.numel() != grid_size(d, n):
+        raise ValueError("f must hold the (2n+2)^d sample grid")
+    _require(U, "U", torch.complex128, dev, contiguous=False)
+    _require(V, "V", torch.complex128, dev, contiguous=False)
+    _require(sigma, "sigma", torch.float64, dev)
+    N = (n + 1) ** d
+    if U.dim() != 2 or U.shape[0] != N or V.shape != U.shape:
+        raise ValueError("U and V must be N x m")
+    m = U.shape[1]
+    if sigma.shape != (m,):
+        raise ValueError("sigma must have shape (m,)")
+    if prec not in ("fp64", "fp32"):
+        raise ValueError("prec must be 'fp64' or 'fp32'")
+    ells = d + (1 if with_s0 else 0)
+    if out is None:
+        out = torch.empty((ells, m, m), dtype=torch.complex128, device=dev)
+    else:
+        _require(out, "out", torch.complex128, dev)
+        if out.shape != (ells, m, m):
+            raise ValueError("out has the wrong shape")
+    _call("prony_build_S", dev, d, n, m, _ptr(f), _ptr(U), U.stride(0), U.stride(1), _ptr(sigma),
+          _ptr(V), V.stride(0), V.stride(1), _lib.PRONY_FP32 if prec == "fp32" else _lib.PRONY_FP64,
+          _lib.PRONY_WITH_S0 if with_s0 else 0, _ptr(out))
+    return out
+
+
+def coeffs(z: torch.Tensor, f: torch.Tensor, d: int, n: int, want_AT: bool = False):
+    """Gram (A^T)^* A^T and rhs (A^T)^* f_I (prony_coeffs); optionally A^T (N x m)."""
+    _require(z, "z", torch.complex128)
+    dev = z.device
+    _require(f, "f", torch.complex128, dev)
+    if f.numel() != grid_size(d, n):
+        raise ValueError("f must hold the (2n+2)^d sample grid")
+    if z.dim() != 2 or z.shape[1] != d:
+        raise ValueError("z must be m x d")
+    m = z.shape[0]
+    gram = torch.empty((m, m), dtype=torch.complex128, device=dev)
+    rhs = torch.empty(m, dtype=torch.complex128, device=dev)
+    AT = torch.empty(((n + 1) ** d, m), dtype=torch.complex128, device=dev) if want_AT else None
+    _call("prony_coeffs", dev, d, n, m, _ptr(z), _ptr(f), _ptr(gram), _ptr(rhs), _ptr(AT))
+    return (gram, rhs, AT) if want_AT else (gram, rhs)
+
+
+def reserve(device: torch.device, d_max: int, n_max: int, m_max: int) -> None:
+    """Pre-size the library workspace (prony_reserve)."""
+    _call("prony_reserve", device, d_max, n_max, m_max)
+
+
+def synchronize(device: torch.device) -> None:
+    _call("prony_synchronize", device)

@@ -1,0 +1,95 @@
+// Internal declarations shared by the translation units of libprony.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "prony.h"
+
+struct prony_handle_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void* ws = nullptr;          // device workspace owned by the handle
+    size_t ws_bytes = 0;
+    int num_cus = 256;
+    size_t lds_per_block = 65536;
+    std::string err;
+};
+
+namespace prony {
+
+prony_status_t fail(prony_handle_t h, prony_status_t st, const std::string& msg);
+prony_status_t hip_fail(prony_handle_t h, hipError_t e, const char* what);
+
+// Make the handle's device current for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Grow the workspace to at least `bytes`. Returns PRONY_ECAPTURE when growth is
+// needed while the handle's stream is being captured.
+prony_status_t ensure_workspace(prony_handle_t h, size_t bytes);
+
+// Launch-error check after a kernel launch.
+prony_status_t check_launch(prony_handle_t h, const char* what);
+
+inline int64_t ipow(int64_t b, int e) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Workspace bytes of one prony_build_S / prony_coeffs call (largest precision/flag).
+size_t pencil_workspace_bytes(prony_handle_t h, int d, int n, int m);
+size_t coeffs_workspace_bytes(int d, int n, int m);
+
+// Common argument validation for (d, n): 1 <= d <= 3, n >= 1, sizes within int32.
+prony_status_t check_dn(prony_handle_t h, int d, int n);
+
+// ---- index maps (Sec. 1: I_n = {0..n}^d row-major; grid {-n..n+1}^d row-major) ----
+
+// Flat grid offset G(k) = sum_l k_l (2n+2)^(d-l) of the point k in I_n with
+// row-major index idx (base n+1).
+__host__ __device__ inline int grid_offset_of_index(int idx, int d, int n) {
+    const int P = n + 1, Q = 2 * n + 2;
+    int g = 0, scale = 1;
+    for (int l = d - 1; l >= 0; --l) {
+        const int q = idx / P;
+        g += (idx - q * P) * scale;
+        idx = q;
+        scale *= Q;
+    }
+    return g;
+}
+
+// Grid offset of the origin shift: c0 = G((n,..,n)), so that f(k-h+e) sits at
+// G(k) - G(h) + c0 + G(e).
+__host__ __device__ inline int grid_center(int d, int n) {
+    const int Q = 2 * n + 2;
+    int g = 0;
+    for (int l = 0; l < d; ++l) g = g * Q + n;
+    return g;
+}
+
+// Grid stride s_l = (2n+2)^(d-l) of unit vector e_l, l = 1..d (0 for l = 0).
+__host__ __device__ inline int grid_shift(int d, int n, int ell) {
+    if (ell <= 0) return 0;
+    const int Q = 2 * n + 2;
+    int s = 1;
+    for (int l = ell; l < d; ++l) s *= Q;
+    return s;
+}
+
+}  // namespace prony

@@ -1,0 +1,123 @@
+// Handle, stream, workspace and error reporting of libprony.
+#include <cstdio>
+#include <new>
+
+#include "common.h"
+
+namespace prony {
+
+prony_status_t fail(prony_handle_t h, prony_status_t st, const std::string& msg) {
+    if (h) h->err = msg;
+    return st;
+}
+
+prony_status_t hip_fail(prony_handle_t h, hipError_t e, const char* what) {
+    return fail(h, PRONY_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+prony_status_t check_launch(prony_handle_t h, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, what);
+    return PRONY_OK;
+}
+
+prony_status_t check_dn(prony_handle_t h, int d, int n) {
+    if (d < 1 || d > 3) return fail(h, PRONY_EINVAL, "d must be 1, 2 or 3");
+    if (n < 1) return fail(h, PRONY_EINVAL, "n must be >= 1");
+    // keep (2n+2)^d and N^2 index arithmetic inside the 32/64-bit ranges used
+    if (ipow(2 * (int64_t)n + 2, d) > (int64_t(1) << 30))
+        return fail(h, PRONY_ENOTSUP, "sample grid larger than 2^30 points");
+    return PRONY_OK;
+}
+
+prony_status_t ensure_workspace(prony_handle_t h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return PRONY_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(h->stream, &cs);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(h, PRONY_ECAPTURE, "workspace must grow during stream capture; call prony_reserve first");
+    if (h->ws) {
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+        e = hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+        if (e != hipSuccess) return hip_fail(h, e, "hipFree");
+    }
+    const size_t grow = align_up(bytes + bytes / 4, size_t(1) << 20);
+    e = hipMalloc(&h->ws, grow);
+    if (e != hipSuccess) {
+        h->ws = nullptr;
+        (void)hipGetLastError();
+        return fail(h, PRONY_ENOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
+    }
+    h->ws_bytes = grow;
+    return PRONY_OK;
+}
+
+}  // namespace prony
+
+using namespace prony;
+
+extern "C" prony_status_t prony_create(prony_handle_t* handle, int device) {
+    if (!handle) return PRONY_EINVAL;
+    *handle = nullptr;
+    if (device == -1) {
+        prony_handle_s* h = new (std::nothrow) prony_handle_s();
+        if (!h) return PRONY_ENOMEM;
+        h->device = -1;
+        *handle = h;
+        return PRONY_OK;
+    }
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return PRONY_EHIP;
+    if (device < 0 || device >= count) return PRONY_EINVAL;
+    prony_handle_s* h = new (std::nothrow) prony_handle_s();
+    if (!h) return PRONY_ENOMEM;
+    h->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        h->num_cus = prop.multiProcessorCount;
+        h->lds_per_block = prop.sharedMemPerBlock;
+    }
+    *handle = h;
+    return PRONY_OK;
+}
+
+extern "C" prony_status_t prony_destroy(prony_handle_t h) {
+    if (!h) return PRONY_EINVAL;
+    if (h->device < 0) {
+        delete h;
+        return PRONY_OK;
+    }
+    DeviceGuard g(h->device);
+    prony_status_t st = PRONY_OK;
+    if (h->ws) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) st = PRONY_EHIP;
+        if (hipFree(h->ws) != hipSuccess) st = PRONY_EHIP;
+    }
+    delete h;
+    return st;
+}
+
+extern "C" prony_status_t prony_set_stream(prony_handle_t h, void* stream) {
+    if (!h) return PRONY_EINVAL;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    return PRONY_OK;
+}
+
+extern "C" prony_status_t prony_synchronize(prony_handle_t h) {
+    if (!h) return PRONY_EINVAL;
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    return PRONY_OK;
+}
+
+extern "C" const char* prony_last_error(prony_handle_t h) {
+    if (!h) return "invalid handle";
+    return h->err.c_str();
+}

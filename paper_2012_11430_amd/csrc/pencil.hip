@@ -1,0 +1,488 @@
+// Pencil matrices S_l = U^* T_l V Sigma^{-1} (Sec. 1, eq. generateSl) on MFMA.
+//
+// Formulation. With h' = h - e_l, T_l[k,h] = f(k - h') and the d products
+// Y_l = T_l V are one product of the shift-free "extended" Toeplitz matrix
+// T_ext[k,h'] = f(k-h'), h' in {-1..n}^d, with the stacked shifted right
+// factors V_l[h',q] = V[h'+e_l, q] (zero where h'+e_l leaves I_n):
+//     [Y_1 .. Y_d] = T_ext [V_1 .. V_d].
+// The complex product is run as a real one: every complex column q yields the
+// real columns (Re, Im) and every complex T entry a contributes two MFMAs, one
+// with Re(a) against (Re v, Im v) and one with Im(a) against (-Im v, Re v).
+// The second factor is packed once per call in that pair layout.
+//
+// Kernels:
+//   pencil_pack   packs V_l (pair layout), U (Re/Im pairs) and the grid
+//                 offsets G(h') of the extended index set into the workspace;
+//   pencil_tiles  one workgroup = 64 rows k x one chunk of h'; the T_ext tile
+//                 is generated from a flat window of the sample grid staged in
+//                 LDS, multiplied on MFMA against the packed V_l, then the
+//                 U^* reduction over the 64 rows runs on MFMA as well and the
+//                 m x (d m) partial is stored;
+//   pencil_reduce sums the partials of all workgroups in FP64 in a fixed order
+//                 and applies Sigma^{-1} in FP64.
+#include <algorithm>
+#include <type_traits>
+
+#include "common.h"
+
+namespace prony {
+namespace {
+
+constexpr int kWaves = 4;               // waves per workgroup
+constexpr int kRowsPerWave = 16;        // MFMA M dimension
+constexpr int kRowsPerTile = kWaves * kRowsPerWave;
+constexpr int kThreads = kWaves * 64;
+
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+template <typename T>
+using pair_t = typename Pair<T>::type;
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t fma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // Row of the 16x16 result held in accumulator element r by lanes 16g..16g+15.
+    static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
+template <>
+struct Mfma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t fma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+
+struct PencilPlan {
+    int d, n, N, m;
+    int ells;       // stacked matrices: d, or d + 1 with S_0
+    int first_ell;  // 0 with S_0, else 1
+    int C;          // complex columns ells * m
+    int nb;         // 16-wide blocks of the 2C real columns
+    int nrp;        // 16 * nb
+    int mbi;        // 16-row blocks of the m output rows
+    int kb;         // (n+2)^d extended indices h'
+    int kc;         // h' per chunk (multiple of 16)
+    int sk;         // chunks
+    int rt;         // 64-row tiles
+    int nwg;        // rt * sk workgroups
+    int win_cap;    // window capacity (complex elements)
+    int c0;         // grid offset of the origin shift
+    size_t lds_bytes;
+    // workspace offsets (bytes)
+    size_t off_v, off_u, off_g, off_p, ws_bytes;
+};
+
+// Grid offset of the extended index h' (row-major over {-1..n}^d).
+__host__ __device__ inline int ext_offset(int hx, int d, int n) {
+    const int E = n + 2, Q = 2 * n + 2;
+    int g = 0, scale = 1;
+    for (int l = d - 1; l >= 0; --l) {
+        const int q = hx / E;
+        g += (hx - q * E - 1) * scale;
+        hx = q;
+        scale *= Q;
+    }
+    return g;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* __restrict__ U, int64_t u_rs,
+                                                   int64_t u_cs, const double2* __restrict__ V, int64_t v_rs,
+                                                   int64_t v_cs, pair_t<T>* __restrict__ vp, pair_t<T>* __restrict__ up,
+                                                   int* __restrict__ gt) {
+    using T2 = pair_t<T>;
+    const int64_t nv = (int64_t)P.sk * P.kc * P.nrp;
+    const int mup = P.mbi * 16;
+    const int64_t nu = (int64_t)P.rt * kRowsPerTile * mup;
+    const int64_t ng = (int64_t)P.sk * P.kc;
+    const int64_t total = nv + nu + ng;
+    const int E = P.n + 2, Pn = P.n + 1;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < nv) {
+            const int hx = (int)(i / P.nrp);
+            const int j = (int)(i - (int64_t)hx * P.nrp);
+            const int c = j >> 1;
+            const bool odd = j & 1;
+            double vr = 0.0, vi = 0.0;
+            if (hx < P.kb && c < P.C) {
+                const int li = c / P.m, q = c - li * P.m;
+                const int ell = li + P.first_ell;   // 0 = T itself, l = shift along axis l
+                int rem = hx, idx = 0, scale = 1;
+                bool inside = true;
+                for (int l = P.d - 1; l >= 0; --l) {
+                    const int qq = rem / E;
+                    const int coord = rem - qq * E - 1 + (l == ell - 1 ? 1 : 0);
+                    rem = qq;
+                    inside = inside && coord >= 0 && coord <= P.n;
+                    idx += coord * scale;
+                    scale *= Pn;
+                }
+                if (inside) {
+                    const double2 v = V[idx * v_rs + q * v_cs];
+                    vr = v.x;
+                    vi = v.y;
+                }
+            }
+            // (Re a) multiplies the first member, (Im a) the second.
+            vp[i] = odd ? T2{(T)vi, (T)vr} : T2{(T)vr, (T)(-vi)};
+        } else if (i < nv + nu) {
+            const int64_t r = i - nv;
+            const int k = (int)(r / mup);
+            const int col = (int)(r - (int64_t)k * mup);
+            double ur = 0.0, ui = 0.0;
+            if (k < P.N && col < P.m) {
+                const double2 u = U[k * u_rs + col * u_cs];
+                ur = u.x;
+                ui = u.y;
+            }
+            up[r] = T2{(T)ur, (T)ui};
+        } else {
+            const int hx = (int)(i - nv - nu);
+            gt[hx] = ext_offset(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
+        }
+    }
+}
+
+template <typename T, int NBMAX>
+__global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const double2* __restrict__ grid,
+                                                         const pair_t<T>* __restrict__ vp,
+                                                         const pair_t<T>* __restrict__ up,
+                                                         const int* __restrict__ gtab, pair_t<T>* __restrict__ part) {
+    using T2 = pair_t<T>;
+    using M = Mfma<T>;
+    using acc_t = typename M::acc_t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T2* win = reinterpret_cast<T2*>(smem);
+    int* gt = reinterpret_cast<int*>(smem + align_up(sizeof(T2) * (size_t)P.win_cap, 16));
+    T* esum = reinterpret_cast<T*>(smem + align_up(sizeof(T2) * (size_t)P.win_cap, 16) +
+                                   align_up(sizeof(int) * (size_t)P.kc, 16));
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const bool odd = lane & 1;
+
+    // Workgroups are dealt to the 8 XCDs round-robin; map consecutive ids of one
+    // XCD to the same chunk of h' so that its packed V rows stay in that L2.
+    const int id = blockIdx.x;
+    const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
+    const int sk_i = L / P.rt, rt_i = L - (L / P.rt) * P.rt;
+
+    const int k_first = rt_i * kRowsPerTile;
+    const int k_last = min(k_first + kRowsPerTile - 1, P.N - 1);
+    const int h_first = sk_i * P.kc;
+    const int h_last = min(h_first + P.kc, P.kb) - 1;
+    const int lo = grid_offset_of_index(k_first, P.d, P.n) - gtab[h_last] + P.c0;
+    const int hi = grid_offset_of_index(k_last, P.d, P.n) - gtab[h_first] + P.c0;
+    const int W = hi - lo + 1;
+
+    for (int w = tid; w < W; w += kThreads) {
+        const double2 v = grid[lo + w];
+        win[w] = T2{(T)v.x, (T)v.y};
+    }
+    for (int i = tid; i < P.kc; i += kThreads) gt[i] = gtab[h_first + i];
+    const int esz = P.mbi * 16 * P.nrp;
+    for (int i = tid; i < esz; i += kThreads) esum[i] = T(0);
+    __syncthreads();
+
+    const int krow = min(k_first + wave * kRowsPerWave + col, P.N - 1);
+    const int gk = grid_offset_of_index(krow, P.d, P.n) + P.c0 - lo;
+
+    acc_t acc[NBMAX];
+#pragma unroll
+    for (int cb = 0; cb < NBMAX; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
+
+    const int nb = P.nb;
+    const T2* vrow = vp + (size_t)(h_first + g) * P.nrp + col;
+    const size_t kstride = (size_t)4 * P.nrp;
+    const int nks = P.kc >> 2;
+#pragma unroll 2
+    for (int ks = 0; ks < nks; ++ks) {
+        const T2 a = win[gk - gt[4 * ks + g]];
+        T2 b[NBMAX];
+#pragma unroll
+        for (int cb = 0; cb < NBMAX; ++cb)
+            if (cb < nb) b[cb] = vrow[ks * kstride + cb * 16];
+#pragma unroll
+        for (int cb = 0; cb < NBMAX; ++cb)
+            if (cb < nb) acc[cb] = M::fma(a.x, b[cb].x, acc[cb]);
+#pragma unroll
+        for (int cb = 0; cb < NBMAX; ++cb)
+            if (cb < nb) acc[cb] = M::fma(a.y, b[cb].y, acc[cb]);
+    }
+
+    // U^* reduction over this wave's 16 rows. The accumulators are the second
+    // MFMA operand directly: element r of lane (g, col) is Y[row(g,r)][16cb+col].
+    // Output column 2c gets Re(U^* Y)_c and 2c+1 gets Im: with the partner lane's
+    // value y' (column j^1), Re = Ur.Yr + Ui.Yi and Im = Ur.Yi - Ui.Yr.
+    const int mup = P.mbi * 16;
+    for (int ib = 0; ib < P.mbi; ++ib) {
+        acc_t e[NBMAX];
+#pragma unroll
+        for (int cb = 0; cb < NBMAX; ++cb) e[cb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = k_first + wave * kRowsPerWave + M::row(g, r);
+            const T2 u = up[(size_t)k * mup + ib * 16 + col];
+#pragma unroll
+            for (int cb = 0; cb < NBMAX; ++cb) {
+                if (cb < nb) {
+                    const T y = acc[cb][r];
+                    const T ys = __shfl_xor(y, 1);
+                    e[cb] = M::fma(u.x, y, e[cb]);
+                    e[cb] = M::fma(u.y, odd ? -ys : ys, e[cb]);
+                }
+            }
+        }
+        // Sum the four waves in a fixed order (bitwise reproducible).
+        for (int w = 0; w < kWaves; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int cb = 0; cb < NBMAX; ++cb) {
+                    if (cb < nb) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            esum[(ib * 16 + M::row(g, r)) * P.nrp + cb * 16 + col] += e[cb][r];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    T2* out = part + (size_t)(sk_i * P.rt + rt_i) * P.m * P.C;
+    for (int o = tid; o < P.m * P.C; o += kThreads) {
+        const int i = o / P.C, c = o - (o / P.C) * P.C;
+        out[o] = T2{esum[i * P.nrp + 2 * c], esum[i * P.nrp + 2 * c + 1]};
+    }
+}
+
+// S[l][i][q] = (sum over workgroup partials) / sigma_q, in FP64, fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void pencil_reduce(int m, int C, int nwg, const pair_t<T>* __restrict__ part,
+                                                     const double* __restrict__ sigma, double2* __restrict__ S) {
+    constexpr int kOut = 32, kGroups = 8;
+    __shared__ double2 red[kGroups][kOut];
+    const int tid = threadIdx.x;
+    const int o = blockIdx.x * kOut + (tid % kOut);
+    const int grp = tid / kOut;
+    const int tot = m * C;
+    double re = 0.0, im = 0.0;
+    if (o < tot) {
+        for (int s = grp; s < nwg; s += kGroups) {
+            const pair_t<T> v = part[(size_t)s * tot + o];
+            re += (double)v.x;
+            im += (double)v.y;
+        }
+    }
+    red[grp][tid % kOut] = make_double2(re, im);
+    __syncthreads();
+    if (grp == 0 && o < tot) {
+        re = 0.0;
+        im = 0.0;
+        for (int k = 0; k < kGroups; ++k) {
+            re += red[k][tid].x;
+            im += red[k][tid].y;
+        }
+        const int i = o / C, c = o - (o / C) * C;
+        const int li = c / m, q = c - li * m;
+        const double s = sigma[q];
+        S[((size_t)li * m + i) * m + q] = make_double2(re / s, im / s);
+    }
+}
+
+size_t lds_bytes_for(int win, int kc, int mbi, int nrp, size_t tsize) {
+    return align_up(2 * tsize * (size_t)win, 16) + align_up(4 * (size_t)kc, 16) + tsize * (size_t)mbi * 16 * nrp;
+}
+
+// Largest G-span of `len` consecutive indices of a row-major box of side `side`
+// (per-axis grid stride 2n+2), over all aligned starts used by the tiling.
+int max_span(int count, int len, int side, int d, int n, bool ext) {
+    int best = 0;
+    for (int s = 0; s < count; s += len) {
+        const int e = std::min(s + len, count) - 1;
+        const int a = ext ? ext_offset(s, d, n) : grid_offset_of_index(s, d, n);
+        const int b = ext ? ext_offset(e, d, n) : grid_offset_of_index(e, d, n);
+        best = std::max(best, b - a);
+    }
+    (void)side;
+    return best;
+}
+
+prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P) {
+    P = PencilPlan{};
+    P.d = d;
+    P.n = n;
+    P.N = (int)ipow(n + 1, d);
+    P.m = m;
+    P.ells = d + (with_s0 ? 1 : 0);
+    P.first_ell = with_s0 ? 0 : 1;
+    P.C = P.ells * m;
+    P.nb = (2 * P.C + 15) / 16;
+    P.nrp = 16 * P.nb;
+    P.mbi = (m + 15) / 16;
+    P.kb = (int)ipow(n + 2, d);
+    P.rt = (P.N + kRowsPerTile - 1) / kRowsPerTile;
+    P.c0 = grid_center(d, n);
+
+    const size_t budget = std::min<size_t>(h->lds_per_block, 96 * 1024);
+    const int target = 4 * h->num_cus;
+    int sk_target = std::max(1, target / P.rt);
+    int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), 16);
+    kc = std::max(kc, std::min(64, (int)align_up((size_t)P.kb, 16)));
+    const int rowspan = max_span(P.N, kRowsPerTile, n + 1, d, n, false);
+    for (;;) {
+        const int sk = (P.kb + kc - 1) / kc;
+        const int colspan = max_span(P.kb, kc, n + 2, d, n, true);
+        const int win = rowspan + colspan + 1;
+        const size_t lds = lds_bytes_for(win, kc, P.mbi, P.nrp, tsize);
+        if (lds <= budget) {
+            P.kc = kc;
+            P.sk = sk;
+            P.win_cap = win;
+            P.lds_bytes = lds;
+            break;
+        }
+        if (kc <= 16) return fail(h, PRONY_ENOTSUP, "prony_build_S: sample window does not fit in LDS");
+        kc = (int)align_up((size_t)(kc / 2), 16);
+    }
+    P.nwg = P.rt * P.sk;
+    const size_t t2 = 2 * tsize;
+    size_t off = 0;
+    P.off_v = off;
+    off = align_up(off + t2 * (size_t)P.sk * P.kc * P.nrp, 256);
+    P.off_u = off;
+    off = align_up(off + t2 * (size_t)P.rt * kRowsPerTile * P.mbi * 16, 256);
+    P.off_g = off;
+    off = align_up(off + 4 * (size_t)P.sk * P.kc, 256);
+    P.off_p = off;
+    off = align_up(off + t2 * (size_t)P.nwg * P.m * P.C, 256);
+    P.ws_bytes = off;
+    return PRONY_OK;
+}
+
+template <typename T>
+prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, const double* f, const double* U, int64_t u_rs,
+                             int64_t u_cs, const double* sigma, const double* V, int64_t v_rs, int64_t v_cs,
+                             double* S) {
+    using T2 = pair_t<T>;
+    prony_status_t st = ensure_workspace(h, P.ws_bytes);
+    if (st != PRONY_OK) return st;
+    unsigned char* ws = static_cast<unsigned char*>(h->ws);
+    T2* vp = reinterpret_cast<T2*>(ws + P.off_v);
+    T2* up = reinterpret_cast<T2*>(ws + P.off_u);
+    int* gt = reinterpret_cast<int*>(ws + P.off_g);
+    T2* part = reinterpret_cast<T2*>(ws + P.off_p);
+
+    const int64_t total = (int64_t)P.sk * P.kc * P.nrp + (int64_t)P.rt * kRowsPerTile * P.mbi * 16 +
+                          (int64_t)P.sk * P.kc;
+    const int pack_blocks = (int)std::min<int64_t>((total + 255) / 256, 4 * (int64_t)h->num_cus);
+    pencil_pack<T><<<pack_blocks, 256, 0, h->stream>>>(P, reinterpret_cast<const double2*>(U), u_rs, u_cs,
+                                                       reinterpret_cast<const double2*>(V), v_rs, v_cs, vp, up, gt);
+    if ((st = check_launch(h, "pencil_pack")) != PRONY_OK) return st;
+
+    const double2* grid = reinterpret_cast<const double2*>(f);
+    if (P.lds_bytes > 65536) {
+        hipError_t e = hipSuccess;
+        if (P.nb <= 4)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, 4>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+        else if (P.nb <= 8)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, 8>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+        else
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, 16>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+        if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+    }
+    if (P.nb <= 4)
+        pencil_tiles<T, 4><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, grid, vp, up, gt, part);
+    else if (P.nb <= 8)
+        pencil_tiles<T, 8><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, grid, vp, up, gt, part);
+    else
+        pencil_tiles<T, 16><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, grid, vp, up, gt, part);
+    if ((st = check_launch(h, "pencil_tiles")) != PRONY_OK) return st;
+
+    const int outs = P.m * P.C;
+    pencil_reduce<T><<<(outs + 31) / 32, 256, 0, h->stream>>>(P.m, P.C, P.nwg, part, sigma,
+                                                              reinterpret_cast<double2*>(S));
+    return check_launch(h, "pencil_reduce");
+}
+
+}  // namespace
+
+// Workspace bytes of one build_S call (used by prony_reserve).
+size_t pencil_workspace_bytes(prony_handle_t h, int d, int n, int m) {
+    size_t best = 0;
+    for (int s0 = 0; s0 < 2; ++s0)
+        for (size_t ts : {sizeof(float), sizeof(double)}) {
+            PencilPlan P;
+            if (make_plan(h, d, n, m, s0 == 1, ts, P) == PRONY_OK) best = std::max(best, P.ws_bytes);
+        }
+    return best;
+}
+
+}  // namespace prony
+
+using namespace prony;
+
+extern "C" prony_status_t prony_build_S(prony_handle_t h, int d, int n, int m, const double* f, const double* U,
+                                        int64_t u_rs, int64_t u_cs, const double* sigma, const double* V,
+                                        int64_t v_rs, int64_t v_cs, prony_prec_t prec, unsigned flags, double* S) {
+    if (!h) return PRONY_EINVAL;
+    prony_status_t st = check_dn(h, d, n);
+    if (st != PRONY_OK) return st;
+    const int64_t N = ipow(n + 1, d);
+    if (m < 1 || m > N) return fail(h, PRONY_EINVAL, "prony_build_S: m must be in 1..N");
+    if (m > 32) return fail(h, PRONY_ENOTSUP, "prony_build_S: m > 32 is not supported");
+    if (!f || !U || !V || !sigma || !S) return fail(h, PRONY_EINVAL, "prony_build_S: null pointer");
+    if (u_rs < 1 || u_cs < 1 || v_rs < 1 || v_cs < 1)
+        return fail(h, PRONY_EINVAL, "prony_build_S: strides must be >= 1");
+    if ((N - 1) * u_rs + (m - 1) * u_cs >= (int64_t(1) << 40) || (N - 1) * v_rs + (m - 1) * v_cs >= (int64_t(1) << 40))
+        return fail(h, PRONY_EINVAL, "prony_build_S: strides out of range");
+    if (prec != PRONY_FP64 && prec != PRONY_FP32) return fail(h, PRONY_EINVAL, "prony_build_S: bad precision");
+    if (flags & ~PRONY_WITH_S0) return fail(h, PRONY_EINVAL, "prony_build_S: unknown flag");
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    const bool s0 = (flags & PRONY_WITH_S0) != 0;
+    PencilPlan P;
+    if (prec == PRONY_FP32) {
+        if ((st = make_plan(h, d, n, m, s0, sizeof(float), P)) != PRONY_OK) return st;
+        return launch_pencil<float>(h, P, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
+    }
+    if ((st = make_plan(h, d, n, m, s0, sizeof(double), P)) != PRONY_OK) return st;
+    return launch_pencil<double>(h, P, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
+}
+
+extern "C" prony_status_t prony_reserve(prony_handle_t h, int d_max, int n_max, int m_max) {
+    if (!h) return PRONY_EINVAL;
+    prony_status_t st = check_dn(h, d_max, n_max);
+    if (st != PRONY_OK) return st;
+    if (m_max < 1 || m_max > 64) return fail(h, PRONY_EINVAL, "prony_reserve: m_max must be in 1..64");
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    size_t need = 0;
+    for (int d = 1; d <= d_max; ++d) {
+        const int m = std::min<int64_t>(m_max, ipow(n_max + 1, d));
+        if (m <= 32) need = std::max(need, pencil_workspace_bytes(h, d, n_max, m));
+        need = std::max(need, coeffs_workspace_bytes(d, n_max, m));
+    }
+    return ensure_workspace(h, need);
+}

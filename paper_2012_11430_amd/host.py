@@ -1,0 +1,116 @@
+"""FP64 host steps of Algorithm 1 that the paper assigns to the CPU (Sec. 3).
+
+* reduced SVD of T: LAPACK for small N, the block power method with rank
+  determination (Sec. 2.2, Algorithm 3) for large N;
+* eigendecomposition of the random combination C_mu and extraction of the
+  nodes z_j, t_j (Algorithm 1, lines 4-6);
+* the m x m solve of the normal equations gram c = rhs formed on the GPU
+  (Algorithm 1, line 7).
+
+`solve` chains these with the GPU calls of `api` into Algorithm 1.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.linalg
+import torch
+
+from . import api
+
+
+def _orth(X: np.ndarray) -> np.ndarray:
+    q, _ = np.linalg.qr(X)
+    return q
+
+
+def power_svd(T: np.ndarray, start_u: np.ndarray, start_v: np.ndarray, tol: float, rank: int | None = None,
+              max_sweeps: int = 60):
+    """Block power SVD with pivoted-QR rank determination in the first sweep
+    (Sec. 2.2, Algorithm 3). Returns (U, sigma, V, detected_rank, sweeps)."""
+    Uk, Vk = _orth(start_u), _orth(start_v)
+    norm_t = np.linalg.norm(T)
+    TV = T @ Vk
+    Qk = Uk.conj().T @ TV
+    sweeps, detected = 0, Vk.shape[1]
+    while np.linalg.norm(TV - Uk @ Qk) > tol * norm_t and sweeps < max_sweeps:
+        sweeps += 1
+        Uk = _orth(T @ Vk)
+        W = T.conj().T @ Uk
+        if sweeps == 1:
+            Qv, Rv, perm = scipy.linalg.qr(W, mode="economic", pivoting=True)
+            tail = np.sqrt(np.cumsum((np.abs(Rv) ** 2).sum(axis=1)[::-1])[::-1])
+            cut = np.nonzero(tail <= tol * np.linalg.norm(Rv))[0]
+            detected = int(cut[0]) if cut.size else Rv.shape[0]
+            r = detected if rank is None else rank
+            inv = np.empty_like(perm)
+            inv[perm] = np.arange(perm.size)
+            Vk = Qv[:, :r]
+            Qk = Rv[:r, inv].conj().T
+        else:
+            Vk, Rv = np.linalg.qr(W)
+            Qk = Rv.conj().T
+        TV = T @ Vk
+    Uq, s, Vqh = np.linalg.svd(Qk, full_matrices=False)
+    r = Vk.shape[1] if rank is None else rank
+    return (Uk @ Uq)[:, :r], s[:r], (Vk @ Vqh.conj().T)[:, :r], detected, sweeps
+
+
+def reduced_svd(T: np.ndarray, m: int, start_blocks=None, tol: float | None = None):
+    """Rank-m reduced SVD of T: LAPACK for N <= 1024, Algorithm 3 above."""
+    N = T.shape[0]
+    if N <= 1024 or start_blocks is None:
+        Uf, s, Vh = np.linalg.svd(T)
+        return Uf[:, :m], s[:m], Vh[:m].conj().T, s
+    tol = N * np.finfo(float).eps if tol is None else tol
+    U, s, V, _, _ = power_svd(T, start_blocks[0], start_blocks[1], tol, rank=m)
+    return U, s, V, s
+
+
+def nodes(S: np.ndarray, mu: np.ndarray):
+    """z_j(l) = diag(W^{-1} S_l W) with W the eigenvectors of C_mu = sum mu_l S_l;
+    t_j(l) = -arg z_j(l) / (2 pi) wrapped to [0, 1)."""
+    C = np.einsum("l,lij->ij", mu, S)
+    _, W = np.linalg.eig(C)
+    lu = scipy.linalg.lu_factor(W)
+    z = np.stack([np.diag(scipy.linalg.lu_solve(lu, S[l] @ W)) for l in range(S.shape[0])], axis=1)
+    t = np.mod(-np.angle(z) / (2.0 * np.pi), 1.0)
+    return z, t
+
+
+def solve_normal_equations(gram: np.ndarray, rhs: np.ndarray) -> np.ndarray:
+    """c from gram c = rhs (Hermitian positive definite; Cholesky, LU if that fails)."""
+    try:
+        return scipy.linalg.cho_solve(scipy.linalg.cho_factor(gram), rhs)
+    except np.linalg.LinAlgError:
+        return np.linalg.solve(gram, rhs)
+
+
+@dataclasses.dataclass
+class Solution:
+    t: np.ndarray
+    c: np.ndarray
+    z: np.ndarray
+    S: np.ndarray
+    sigma: np.ndarray
+    U: np.ndarray
+    V: np.ndarray
+
+
+def solve(f: torch.Tensor, d: int, n: int, m: int, mu: np.ndarray, prec: str = "fp64",
+          start_blocks=None) -> Solution:
+    """Algorithm 1 on one GPU plus the host: T (GPU) -> reduced SVD (host) -> S_l (GPU)
+    -> nodes (host) -> Vandermonde products (GPU) -> coefficients (host)."""
+    dev = f.device
+    T = api.build_T(f, d, n, 0).cpu().numpy()
+    U, s, V, _ = reduced_svd(T, m, start_blocks)
+    del T
+    Ud = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
+    sd = torch.from_numpy(np.ascontiguousarray(s)).to(dev)
+    S = api.build_S(f, d, n, Ud, sd, Vd, prec=prec).cpu().numpy()
+    z, t = nodes(S, mu)
+    gram, rhs = api.coeffs(torch.from_numpy(np.ascontiguousarray(z)).to(dev), f, d, n)
+    c = solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy())
+    return Solution(t=t, c=c, z=z, S=S, sigma=s, U=U, V=V)

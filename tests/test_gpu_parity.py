@@ -1,0 +1,263 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on seeded inputs.
+
+Tolerances: T and the index maps are exact copies (bitwise); samples within
+1e-13 * sum|c_j|; Gram/rhs within 1e-12 relative; S_l normwise relative error
+max_l ||S_l - S_l^oracle||_F / ||S_l^oracle||_F <= 1e-12 on the FP64 path and
+<= 1e-5 on the FP32 path.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import prony_oracle as O
+from paper_2012_11430_amd import api, host
+from workload import config_instances, random_orthonormal
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@functools.lru_cache(maxsize=None)
+def _problem(name, level_index=0):
+    """Oracle grid and reduced SVD factors of the first instance of a workload."""
+    inst = config_instances(name, count=1)[0]
+    level = inst.noise_levels[level_index]
+    noise = inst.noise(level) if level > 0 else None
+    grid = O.samples(inst.t, inst.c, inst.n, abs_noise=noise)
+    T = O.toeplitz(grid, inst.d, inst.n, 0)
+    if inst.N <= 1024:
+        U, s, V = O.reduced_svd(T, inst.m)
+    else:
+        rng = np.random.Generator(np.random.PCG64(7))
+        U, s, V, _, _ = O.block_power_svd(T, random_orthonormal(rng, inst.N, 2 * inst.m),
+                                          random_orthonormal(rng, inst.N, 2 * inst.m),
+                                          tol=inst.N * O.EPS64, rank=inst.m)
+    del T
+    return inst, grid, U, s, V
+
+
+# ------------------------------------------------------------------ samples
+
+
+@pytest.mark.parametrize("name", ["c0", "c1", "c2"])
+def test_samples_match_oracle(name):
+    inst = config_instances(name, count=1)[0]
+    _say(f"samples {name}")
+    noise = inst.noise() if inst.noise_levels[0] > 0 else None
+    ref = O.samples(inst.t, inst.c, inst.n, abs_noise=noise)
+    got = api.samples(_dev(inst.t), _dev(inst.c), inst.n,
+                      noise=_dev(noise) if noise is not None else None).cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.sum(np.abs(inst.c))
+
+
+@pytest.mark.parametrize("d,n,m", [(1, 1, 1), (1, 40, 7), (3, 2, 3), (2, 5, 600)])
+def test_samples_small_and_many_terms(d, n, m):
+    rng = np.random.Generator(np.random.PCG64(d * 100 + n + m))
+    t = rng.random((m, d))
+    c = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    ref = O.samples(t, c, n)
+    got = api.samples(_dev(t), _dev(c), n).cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.sum(np.abs(c))
+
+
+# ------------------------------------------------------------------ T, T_l
+
+
+@pytest.mark.parametrize("d,n", [(1, 1), (1, 37), (2, 3), (2, 15), (3, 2), (3, 5)])
+def test_build_T_is_the_exact_gather(d, n):
+    rng = np.random.Generator(np.random.PCG64(d + 10 * n))
+    G = (2 * n + 2) ** d
+    grid = rng.standard_normal(G) + 1j * rng.standard_normal(G)
+    fd = _dev(grid)
+    for which in range(d + 1):
+        got = api.build_T(fd, d, n, which).cpu().numpy()
+        assert np.array_equal(got, O.toeplitz(grid, d, n, which)), (d, n, which)
+
+
+def test_build_T_full_size_c1():
+    inst, grid, *_ = _problem("c1")
+    _say("build_T c1 full size")
+    fd = _dev(grid)
+    for which in (0, 2):
+        got = api.build_T(fd, inst.d, inst.n, which).cpu().numpy()
+        assert np.array_equal(got, O.toeplitz(grid, inst.d, inst.n, which))
+
+
+def test_build_T_leading_dimension():
+    d, n = 2, 4
+    N = (n + 1) ** d
+    rng = np.random.Generator(np.random.PCG64(3))
+    grid = rng.standard_normal((2 * n + 2) ** d) + 1j * rng.standard_normal((2 * n + 2) ** d)
+    big = torch.full((N, N + 7), 5.0 + 5.0j, dtype=torch.complex128, device=DEV)
+    api.build_T(_dev(grid), d, n, 1, out=big[:, :N])
+    host_big = big.cpu().numpy()
+    assert np.array_equal(host_big[:, :N], O.toeplitz(grid, d, n, 1))
+    assert np.all(host_big[:, N:] == 5.0 + 5.0j)
+
+
+# ------------------------------------------------------------------ S_l
+
+
+def _check_S(inst, grid, U, s, V, prec, with_s0):
+    ref = O.pencil_matrices(grid, inst.d, inst.n, U, s, V, with_s0=with_s0)
+    got = api.build_S(_dev(grid), inst.d, inst.n, _dev(U), _dev(s), _dev(V), prec=prec,
+                      with_s0=with_s0).cpu().numpy()
+    errs = [_rel(got[l], ref[l]) for l in range(ref.shape[0])]
+    assert max(errs) <= TOL[prec], (prec, errs)
+    return got, errs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("with_s0", [False, True])
+def test_build_S_c0(prec, with_s0):
+    inst, grid, U, s, V = _problem("c0")
+    got, _ = _check_S(inst, grid, U, s, V, prec, with_s0)
+    if with_s0:   # exact SVD: S_0 = I
+        assert np.max(np.abs(got[0] - np.eye(inst.m))) < 10 * TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_build_S_c1_full_size(prec):
+    _say(f"build_S c1 {prec}")
+    inst, grid, U, s, V = _problem("c1")
+    _check_S(inst, grid, U, s, V, prec, with_s0=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_build_S_c2_full_size(prec):
+    _say(f"build_S c2 {prec}")
+    inst, grid, U, s, V = _problem("c2", level_index=4)
+    _check_S(inst, grid, U, s, V, prec, with_s0=False)
+
+
+CASES = [(1, 1, 1), (1, 63, 5), (1, 200, 32), (2, 1, 2), (2, 4, 16), (2, 9, 17), (2, 20, 32),
+         (3, 1, 3), (3, 3, 8), (3, 6, 31)]
+
+
+@pytest.mark.parametrize("d,n,m", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_build_S_ragged_random(d, n, m, prec):
+    # arbitrary grids and factors: several row tiles and h' chunks with ragged tails
+    rng = np.random.Generator(np.random.PCG64(1000 * d + 10 * n + m))
+    N = (n + 1) ** d
+    G = (2 * n + 2) ** d
+    grid = rng.standard_normal(G) + 1j * rng.standard_normal(G)
+    U = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+    V = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+    s = rng.uniform(0.5, 2.0, m)
+
+    class Inst:
+        pass
+    inst = Inst()
+    inst.d, inst.n, inst.m = d, n, m
+    _check_S(inst, grid, U, s, V, prec, with_s0=(m % 2 == 1))
+
+
+def test_build_S_strided_factors():
+    inst, grid, U, s, V = _problem("c0")
+    ref = O.pencil_matrices(grid, inst.d, inst.n, U, s, V)
+    Ut = _dev(U.T.copy()).T          # column-major storage: row stride 1, column stride N
+    Vt = _dev(V.T.copy()).T
+    assert Ut.stride() == (1, inst.N)
+    got = api.build_S(_dev(grid), inst.d, inst.n, Ut, _dev(s), Vt, prec="fp64").cpu().numpy()
+    assert max(_rel(got[l], ref[l]) for l in range(inst.d)) <= 1e-12
+
+
+def test_build_S_is_deterministic():
+    inst, grid, U, s, V = _problem("c1")
+    args = (_dev(grid), inst.d, inst.n, _dev(U), _dev(s), _dev(V))
+    a = api.build_S(*args, prec="fp32")
+    b = api.build_S(*args, prec="fp32")
+    assert torch.equal(a, b)
+
+
+def test_build_S_eigenvalues_are_the_nodes_c0():
+    inst, grid, U, s, V = _problem("c0")
+    S = api.build_S(_dev(grid), inst.d, inst.n, _dev(U), _dev(s), _dev(V), prec="fp64").cpu().numpy()
+    for ell in range(inst.d):
+        ev = np.linalg.eigvals(S[ell])
+        z = np.exp(-2j * np.pi * inst.t[:, ell])
+        assert np.max(np.min(np.abs(ev[:, None] - z[None, :]), axis=1)) < 1e-11
+
+
+# ------------------------------------------------------------------ Vandermonde products
+
+
+@pytest.mark.parametrize("name", ["c0", "c1", "c2"])
+def test_coeffs_match_oracle(name):
+    inst, grid, *_ = _problem(name)
+    _say(f"coeffs {name}")
+    rng = np.random.Generator(np.random.PCG64(11))
+    z = np.exp(-2j * np.pi * inst.t) * (1 + 1e-4 * rng.standard_normal(inst.t.shape))
+    gram_ref, rhs_ref = O.coefficient_products(z, grid, inst.d, inst.n)
+    gram, rhs, AT = api.coeffs(_dev(z), _dev(grid), inst.d, inst.n, want_AT=True)
+    assert _rel(gram.cpu().numpy(), gram_ref) <= 1e-12
+    assert _rel(rhs.cpu().numpy(), rhs_ref) <= 1e-12
+    AT_ref = O.vandermonde_transpose(z, inst.d, inst.n)
+    assert np.max(np.abs(AT.cpu().numpy() - AT_ref) / np.abs(AT_ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("d,n,m", [(1, 1, 1), (1, 100, 64), (2, 8, 3), (3, 4, 33)])
+def test_coeffs_ragged(d, n, m):
+    rng = np.random.Generator(np.random.PCG64(d + n + m))
+    z = np.exp(2j * np.pi * rng.random((m, d))) * (1 + 1e-3 * rng.standard_normal((m, d)))
+    G = (2 * n + 2) ** d
+    grid = rng.standard_normal(G) + 1j * rng.standard_normal(G)
+    gram_ref, rhs_ref = O.coefficient_products(z, grid, d, n)
+    gram, rhs = api.coeffs(_dev(z), _dev(grid), d, n)
+    assert _rel(gram.cpu().numpy(), gram_ref) <= 1e-12
+    assert _rel(rhs.cpu().numpy(), rhs_ref) <= 1e-12
+
+
+# ------------------------------------------------------------------ Algorithm 1 end to end
+
+
+def test_end_to_end_c0_exact_recovery():
+    inst = config_instances("c0")[0]
+    f = api.samples(_dev(inst.t), _dev(inst.c), inst.n)
+    for prec in ("fp64", "fp32"):
+        sol = host.solve(f, inst.d, inst.n, inst.m, inst.mu, prec=prec)
+        dt, dc = O.recovery_errors(dict(t=sol.t, c=sol.c), inst.t, inst.c)
+        if prec == "fp64":
+            assert dt < 1e-12 and dc < 1e-10, (dt, dc)
+        else:
+            assert dt < 1e-6 and dc < 1e-5, (dt, dc)
+
+
+def test_end_to_end_c1_against_oracle_pipeline():
+    inst, grid, U, s, V = _problem("c1")
+    _say("end to end c1")
+    Sref = O.pencil_matrices(grid, inst.d, inst.n, U, s, V)
+    zr, tr, _ = O.nodes_from_pencil(Sref, inst.mu)
+    cr, _ = O.least_squares_coefficients(zr, grid, inst.d, inst.n)
+    dt_ref, dc_ref = O.recovery_errors(dict(t=tr, c=cr), inst.t, inst.c)
+    fd = _dev(grid)
+    for prec in ("fp64", "fp32"):
+        S = api.build_S(fd, inst.d, inst.n, _dev(U), _dev(s), _dev(V), prec=prec).cpu().numpy()
+        z, t = host.nodes(S, inst.mu)
+        gram, rhs = api.coeffs(_dev(z), fd, inst.d, inst.n)
+        c = host.solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy())
+        dt, dc = O.recovery_errors(dict(t=t, c=c), inst.t, inst.c)
+        _say(f"  c1 {prec}: dt {dt:.3e} (oracle {dt_ref:.3e})  dc {dc:.3e} (oracle {dc_ref:.3e})")
+        if prec == "fp64":
+            assert dt < 10 * dt_ref + 1e-12 and dc < 10 * dc_ref + 1e-10
+        else:
+            assert dt < max(10 * dt_ref, 1e-6) and dc < max(10 * dc_ref, 1e-5)
