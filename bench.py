@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the GPU hot path of the matrix-pencil Prony method on one MI355X.
+
+One step is one pass of the GPU steps of Algorithm 1 over the resident inputs
+of one problem (default workload c1: d=2, n=63, N=4096, m=20, noise 1e-6):
+  samples of the exponential sum on the grid -> T (materialised for the host
+  SVD) -> S_1..S_d = U^* T_l V Sigma^{-1} -> Gram matrix and right-hand side
+  of the coefficient least-squares problem.
+The host steps (SVD, eigendecomposition, m x m solve) run once, untimed, to
+produce the inputs U, Sigma, V and z of the timed GPU steps.
+
+value = S-build flops F_S = d (8 N^2 m + 8 N m^2 + 2 m^2) divided by the time
+of one whole step, in TFLOP/s. The JSON line also carries the S-build alone in
+FP32 and FP64, the roofline of the dominant kernel (measured with HIP events
+around its launches in the timed region) and the CPU oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "S_ℓ-build complex TFLOP/s + instances/s, FP32-MFMA vs FP64, at stated rel err"
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X dense MFMA peaks
+DOMINANT = "pencil_tiles"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pencil_tiles_c1_traffic.json")
+
+
+def s_flops(d, N, m):
+    return d * (8.0 * N * N * m + 8.0 * N * m * m + 2.0 * m * m)
+
+
+def tile_flops(d, N, m):
+    # algorithmic work of one pencil_tiles launch: T_l V and the U^* reduction
+    return d * (8.0 * N * N * m + 8.0 * N * m * m)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for name in ("pencil.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2012_11430_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2"])
+    ap.add_argument("--cpu-sample-steps", type=int, default=3,
+                    help="oracle steps timed for the CPU baseline (0 skips it)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB (a reference dispatch "
+                         "of known traffic for hardware-counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the hot path is a single-GPU kernel pipeline "
+              "(multi-GPU sharding is described in the design notes, not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2012_11430_amd import _lib, api, host
+    from workload import config_instances, random_orthonormal
+
+    _lib.load()   # fails loudly when the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    inst = config_instances(args.workload, count=1)[0]
+    d, n, m, N = inst.d, inst.n, inst.m, inst.N
+    level = inst.noise_levels[0]
+
+    def to_dev(x):
+        return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+    # ---------------- resident inputs (untimed; host steps run once)
+    t_d, c_d = to_dev(inst.t), to_dev(inst.c)
+    noise_d = to_dev(inst.noise(level)) if level > 0 else None
+    f = api.samples(t_d, c_d, n, noise=noise_d)
+    Tbuf = torch.empty((N, N), dtype=torch.complex128, device=dev)
+    api.build_T(f, d, n, 0, out=Tbuf)
+    T = Tbuf.cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(12345))
+    blocks = (random_orthonormal(rng, N, 2 * m), random_orthonormal(rng, N, 2 * m))
+    U, sig, V, _ = host.reduced_svd(T, m, start_blocks=blocks)
+    del T
+    Ud, sd, Vd = to_dev(U), to_dev(sig), to_dev(V)
+    Sbuf = torch.empty((d, m, m), dtype=torch.complex128, device=dev)
+    api.build_S(f, d, n, Ud, sd, Vd, prec="fp64", out=Sbuf)
+    z, _ = host.nodes(Sbuf.cpu().numpy(), inst.mu)
+    z_d = to_dev(z)
+
+    def step(prec):
+        api.samples(t_d, c_d, n, noise=noise_d, out=f)
+        api.build_T(f, d, n, 0, out=Tbuf)
+        api.build_S(f, d, n, Ud, sd, Vd, prec=prec, out=Sbuf)
+        api.coeffs(z_d, f, d, n)
+
+    # ---------------- timed region: K whole steps
+    for _ in range(args.warmup):
+        step(args.prec)
+    torch.cuda.synchronize()
+    api.profile_enable(dev, DOMINANT)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step(args.prec)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    launches, tiles_ms = api.profile_read(dev)
+    api.profile_enable(dev, None)
+    tiles_avg_ms = tiles_ms / max(1, launches)
+
+    # ---------------- the S-build alone, both precisions (same inputs)
+    sbuild = {}
+    S_out = {}
+    for prec in ("fp32", "fp64"):
+        for _ in range(args.warmup):
+            api.build_S(f, d, n, Ud, sd, Vd, prec=prec, out=Sbuf)
+        api.profile_enable(dev, DOMINANT)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            api.build_S(f, d, n, Ud, sd, Vd, prec=prec, out=Sbuf)
+        e1.record()
+        torch.cuda.synchronize()
+        nl, tot = api.profile_read(dev)
+        api.profile_enable(dev, None)
+        ms = e0.elapsed_time(e1) / args.steps
+        sbuild[prec] = {"ms": round(ms, 5), "tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 3),
+                        "tiles_ms": round(tot / max(1, nl), 5)}
+        S_out[prec] = Sbuf.cpu().numpy().copy()
+
+    F = s_flops(d, N, m)
+    value = F / (ms_step * 1e-3) / 1e12
+    achieved = tile_flops(d, N, m) / (tiles_avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.prec]
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        if rec.get("source_digest") == source_digest() and rec.get("workload") == args.workload \
+                and rec.get("prec") == args.prec:
+            traffic = rec.get("hbm_bytes_per_launch")
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: d={d}, n={n}, N={N}, m={m}, additive noise {level:g}*max|c|",
+            "step": "samples -> T (N x N, for the host SVD) -> S_1..S_d -> Gram/rhs",
+            "s_build_precision": args.prec,
+            "seed": list(inst.seed),
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": DOMINANT,
+            "achieved": round(achieved, 3),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": traffic,
+            "avg_launch_ms": round(tiles_avg_ms, 5),
+            "launches_timed": launches,
+            "flops_per_launch": tile_flops(d, N, m),
+        },
+        "s_build": sbuild,
+        "wall_s_timed": round(wall, 4),
+    }
+
+    if args.cpu_sample_steps > 0:
+        result["cpu_baseline"] = cpu_baseline(inst, U, sig, V, z, S_out, args.cpu_sample_steps,
+                                              f.cpu().numpy())
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, grid_gpu):
+    """The CPU oracle timed on `steps` whole steps of the same workload; also the
+    relative error of the GPU S-build against the oracle on the same inputs."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import prony_oracle as O
+
+    d, n = inst.d, inst.n
+    level = inst.noise_levels[0]
+    noise = inst.noise(level) if level > 0 else None
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        grid = O.samples(inst.t, inst.c, n, abs_noise=noise)
+        O.toeplitz(grid, d, n, 0)
+        S = O.pencil_matrices(grid, d, n, U, sig, V)
+        O.coefficient_products(z, grid, d, n)
+    el = (time.perf_counter() - t0) / steps
+    F = s_flops(d, inst.N, inst.m)
+    rel = {p: max(float(np.linalg.norm(S_gpu[p][l] - S[l]) / np.linalg.norm(S[l])) for l in range(d))
+           for p in S_gpu}
+    return {
+        "value": round(F / el / 1e12, 6),
+        "unit": "TFLOP/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"{steps} whole oracle steps (samples, T, S_1..S_d, Gram/rhs) of the same workload, "
+                  f"{el:.3f} s per step",
+        "s_rel_err_vs_oracle": {p: float(f"{v:.3e}") for p, v in rel.items()},
+        "samples_max_abs_err": float(f"{np.max(np.abs(grid_gpu - grid)):.3e}"),
+    }
+
+
+if __name__ == "__main__":
+    main()

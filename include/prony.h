@@ -89,6 +89,17 @@ const char* prony_last_error(prony_handle_t handle);
    calls allocate nothing (needed before capturing a stream into a HIP graph). */
 prony_status_t prony_reserve(prony_handle_t handle, int d_max, int n_max, int m_max);
 
+/* Profiling aid. With a non-NULL `kernel` name, every later launch of that kernel
+   by the handle is bracketed by a pair of HIP events recorded on the handle's
+   stream; NULL stops recording. Each call discards earlier records.
+   Kernel names: "samples", "toeplitz", "pencil_pack", "pencil_tiles",
+   "coeffs_tiles", "coeffs_reduce". */
+prony_status_t prony_profile_enable(prony_handle_t handle, const char* kernel);
+
+/* Synchronise the stream and report the recorded launches of the profiled kernel:
+   their count and the sum of their event-to-event times in milliseconds. */
+prony_status_t prony_profile_read(prony_handle_t handle, int* launches, double* total_ms);
+
 /* ---- Algorithm 1, GPU steps -------------------------------------------------- */
 
 /* Samples of the exponential sum (Sec. 1, eq. exp_sum), with the additive noise

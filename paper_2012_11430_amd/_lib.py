@@ -42,6 +42,8 @@ SIGNATURES = {
     "prony_build_S": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _c_i64, _c_i64, _ptr, _ptr, _c_i64, _c_i64,
                        _c_int, ctypes.c_uint, _ptr], _c_int),
     "prony_coeffs": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _ptr, _ptr, _ptr], _c_int),
+    "prony_profile_enable": ([_ptr, ctypes.c_char_p], _c_int),
+    "prony_profile_read": ([_ptr, ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_double)], _c_int),
 }
 
 

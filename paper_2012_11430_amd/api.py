@@ -166,3 +166,16 @@ def reserve(device: torch.device, d_max: int, n_max: int, m_max: int) -> None:
 
 def synchronize(device: torch.device) -> None:
     _call("prony_synchronize", device)
+
+
+def profile_enable(device: torch.device, kernel: str | None) -> None:
+    """Bracket every later launch of `kernel` with HIP events (None stops; resets records)."""
+    _call("prony_profile_enable", device, kernel.encode() if kernel else None)
+
+
+def profile_read(device: torch.device):
+    """(launches, total milliseconds) of the profiled kernel since profile_enable."""
+    launches = ctypes.c_int()
+    total = ctypes.c_double()
+    _call("prony_profile_read", device, ctypes.byref(launches), ctypes.byref(total))
+    return launches.value, total.value

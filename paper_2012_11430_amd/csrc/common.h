@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "prony.h"
 
@@ -16,6 +17,10 @@ struct prony_handle_s {
     int num_cus = 256;
     size_t lds_per_block = 65536;
     std::string err;
+    // profiling: events around launches of one named kernel
+    std::string prof_kernel;
+    std::vector<hipEvent_t> prof_events;   // pool, pairs (start, stop)
+    size_t prof_used = 0;                  // events in use (2 per launch)
 };
 
 namespace prony {
@@ -39,6 +44,16 @@ struct DeviceGuard {
 // Grow the workspace to at least `bytes`. Returns PRONY_ECAPTURE when growth is
 // needed while the handle's stream is being captured.
 prony_status_t ensure_workspace(prony_handle_t h, size_t bytes);
+
+// Brackets one kernel launch with profiling events when the handle profiles `name`.
+class ProfileScope {
+  public:
+    ProfileScope(prony_handle_t h, const char* name);
+    ~ProfileScope();
+  private:
+    prony_handle_t h_;
+    hipEvent_t stop_ = nullptr;
+};
 
 // Launch-error check after a kernel launch.
 prony_status_t check_launch(prony_handle_t h, const char* what);

@@ -56,9 +56,56 @@ prony_status_t ensure_workspace(prony_handle_t h, size_t bytes) {
     return PRONY_OK;
 }
 
+static hipEvent_t next_event(prony_handle_t h) {
+    if (h->prof_used == h->prof_events.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->prof_events.push_back(e);
+    }
+    return h->prof_events[h->prof_used++];
+}
+
+ProfileScope::ProfileScope(prony_handle_t h, const char* name) : h_(h) {
+    if (h->prof_kernel.empty() || h->prof_kernel != name) return;
+    hipEvent_t start = next_event(h);
+    hipEvent_t stop = next_event(h);
+    if (!start || !stop) return;
+    if (hipEventRecord(start, h->stream) != hipSuccess) return;
+    stop_ = stop;
+}
+
+ProfileScope::~ProfileScope() {
+    if (stop_) (void)hipEventRecord(stop_, h_->stream);
+}
+
 }  // namespace prony
 
 using namespace prony;
+
+extern "C" prony_status_t prony_profile_enable(prony_handle_t h, const char* kernel) {
+    if (!h) return PRONY_EINVAL;
+    h->prof_kernel = kernel ? kernel : "";
+    h->prof_used = 0;
+    return PRONY_OK;
+}
+
+extern "C" prony_status_t prony_profile_read(prony_handle_t h, int* launches, double* total_ms) {
+    if (!h || !launches || !total_ms) return PRONY_EINVAL;
+    *launches = 0;
+    *total_ms = 0.0;
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    for (size_t i = 0; i + 1 < h->prof_used; i += 2) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, h->prof_events[i], h->prof_events[i + 1]);
+        if (e != hipSuccess) return hip_fail(h, e, "hipEventElapsedTime");
+        *total_ms += ms;
+        *launches += 1;
+    }
+    return PRONY_OK;
+}
 
 extern "C" prony_status_t prony_create(prony_handle_t* handle, int device) {
     if (!handle) return PRONY_EINVAL;
@@ -98,6 +145,7 @@ extern "C" prony_status_t prony_destroy(prony_handle_t h) {
         if (hipStreamSynchronize(h->stream) != hipSuccess) st = PRONY_EHIP;
         if (hipFree(h->ws) != hipSuccess) st = PRONY_EHIP;
     }
+    for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
     delete h;
     return st;
 }

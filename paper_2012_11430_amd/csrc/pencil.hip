@@ -17,10 +17,12 @@
 //                 is generated from a flat window of the sample grid staged in
 //                 LDS, multiplied on MFMA against the packed V_l, then the
 //                 U^* reduction over the 64 rows runs on MFMA as well and the
-//                 m x (d m) partial is stored;
-//   pencil_reduce sums the partials of all workgroups in FP64 in a fixed order
-//                 and applies Sigma^{-1} in FP64.
+//                 m x (d m) partial is stored.
+//                 The last workgroups to finish reduce the partials of all
+//                 workgroups in FP64 in a fixed order and apply Sigma^{-1} in
+//                 FP64 (no separate reduction launch).
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "common.h"
@@ -81,9 +83,11 @@ struct PencilPlan {
     int nwg;        // rt * sk workgroups
     int win_cap;    // window capacity (complex elements)
     int c0;         // grid offset of the origin shift
+    int gs;         // workgroups per first-level reduction group
+    int ngroups;    // first-level groups
     size_t lds_bytes;
     // workspace offsets (bytes)
-    size_t off_v, off_u, off_g, off_p, ws_bytes;
+    size_t off_v, off_u, off_g, off_p, off_gp, off_c, ws_bytes;
 };
 
 // Grid offset of the extended index h' (row-major over {-1..n}^d).
@@ -103,13 +107,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* __restrict__ U, int64_t u_rs,
                                                    int64_t u_cs, const double2* __restrict__ V, int64_t v_rs,
                                                    int64_t v_cs, pair_t<T>* __restrict__ vp, pair_t<T>* __restrict__ up,
-                                                   int* __restrict__ gt) {
+                                                   int* __restrict__ gt, unsigned* __restrict__ counters) {
     using T2 = pair_t<T>;
-    const int64_t nv = (int64_t)P.sk * P.kc * P.nrp;
+    const int64_t kbp = (int64_t)P.sk * P.kc + 4;     // K rows incl. the prefetch pad
+    const int64_t nv = kbp * P.nrp;
     const int mup = P.mbi * 16;
     const int64_t nu = (int64_t)P.rt * kRowsPerTile * mup;
-    const int64_t ng = (int64_t)P.sk * P.kc;
-    const int64_t total = nv + nu + ng;
+    const int64_t ng = kbp;
+    const int64_t total = nv + nu + ng + P.ngroups + 1;
     const int E = P.n + 2, Pn = P.n + 1;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -151,26 +156,36 @@ __global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* 
                 ui = u.y;
             }
             up[r] = T2{(T)ur, (T)ui};
-        } else {
+        } else if (i < nv + nu + ng) {
             const int hx = (int)(i - nv - nu);
             gt[hx] = ext_offset(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
+        } else {
+            counters[i - nv - nu - ng] = 0u;
         }
     }
 }
 
-template <typename T, int NBMAX>
+// Padding of the packed second factor and of the h' offsets: the K loop
+// prefetches one K step (4 rows) past the end of a chunk.
+constexpr int kPrefetchRows = 4;
+
+template <typename T, int NB>
 __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const double2* __restrict__ grid,
                                                          const pair_t<T>* __restrict__ vp,
                                                          const pair_t<T>* __restrict__ up,
-                                                         const int* __restrict__ gtab, pair_t<T>* __restrict__ part) {
+                                                         const int* __restrict__ gtab, pair_t<T>* __restrict__ part,
+                                                         double2* __restrict__ gpart, unsigned* __restrict__ counters,
+                                                         const double* __restrict__ sigma, double2* __restrict__ S) {
     using T2 = pair_t<T>;
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
     extern __shared__ __align__(16) unsigned char smem[];
+    // Phase 1 (K loop): grid window + h' offsets. Phase 2 (U^* reduction): the
+    // same bytes hold the per-workgroup sum of the wave results.
     T2* win = reinterpret_cast<T2*>(smem);
     int* gt = reinterpret_cast<int*>(smem + align_up(sizeof(T2) * (size_t)P.win_cap, 16));
-    T* esum = reinterpret_cast<T*>(smem + align_up(sizeof(T2) * (size_t)P.win_cap, 16) +
-                                   align_up(sizeof(int) * (size_t)P.kc, 16));
+    T* esum = reinterpret_cast<T*>(smem);
+    __shared__ int s_last;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -195,36 +210,40 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const dou
         const double2 v = grid[lo + w];
         win[w] = T2{(T)v.x, (T)v.y};
     }
-    for (int i = tid; i < P.kc; i += kThreads) gt[i] = gtab[h_first + i];
-    const int esz = P.mbi * 16 * P.nrp;
-    for (int i = tid; i < esz; i += kThreads) esum[i] = T(0);
+    for (int i = tid; i < P.kc + kPrefetchRows; i += kThreads) gt[i] = gtab[min(h_first + i, h_last)];
     __syncthreads();
 
     const int krow = min(k_first + wave * kRowsPerWave + col, P.N - 1);
     const int gk = grid_offset_of_index(krow, P.d, P.n) + P.c0 - lo;
 
-    acc_t acc[NBMAX];
+    acc_t acc[NB];
 #pragma unroll
-    for (int cb = 0; cb < NBMAX; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
 
-    const int nb = P.nb;
+    // K loop over this chunk, 4 h' per step (lane group g takes h' = 4 ks + g);
+    // the operands of step ks+1 are loaded while the MFMAs of step ks run.
     const T2* vrow = vp + (size_t)(h_first + g) * P.nrp + col;
     const size_t kstride = (size_t)4 * P.nrp;
     const int nks = P.kc >> 2;
-#pragma unroll 2
+    T2 a = win[gk - gt[g]];
+    T2 b[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) b[cb] = vrow[cb * 16];
     for (int ks = 0; ks < nks; ++ks) {
-        const T2 a = win[gk - gt[4 * ks + g]];
-        T2 b[NBMAX];
+        const T2 an = win[gk - gt[4 * (ks + 1) + g]];
+        T2 bn[NB];
+        const T2* vnext = vrow + (ks + 1) * kstride;
 #pragma unroll
-        for (int cb = 0; cb < NBMAX; ++cb)
-            if (cb < nb) b[cb] = vrow[ks * kstride + cb * 16];
+        for (int cb = 0; cb < NB; ++cb) bn[cb] = vnext[cb * 16];
 #pragma unroll
-        for (int cb = 0; cb < NBMAX; ++cb)
-            if (cb < nb) acc[cb] = M::fma(a.x, b[cb].x, acc[cb]);
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = M::fma(a.x, b[cb].x, acc[cb]);
 #pragma unroll
-        for (int cb = 0; cb < NBMAX; ++cb)
-            if (cb < nb) acc[cb] = M::fma(a.y, b[cb].y, acc[cb]);
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = M::fma(a.y, b[cb].y, acc[cb]);
+        a = an;
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) b[cb] = bn[cb];
     }
+    __syncthreads();   // the window is dead from here on; its bytes become esum
 
     // U^* reduction over this wave's 16 rows. The accumulators are the second
     // MFMA operand directly: element r of lane (g, col) is Y[row(g,r)][16cb+col].
@@ -232,32 +251,30 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const dou
     // value y' (column j^1), Re = Ur.Yr + Ui.Yi and Im = Ur.Yi - Ui.Yr.
     const int mup = P.mbi * 16;
     for (int ib = 0; ib < P.mbi; ++ib) {
-        acc_t e[NBMAX];
+        acc_t e[NB];
 #pragma unroll
-        for (int cb = 0; cb < NBMAX; ++cb) e[cb] = acc_t{0, 0, 0, 0};
+        for (int cb = 0; cb < NB; ++cb) e[cb] = acc_t{0, 0, 0, 0};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int k = k_first + wave * kRowsPerWave + M::row(g, r);
             const T2 u = up[(size_t)k * mup + ib * 16 + col];
 #pragma unroll
-            for (int cb = 0; cb < NBMAX; ++cb) {
-                if (cb < nb) {
-                    const T y = acc[cb][r];
-                    const T ys = __shfl_xor(y, 1);
-                    e[cb] = M::fma(u.x, y, e[cb]);
-                    e[cb] = M::fma(u.y, odd ? -ys : ys, e[cb]);
-                }
+            for (int cb = 0; cb < NB; ++cb) {
+                const T y = acc[cb][r];
+                const T ys = __shfl_xor(y, 1);
+                e[cb] = M::fma(u.x, y, e[cb]);
+                e[cb] = M::fma(u.y, odd ? -ys : ys, e[cb]);
             }
         }
         // Sum the four waves in a fixed order (bitwise reproducible).
         for (int w = 0; w < kWaves; ++w) {
             if (wave == w) {
 #pragma unroll
-                for (int cb = 0; cb < NBMAX; ++cb) {
-                    if (cb < nb) {
+                for (int cb = 0; cb < NB; ++cb) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            esum[(ib * 16 + M::row(g, r)) * P.nrp + cb * 16 + col] += e[cb][r];
+                    for (int r = 0; r < 4; ++r) {
+                        T* dst = &esum[(ib * 16 + M::row(g, r)) * P.nrp + cb * 16 + col];
+                        *dst = (w == 0) ? e[cb][r] : *dst + e[cb][r];
                     }
                 }
             }
@@ -265,54 +282,67 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const dou
         }
     }
 
-    T2* out = part + (size_t)(sk_i * P.rt + rt_i) * P.m * P.C;
-    for (int o = tid; o < P.m * P.C; o += kThreads) {
+    const int tot = P.m * P.C;
+    T2* out = part + (size_t)L * tot;
+    for (int o = tid; o < tot; o += kThreads) {
         const int i = o / P.C, c = o - (o / P.C) * P.C;
         out[o] = T2{esum[i * P.nrp + 2 * c], esum[i * P.nrp + 2 * c + 1]};
     }
-}
 
-// S[l][i][q] = (sum over workgroup partials) / sigma_q, in FP64, fixed order.
-template <typename T>
-__global__ __launch_bounds__(256) void pencil_reduce(int m, int C, int nwg, const pair_t<T>* __restrict__ part,
-                                                     const double* __restrict__ sigma, double2* __restrict__ S) {
-    constexpr int kOut = 32, kGroups = 8;
-    __shared__ double2 red[kGroups][kOut];
-    const int tid = threadIdx.x;
-    const int o = blockIdx.x * kOut + (tid % kOut);
-    const int grp = tid / kOut;
-    const int tot = m * C;
-    double re = 0.0, im = 0.0;
-    if (o < tot) {
-        for (int s = grp; s < nwg; s += kGroups) {
-            const pair_t<T> v = part[(size_t)s * tot + o];
+    // Deterministic two-level reduction of the workgroup partials: the last
+    // workgroup to finish in a group of P.gs sums that group's partials in slot
+    // order; the last group to finish sums the group results in order and
+    // applies Sigma^{-1}. Release/acquire fences make the partials written on
+    // other XCDs visible; counters return to zero for the next launch.
+    __threadfence();
+    __syncthreads();
+    const int grp = L / P.gs;
+    const int s_begin = grp * P.gs;
+    const int s_end = min(s_begin + P.gs, P.nwg);
+    if (tid == 0) s_last = atomicAdd(&counters[grp], 1u) == (unsigned)(s_end - s_begin - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int o = tid; o < tot; o += kThreads) {
+        double re = 0.0, im = 0.0;
+        for (int s2 = s_begin; s2 < s_end; ++s2) {
+            const T2 v = part[(size_t)s2 * tot + o];
             re += (double)v.x;
             im += (double)v.y;
         }
+        gpart[(size_t)grp * tot + o] = make_double2(re, im);
     }
-    red[grp][tid % kOut] = make_double2(re, im);
+    if (tid == 0) counters[grp] = 0u;
+    __threadfence();
     __syncthreads();
-    if (grp == 0 && o < tot) {
-        re = 0.0;
-        im = 0.0;
-        for (int k = 0; k < kGroups; ++k) {
-            re += red[k][tid].x;
-            im += red[k][tid].y;
+    if (tid == 0) s_last = atomicAdd(&counters[P.ngroups], 1u) == (unsigned)(P.ngroups - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int o = tid; o < tot; o += kThreads) {
+        double re = 0.0, im = 0.0;
+        for (int q2 = 0; q2 < P.ngroups; ++q2) {
+            const double2 v = gpart[(size_t)q2 * tot + o];
+            re += v.x;
+            im += v.y;
         }
-        const int i = o / C, c = o - (o / C) * C;
-        const int li = c / m, q = c - li * m;
-        const double s = sigma[q];
-        S[((size_t)li * m + i) * m + q] = make_double2(re / s, im / s);
+        const int i = o / P.C, c = o - (o / P.C) * P.C;
+        const int li = c / P.m, q = c - li * P.m;
+        const double sq = sigma[q];
+        S[((size_t)li * P.m + i) * P.m + q] = make_double2(re / sq, im / sq);
     }
+    if (tid == 0) counters[P.ngroups] = 0u;
 }
 
 size_t lds_bytes_for(int win, int kc, int mbi, int nrp, size_t tsize) {
-    return align_up(2 * tsize * (size_t)win, 16) + align_up(4 * (size_t)kc, 16) + tsize * (size_t)mbi * 16 * nrp;
+    const size_t loop = align_up(2 * tsize * (size_t)win, 16) + 4 * ((size_t)kc + kPrefetchRows);
+    const size_t epi = tsize * (size_t)mbi * 16 * nrp;
+    return align_up(std::max(loop, epi), 16);
 }
 
-// Largest G-span of `len` consecutive indices of a row-major box of side `side`
-// (per-axis grid stride 2n+2), over all aligned starts used by the tiling.
-int max_span(int count, int len, int side, int d, int n, bool ext) {
+// Largest G-span of the aligned runs of `len` consecutive indices (row tiles of
+// I_n, or chunks of the extended set {-1..n}^d).
+int max_span(int count, int len, int d, int n, bool ext) {
     int best = 0;
     for (int s = 0; s < count; s += len) {
         const int e = std::min(s + len, count) - 1;
@@ -320,7 +350,6 @@ int max_span(int count, int len, int side, int d, int n, bool ext) {
         const int b = ext ? ext_offset(e, d, n) : grid_offset_of_index(e, d, n);
         best = std::max(best, b - a);
     }
-    (void)side;
     return best;
 }
 
@@ -340,20 +369,19 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.rt = (P.N + kRowsPerTile - 1) / kRowsPerTile;
     P.c0 = grid_center(d, n);
 
-    const size_t budget = std::min<size_t>(h->lds_per_block, 96 * 1024);
+    const size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
     const int target = 4 * h->num_cus;
-    int sk_target = std::max(1, target / P.rt);
+    const int sk_target = std::max(1, target / P.rt);
     int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), 16);
-    kc = std::max(kc, std::min(64, (int)align_up((size_t)P.kb, 16)));
-    const int rowspan = max_span(P.N, kRowsPerTile, n + 1, d, n, false);
+    kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, 16)));
+    const int rowspan = max_span(P.N, kRowsPerTile, d, n, false);
     for (;;) {
-        const int sk = (P.kb + kc - 1) / kc;
-        const int colspan = max_span(P.kb, kc, n + 2, d, n, true);
+        const int colspan = max_span(P.kb, kc, d, n, true);
         const int win = rowspan + colspan + 1;
         const size_t lds = lds_bytes_for(win, kc, P.mbi, P.nrp, tsize);
         if (lds <= budget) {
             P.kc = kc;
-            P.sk = sk;
+            P.sk = (P.kb + kc - 1) / kc;
             P.win_cap = win;
             P.lds_bytes = lds;
             break;
@@ -362,18 +390,70 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
         kc = (int)align_up((size_t)(kc / 2), 16);
     }
     P.nwg = P.rt * P.sk;
+    P.gs = std::max(1, (int)std::ceil(std::sqrt((double)P.nwg)));
+    P.ngroups = (P.nwg + P.gs - 1) / P.gs;
     const size_t t2 = 2 * tsize;
+    const size_t tot = (size_t)P.m * P.C;
     size_t off = 0;
     P.off_v = off;
-    off = align_up(off + t2 * (size_t)P.sk * P.kc * P.nrp, 256);
+    off = align_up(off + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
     P.off_u = off;
     off = align_up(off + t2 * (size_t)P.rt * kRowsPerTile * P.mbi * 16, 256);
     P.off_g = off;
-    off = align_up(off + 4 * (size_t)P.sk * P.kc, 256);
+    off = align_up(off + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
     P.off_p = off;
-    off = align_up(off + t2 * (size_t)P.nwg * P.m * P.C, 256);
+    off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
+    P.off_gp = off;
+    off = align_up(off + sizeof(double2) * (size_t)P.ngroups * tot, 256);
+    P.off_c = off;
+    off = align_up(off + sizeof(unsigned) * ((size_t)P.ngroups + 1), 256);
     P.ws_bytes = off;
     return PRONY_OK;
+}
+
+template <typename T, int NB>
+prony_status_t launch_tiles(prony_handle_t h, const PencilPlan& P, const double2* grid, const pair_t<T>* vp,
+                            const pair_t<T>* up, const int* gt, pair_t<T>* part, double2* gpart, unsigned* counters,
+                            const double* sigma, double2* S) {
+    if (P.lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, NB>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+        if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+    }
+    ProfileScope prof(h, "pencil_tiles");
+    pencil_tiles<T, NB><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, grid, vp, up, gt, part, gpart, counters,
+                                                                      sigma, S);
+    return PRONY_OK;
+}
+
+template <typename T>
+prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const double2* grid, const pair_t<T>* vp,
+                              const pair_t<T>* up, const int* gt, pair_t<T>* part, double2* gpart,
+                              unsigned* counters, const double* sigma, double2* S) {
+#define PRONY_TILES_CASE(NBV) \
+    case NBV:                 \
+        return launch_tiles<T, NBV>(h, P, grid, vp, up, gt, part, gpart, counters, sigma, S);
+    switch (P.nb) {
+        PRONY_TILES_CASE(1)
+        PRONY_TILES_CASE(2)
+        PRONY_TILES_CASE(3)
+        PRONY_TILES_CASE(4)
+        PRONY_TILES_CASE(5)
+        PRONY_TILES_CASE(6)
+        PRONY_TILES_CASE(7)
+        PRONY_TILES_CASE(8)
+        PRONY_TILES_CASE(9)
+        PRONY_TILES_CASE(10)
+        PRONY_TILES_CASE(11)
+        PRONY_TILES_CASE(12)
+        PRONY_TILES_CASE(13)
+        PRONY_TILES_CASE(14)
+        PRONY_TILES_CASE(15)
+        PRONY_TILES_CASE(16)
+        default:
+            return fail(h, PRONY_ENOTSUP, "prony_build_S: too many columns");
+    }
+#undef PRONY_TILES_CASE
 }
 
 template <typename T>
@@ -388,40 +468,23 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, const double
     T2* up = reinterpret_cast<T2*>(ws + P.off_u);
     int* gt = reinterpret_cast<int*>(ws + P.off_g);
     T2* part = reinterpret_cast<T2*>(ws + P.off_p);
+    double2* gpart = reinterpret_cast<double2*>(ws + P.off_gp);
+    unsigned* counters = reinterpret_cast<unsigned*>(ws + P.off_c);
 
-    const int64_t total = (int64_t)P.sk * P.kc * P.nrp + (int64_t)P.rt * kRowsPerTile * P.mbi * 16 +
-                          (int64_t)P.sk * P.kc;
+    const int64_t kbp = (int64_t)P.sk * P.kc + kPrefetchRows;
+    const int64_t total = kbp * P.nrp + (int64_t)P.rt * kRowsPerTile * P.mbi * 16 + kbp + P.ngroups + 1;
     const int pack_blocks = (int)std::min<int64_t>((total + 255) / 256, 4 * (int64_t)h->num_cus);
-    pencil_pack<T><<<pack_blocks, 256, 0, h->stream>>>(P, reinterpret_cast<const double2*>(U), u_rs, u_cs,
-                                                       reinterpret_cast<const double2*>(V), v_rs, v_cs, vp, up, gt);
-    if ((st = check_launch(h, "pencil_pack")) != PRONY_OK) return st;
-
-    const double2* grid = reinterpret_cast<const double2*>(f);
-    if (P.lds_bytes > 65536) {
-        hipError_t e = hipSuccess;
-        if (P.nb <= 4)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, 4>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
-        else if (P.nb <= 8)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, 8>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
-        else
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, 16>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
-        if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+    {
+        ProfileScope prof(h, "pencil_pack");
+        pencil_pack<T><<<pack_blocks, 256, 0, h->stream>>>(P, reinterpret_cast<const double2*>(U), u_rs, u_cs,
+                                                           reinterpret_cast<const double2*>(V), v_rs, v_cs, vp, up,
+                                                           gt, counters);
     }
-    if (P.nb <= 4)
-        pencil_tiles<T, 4><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, grid, vp, up, gt, part);
-    else if (P.nb <= 8)
-        pencil_tiles<T, 8><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, grid, vp, up, gt, part);
-    else
-        pencil_tiles<T, 16><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, grid, vp, up, gt, part);
-    if ((st = check_launch(h, "pencil_tiles")) != PRONY_OK) return st;
-
-    const int outs = P.m * P.C;
-    pencil_reduce<T><<<(outs + 31) / 32, 256, 0, h->stream>>>(P.m, P.C, P.nwg, part, sigma,
-                                                              reinterpret_cast<double2*>(S));
-    return check_launch(h, "pencil_reduce");
+    if ((st = check_launch(h, "pencil_pack")) != PRONY_OK) return st;
+    st = dispatch_tiles<T>(h, P, reinterpret_cast<const double2*>(f), vp, up, gt, part, gpart, counters, sigma,
+                           reinterpret_cast<double2*>(S));
+    if (st != PRONY_OK) return st;
+    return check_launch(h, "pencil_tiles");
 }
 
 }  // namespace

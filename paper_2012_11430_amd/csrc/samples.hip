@@ -73,9 +73,11 @@ extern "C" prony_status_t prony_samples(prony_handle_t h, int d, int n, int m, c
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     const int gsize = (int)ipow(2 * n + 2, d);
     const int blocks = (gsize + kThreads - 1) / kThreads;
-    samples_kernel<<<blocks, kThreads, 0, h->stream>>>(d, n, m, gsize, t,
-                                                         reinterpret_cast<const double2*>(c),
-                                                         reinterpret_cast<const double2*>(noise),
-                                                         reinterpret_cast<double2*>(f));
+    {
+        ProfileScope prof(h, "samples");
+        samples_kernel<<<blocks, kThreads, 0, h->stream>>>(d, n, m, gsize, t, reinterpret_cast<const double2*>(c),
+                                                           reinterpret_cast<const double2*>(noise),
+                                                           reinterpret_cast<double2*>(f));
+    }
     return check_launch(h, "samples_kernel");
 }

@@ -46,7 +46,10 @@ extern "C" prony_status_t prony_build_T(prony_handle_t h, int d, int n, int whic
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     const int base = grid_center(d, n) + grid_shift(d, n, which);
     dim3 grid((unsigned)((N + kCols - 1) / kCols), (unsigned)((N + kRows - 1) / kRows));
-    toeplitz_kernel<<<grid, kCols, 0, h->stream>>>(d, n, (int)N, base, reinterpret_cast<const double2*>(f),
-                                                   reinterpret_cast<double2*>(out), ld);
+    {
+        ProfileScope prof(h, "toeplitz");
+        toeplitz_kernel<<<grid, kCols, 0, h->stream>>>(d, n, (int)N, base, reinterpret_cast<const double2*>(f),
+                                                       reinterpret_cast<double2*>(out), ld);
+    }
     return check_launch(h, "toeplitz_kernel");
 }

@@ -127,12 +127,18 @@ extern "C" prony_status_t prony_coeffs(prony_handle_t h, int d, int n, int m, co
     if ((st = ensure_workspace(h, coeffs_workspace_bytes(d, n, m))) != PRONY_OK) return st;
     const int tiles = (int)((N + kRows - 1) / kRows);
     double2* part = static_cast<double2*>(h->ws);
-    coeffs_tiles<<<tiles, kThreads, 0, h->stream>>>(d, n, (int)N, m, reinterpret_cast<const double2*>(z),
-                                                    reinterpret_cast<const double2*>(f),
-                                                    reinterpret_cast<double2*>(AT_out), part);
+    {
+        ProfileScope prof(h, "coeffs_tiles");
+        coeffs_tiles<<<tiles, kThreads, 0, h->stream>>>(d, n, (int)N, m, reinterpret_cast<const double2*>(z),
+                                                        reinterpret_cast<const double2*>(f),
+                                                        reinterpret_cast<double2*>(AT_out), part);
+    }
     if ((st = check_launch(h, "coeffs_tiles")) != PRONY_OK) return st;
     const int tot = m * m + m;
-    coeffs_reduce<<<(tot + kThreads - 1) / kThreads, kThreads, 0, h->stream>>>(
-        m, tiles, part, reinterpret_cast<double2*>(gram), reinterpret_cast<double2*>(rhs));
+    {
+        ProfileScope prof(h, "coeffs_reduce");
+        coeffs_reduce<<<(tot + kThreads - 1) / kThreads, kThreads, 0, h->stream>>>(
+            m, tiles, part, reinterpret_cast<double2*>(gram), reinterpret_cast<double2*>(rhs));
+    }
     return check_launch(h, "coeffs_reduce");
 }
