@@ -68,6 +68,12 @@ struct Mfma<double> {
     static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
 };
 
+// The K loop keeps operands of kDepth K steps (4 h' each) in flight; it reads
+// up to kPrefetchRows h' past the end of a chunk (packed rows padded with zeros,
+// offsets clamped to the chunk so that the reads stay inside the LDS window).
+constexpr int kDepth = 4;
+constexpr int kPrefetchRows = 4 * kDepth;
+
 struct PencilPlan {
     int d, n, N, m;
     int ells;       // stacked matrices: d, or d + 1 with S_0
@@ -87,7 +93,7 @@ struct PencilPlan {
     int ngroups;    // first-level groups
     size_t lds_bytes;
     // workspace offsets (bytes)
-    size_t off_v, off_u, off_g, off_p, off_gp, off_c, ws_bytes;
+    size_t off_v, off_u, off_g, off_p, off_gp, ws_bytes;
 };
 
 // Grid offset of the extended index h' (row-major over {-1..n}^d).
@@ -103,26 +109,27 @@ __host__ __device__ inline int ext_offset(int hx, int d, int n) {
     return g;
 }
 
+// Packs, per call: (y = 0) the stacked shifted factors V_l in the pair layout,
+// rows h' of the extended index set padded with zeros to sk*kc + kPrefetchRows;
+// (y = 1) the (Re U, Im U) pairs, rows padded to whole 64-row tiles and
+// columns to 16*mbi; (y = 2) the grid offsets G(h') and the zeroed reduction
+// counters. All index arithmetic fits in 32 bits (checked by the host plan).
 template <typename T>
 __global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* __restrict__ U, int64_t u_rs,
                                                    int64_t u_cs, const double2* __restrict__ V, int64_t v_rs,
                                                    int64_t v_cs, pair_t<T>* __restrict__ vp, pair_t<T>* __restrict__ up,
                                                    int* __restrict__ gt, unsigned* __restrict__ counters) {
     using T2 = pair_t<T>;
-    const int64_t kbp = (int64_t)P.sk * P.kc + 4;     // K rows incl. the prefetch pad
-    const int64_t nv = kbp * P.nrp;
-    const int mup = P.mbi * 16;
-    const int64_t nu = (int64_t)P.rt * kRowsPerTile * mup;
-    const int64_t ng = kbp;
-    const int64_t total = nv + nu + ng + P.ngroups + 1;
-    const int E = P.n + 2, Pn = P.n + 1;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (i < nv) {
-            const int hx = (int)(i / P.nrp);
-            const int j = (int)(i - (int64_t)hx * P.nrp);
+    const int kbp = P.sk * P.kc + kPrefetchRows;
+    const int stride = gridDim.x * blockDim.x;
+    const int first = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.y == 0) {
+        const int E = P.n + 2, Pn = P.n + 1;
+        const int nv = kbp * P.nrp;
+        for (int i = first; i < nv; i += stride) {
+            const int hx = i / P.nrp;
+            const int j = i - hx * P.nrp;
             const int c = j >> 1;
-            const bool odd = j & 1;
             double vr = 0.0, vi = 0.0;
             if (hx < P.kb && c < P.C) {
                 const int li = c / P.m, q = c - li * P.m;
@@ -144,11 +151,14 @@ __global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* 
                 }
             }
             // (Re a) multiplies the first member, (Im a) the second.
-            vp[i] = odd ? T2{(T)vi, (T)vr} : T2{(T)vr, (T)(-vi)};
-        } else if (i < nv + nu) {
-            const int64_t r = i - nv;
-            const int k = (int)(r / mup);
-            const int col = (int)(r - (int64_t)k * mup);
+            vp[i] = (j & 1) ? T2{(T)vi, (T)vr} : T2{(T)vr, (T)(-vi)};
+        }
+    } else if (blockIdx.y == 1) {
+        const int mup = P.mbi * 16;
+        const int nu = P.rt * kRowsPerTile * mup;
+        for (int r = first; r < nu; r += stride) {
+            const int k = r / mup;
+            const int col = r - k * mup;
             double ur = 0.0, ui = 0.0;
             if (k < P.N && col < P.m) {
                 const double2 u = U[k * u_rs + col * u_cs];
@@ -156,18 +166,13 @@ __global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* 
                 ui = u.y;
             }
             up[r] = T2{(T)ur, (T)ui};
-        } else if (i < nv + nu + ng) {
-            const int hx = (int)(i - nv - nu);
-            gt[hx] = ext_offset(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
-        } else {
-            counters[i - nv - nu - ng] = 0u;
         }
+    } else {
+        for (int hx = first; hx < kbp; hx += stride) gt[hx] = ext_offset(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
+        for (int i = first; i <= P.ngroups; i += stride) counters[i] = 0u;
     }
 }
 
-// Padding of the packed second factor and of the h' offsets: the K loop
-// prefetches one K step (4 rows) past the end of a chunk.
-constexpr int kPrefetchRows = 4;
 
 template <typename T, int NB>
 __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const double2* __restrict__ grid,
@@ -210,7 +215,11 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const dou
         const double2 v = grid[lo + w];
         win[w] = T2{(T)v.x, (T)v.y};
     }
-    for (int i = tid; i < P.kc + kPrefetchRows; i += kThreads) gt[i] = gtab[min(h_first + i, h_last)];
+    // h' offsets transposed per lane group: gt[g * stride + s] = G(h' = h_first + 4 s + g),
+    // so one 16-byte LDS read gives a lane the offsets of four consecutive K steps.
+    const int gstride = (P.kc + kPrefetchRows) >> 2;
+    for (int i = tid; i < P.kc + kPrefetchRows; i += kThreads)
+        gt[(i & 3) * gstride + (i >> 2)] = gtab[min(h_first + i, h_last)];
     __syncthreads();
 
     const int krow = min(k_first + wave * kRowsPerWave + col, P.N - 1);
@@ -220,28 +229,57 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const dou
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
 
-    // K loop over this chunk, 4 h' per step (lane group g takes h' = 4 ks + g);
-    // the operands of step ks+1 are loaded while the MFMAs of step ks run.
+    // K loop over this chunk, 4 h' per step (lane group g takes h' = 4 ks + g).
+    // Operands rotate through kDepth register buffers: while the MFMAs of step
+    // ks run, the loads of steps ks+1 .. ks+kDepth-1 are in flight.
     const T2* vrow = vp + (size_t)(h_first + g) * P.nrp + col;
     const size_t kstride = (size_t)4 * P.nrp;
     const int nks = P.kc >> 2;
-    T2 a = win[gk - gt[g]];
-    T2 b[NB];
+    const int4* gq = reinterpret_cast<const int4*>(gt + g * gstride);
+    T2 a[kDepth];
+    T2 b[kDepth][NB];
+    auto load_b = [&](T2* dst, int step) {
+        const T2* src = vrow + (size_t)step * kstride;
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) b[cb] = vrow[cb * 16];
-    for (int ks = 0; ks < nks; ++ks) {
-        const T2 an = win[gk - gt[4 * (ks + 1) + g]];
-        T2 bn[NB];
-        const T2* vnext = vrow + (ks + 1) * kstride;
+        for (int cb = 0; cb < NB; ++cb) dst[cb] = src[cb * 16];
+    };
+    auto mma = [&](const T2& av, const T2* bv) {
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) bn[cb] = vnext[cb * 16];
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = M::fma(av.x, bv[cb].x, acc[cb]);
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[cb] = M::fma(a.x, b[cb].x, acc[cb]);
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[cb] = M::fma(a.y, b[cb].y, acc[cb]);
-        a = an;
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) b[cb] = bn[cb];
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = M::fma(av.y, bv[cb].y, acc[cb]);
+    };
+    int4 gc = gq[0];
+    a[0] = win[gk - gc.x];
+    a[1] = win[gk - gc.y];
+    a[2] = win[gk - gc.z];
+    load_b(b[0], 0);
+    load_b(b[1], 1);
+    load_b(b[2], 2);
+    // sched_barrier keeps the compiler from sinking the prefetches next to their use.
+    for (int ks = 0; ks < nks; ks += kDepth) {
+        const int4 gn = gq[(ks >> 2) + 1];
+        a[3] = win[gk - gc.w];
+        load_b(b[3], ks + 3);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a[0], b[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        a[0] = win[gk - gn.x];
+        load_b(b[0], ks + 4);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a[1], b[1]);
+        __builtin_amdgcn_sched_barrier(0);
+        a[1] = win[gk - gn.y];
+        load_b(b[1], ks + 5);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a[2], b[2]);
+        __builtin_amdgcn_sched_barrier(0);
+        a[2] = win[gk - gn.z];
+        load_b(b[2], ks + 6);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a[3], b[3]);
+        __builtin_amdgcn_sched_barrier(0);
+        gc = gn;
     }
     __syncthreads();   // the window is dead from here on; its bytes become esum
 
@@ -335,7 +373,7 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const dou
 }
 
 size_t lds_bytes_for(int win, int kc, int mbi, int nrp, size_t tsize) {
-    const size_t loop = align_up(2 * tsize * (size_t)win, 16) + 4 * ((size_t)kc + kPrefetchRows);
+    const size_t loop = align_up(2 * tsize * (size_t)win, 16) + 4 * ((size_t)kc + kPrefetchRows + 16);
     const size_t epi = tsize * (size_t)mbi * 16 * nrp;
     return align_up(std::max(loop, epi), 16);
 }
@@ -390,6 +428,9 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
         kc = (int)align_up((size_t)(kc / 2), 16);
     }
     P.nwg = P.rt * P.sk;
+    if (((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp >= (int64_t(1) << 31) ||
+        (int64_t)P.nwg * P.m * P.C >= (int64_t(1) << 31))
+        return fail(h, PRONY_ENOTSUP, "prony_build_S: problem too large for 32-bit tile indexing");
     P.gs = std::max(1, (int)std::ceil(std::sqrt((double)P.nwg)));
     P.ngroups = (P.nwg + P.gs - 1) / P.gs;
     const size_t t2 = 2 * tsize;
@@ -405,9 +446,8 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
     P.off_gp = off;
     off = align_up(off + sizeof(double2) * (size_t)P.ngroups * tot, 256);
-    P.off_c = off;
-    off = align_up(off + sizeof(unsigned) * ((size_t)P.ngroups + 1), 256);
     P.ws_bytes = off;
+    if (P.ngroups + 1 > kCounterSlots) return fail(h, PRONY_ENOTSUP, "prony_build_S: too many workgroups");
     return PRONY_OK;
 }
 
@@ -469,16 +509,16 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, const double
     int* gt = reinterpret_cast<int*>(ws + P.off_g);
     T2* part = reinterpret_cast<T2*>(ws + P.off_p);
     double2* gpart = reinterpret_cast<double2*>(ws + P.off_gp);
-    unsigned* counters = reinterpret_cast<unsigned*>(ws + P.off_c);
+    unsigned* counters = h->counters;
 
     const int64_t kbp = (int64_t)P.sk * P.kc + kPrefetchRows;
-    const int64_t total = kbp * P.nrp + (int64_t)P.rt * kRowsPerTile * P.mbi * 16 + kbp + P.ngroups + 1;
-    const int pack_blocks = (int)std::min<int64_t>((total + 255) / 256, 4 * (int64_t)h->num_cus);
+    const int64_t largest = std::max<int64_t>(kbp * P.nrp, (int64_t)P.rt * kRowsPerTile * P.mbi * 16);
+    const int pack_blocks = (int)std::min<int64_t>((largest + 255) / 256, 2 * (int64_t)h->num_cus);
     {
         ProfileScope prof(h, "pencil_pack");
-        pencil_pack<T><<<pack_blocks, 256, 0, h->stream>>>(P, reinterpret_cast<const double2*>(U), u_rs, u_cs,
-                                                           reinterpret_cast<const double2*>(V), v_rs, v_cs, vp, up,
-                                                           gt, counters);
+        pencil_pack<T><<<dim3(pack_blocks, 3), 256, 0, h->stream>>>(
+            P, reinterpret_cast<const double2*>(U), u_rs, u_cs, reinterpret_cast<const double2*>(V), v_rs, v_cs, vp,
+            up, gt, counters);
     }
     if ((st = check_launch(h, "pencil_pack")) != PRONY_OK) return st;
     st = dispatch_tiles<T>(h, P, reinterpret_cast<const double2*>(f), vp, up, gt, part, gpart, counters, sigma,

@@ -7,11 +7,12 @@ namespace prony {
 namespace {
 
 constexpr int kCols = 256;     // threads per block = columns per block
+typedef double vdouble2 __attribute__((ext_vector_type(2)));   // one 16-byte access
 constexpr int kRows = 16;      // rows written by each block
 
 __global__ __launch_bounds__(kCols) void toeplitz_kernel(int d, int n, int N, int base,
-                                                         const double2* __restrict__ f,
-                                                         double2* __restrict__ out, int64_t ld) {
+                                                         const vdouble2* __restrict__ f,
+                                                         vdouble2* __restrict__ out, int64_t ld) {
     const int h = blockIdx.x * kCols + threadIdx.x;
     const int k0 = blockIdx.y * kRows;
     if (h >= N) return;
@@ -19,9 +20,8 @@ __global__ __launch_bounds__(kCols) void toeplitz_kernel(int d, int n, int N, in
     const int kend = min(k0 + kRows, N);
     for (int k = k0; k < kend; ++k) {
         const int gk = grid_offset_of_index(k, d, n);   // uniform across the block
-        const double2 v = f[gk - gh + base];
-        __builtin_nontemporal_store(v.x, &out[(int64_t)k * ld + h].x);
-        __builtin_nontemporal_store(v.y, &out[(int64_t)k * ld + h].y);
+        const vdouble2 v = f[gk - gh + base];
+        __builtin_nontemporal_store(v, &out[(int64_t)k * ld + h]);
     }
 }
 
@@ -48,8 +48,8 @@ extern "C" prony_status_t prony_build_T(prony_handle_t h, int d, int n, int whic
     dim3 grid((unsigned)((N + kCols - 1) / kCols), (unsigned)((N + kRows - 1) / kRows));
     {
         ProfileScope prof(h, "toeplitz");
-        toeplitz_kernel<<<grid, kCols, 0, h->stream>>>(d, n, (int)N, base, reinterpret_cast<const double2*>(f),
-                                                       reinterpret_cast<double2*>(out), ld);
+        toeplitz_kernel<<<grid, kCols, 0, h->stream>>>(d, n, (int)N, base, reinterpret_cast<const vdouble2*>(f),
+                                                       reinterpret_cast<vdouble2*>(out), ld);
     }
     return check_launch(h, "toeplitz_kernel");
 }

@@ -2,11 +2,10 @@
 // Algorithm 1, last line): A^T[k,j] = prod_l z_j(l)^{k_l}, gram = (A^T)^* A^T and
 // rhs = (A^T)^* f_I, reduced over k in I_n. FP64 throughout.
 //
-// coeffs_tiles: one workgroup per 64 rows k. The rows of A^T are evaluated into
-//               LDS (integer powers by binary exponentiation), optionally
-//               written out, then the 64-row partial Gram matrix and right-hand
-//               side are formed from LDS and stored.
-// coeffs_reduce: sums the per-tile partials in a fixed order.
+// coeffs_tiles: a workgroup evaluates rows of A^T into LDS 64 at a time
+//               (integer powers by binary exponentiation), optionally writes
+//               them out, and accumulates its part of the Gram matrix and
+//               right-hand side; the last workgroup adds the parts in order.
 #include <algorithm>
 
 #include "common.h"
@@ -33,79 +32,109 @@ __device__ __forceinline__ double2 cpow_int(double2 z, int e) {
     return r;
 }
 
-__global__ __launch_bounds__(kThreads) void coeffs_tiles(int d, int n, int N, int m, const double2* __restrict__ z,
+constexpr int kEntries = (kMaxM * kMaxM + kMaxM + kThreads - 1) / kThreads;
+
+// One workgroup takes `chunks` consecutive 64-row chunks of I_n. Per chunk the
+// rows of A^T are evaluated into LDS, then every thread accumulates its fixed
+// entries of (A^T)^* [A^T | f_I] over the chunk in FP64 registers. The
+// workgroup's sums are stored; the last workgroup to finish adds them up in
+// workgroup order (bitwise reproducible) and writes gram and rhs.
+__global__ __launch_bounds__(kThreads) void coeffs_tiles(int d, int n, int N, int m, int chunks,
+                                                         const double2* __restrict__ z,
                                                          const double2* __restrict__ f, double2* __restrict__ at_out,
-                                                         double2* __restrict__ part) {
+                                                         double2* __restrict__ part, unsigned* __restrict__ counter,
+                                                         double2* __restrict__ gram, double2* __restrict__ rhs) {
     __shared__ double2 sz[kMaxM * 3];
     __shared__ double2 sa[kRows * kMaxM];
     __shared__ double2 sf[kRows];
+    __shared__ int s_last;
     const int tid = threadIdx.x;
-    const int k0 = blockIdx.x * kRows;
+    const int tot = m * m + m;
     for (int i = tid; i < m * d; i += kThreads) sz[i] = z[i];
     const int c0 = grid_center(d, n);
-    for (int r = tid; r < kRows; r += kThreads) {
-        const int k = k0 + r;
-        sf[r] = k < N ? f[grid_offset_of_index(k, d, n) + c0] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
     const int P = n + 1;
-    for (int e = tid; e < kRows * m; e += kThreads) {
-        const int r = e / m, j = e - (e / m) * m;
-        const int k = k0 + r;
-        double2 a = make_double2(0.0, 0.0);
-        if (k < N) {
-            a = make_double2(1.0, 0.0);
-            int rem = k;
-            for (int l = d - 1; l >= 0; --l) {
-                const int q = rem / P;
-                a = cmul(a, cpow_int(sz[j * d + l], rem - q * P));
-                rem = q;
+    double re[kEntries], im[kEntries];
+#pragma unroll
+    for (int u = 0; u < kEntries; ++u) re[u] = im[u] = 0.0;
+
+    const int nchunks = (N + kRows - 1) / kRows;
+    const int c_end = min((blockIdx.x + 1) * chunks, nchunks);
+    for (int ch = blockIdx.x * chunks; ch < c_end; ++ch) {
+        const int k0 = ch * kRows;
+        __syncthreads();
+        for (int r = tid; r < kRows; r += kThreads) {
+            const int k = k0 + r;
+            sf[r] = k < N ? f[grid_offset_of_index(k, d, n) + c0] : make_double2(0.0, 0.0);
+        }
+        for (int e = tid; e < kRows * m; e += kThreads) {
+            const int r = e / m, j = e - (e / m) * m;
+            const int k = k0 + r;
+            double2 a = make_double2(0.0, 0.0);
+            if (k < N) {
+                a = make_double2(1.0, 0.0);
+                int rem = k;
+                for (int l = d - 1; l >= 0; --l) {
+                    const int q = rem / P;
+                    a = cmul(a, cpow_int(sz[j * d + l], rem - q * P));
+                    rem = q;
+                }
+                if (at_out) at_out[(size_t)k * m + j] = a;
             }
-            if (at_out) at_out[(size_t)k * m + j] = a;
+            sa[r * kMaxM + j] = a;
         }
-        sa[r * kMaxM + j] = a;
+        __syncthreads();
+        const int rows = min(kRows, N - k0);
+#pragma unroll
+        for (int u = 0; u < kEntries; ++u) {
+            const int e = tid + u * kThreads;
+            if (e < tot) {
+                const int i = e < m * m ? e / m : e - m * m;
+                const int j = e < m * m ? e - (e / m) * m : -1;
+                for (int r = 0; r < rows; ++r) {
+                    const double2 ai = sa[r * kMaxM + i];
+                    const double2 b = j >= 0 ? sa[r * kMaxM + j] : sf[r];
+                    // conj(ai) * b
+                    re[u] = fma(ai.x, b.x, fma(ai.y, b.y, re[u]));
+                    im[u] = fma(ai.x, b.y, fma(-ai.y, b.x, im[u]));
+                }
+            }
+        }
     }
+    double2* out = part + (size_t)blockIdx.x * tot;
+#pragma unroll
+    for (int u = 0; u < kEntries; ++u) {
+        const int e = tid + u * kThreads;
+        if (e < tot) out[e] = make_double2(re[u], im[u]);
+    }
+    __threadfence();
     __syncthreads();
-    double2* out = part + (size_t)blockIdx.x * (m * m + m);
-    const int rows = min(kRows, N - k0);
-    for (int e = tid; e < m * m + m; e += kThreads) {
-        const int i = e < m * m ? e / m : e - m * m;
-        const int j = e < m * m ? e - (e / m) * m : -1;
-        double re = 0.0, im = 0.0;
-        for (int r = 0; r < rows; ++r) {
-            const double2 ai = sa[r * kMaxM + i];
-            const double2 b = j >= 0 ? sa[r * kMaxM + j] : sf[r];
-            // conj(ai) * b
-            re = fma(ai.x, b.x, fma(ai.y, b.y, re));
-            im = fma(ai.x, b.y, fma(-ai.y, b.x, im));
+    if (tid == 0) s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int e = tid; e < tot; e += kThreads) {
+        double sr = 0.0, si = 0.0;
+        for (int w = 0; w < (int)gridDim.x; ++w) {
+            const double2 v = part[(size_t)w * tot + e];
+            sr += v.x;
+            si += v.y;
         }
-        out[e] = make_double2(re, im);
+        if (e < m * m)
+            gram[e] = make_double2(sr, si);
+        else
+            rhs[e - m * m] = make_double2(sr, si);
     }
+    if (tid == 0) *counter = 0u;
 }
 
-__global__ __launch_bounds__(kThreads) void coeffs_reduce(int m, int tiles, const double2* __restrict__ part,
-                                                          double2* __restrict__ gram, double2* __restrict__ rhs) {
-    const int e = blockIdx.x * kThreads + threadIdx.x;
-    const int tot = m * m + m;
-    if (e >= tot) return;
-    double re = 0.0, im = 0.0;
-    for (int t = 0; t < tiles; ++t) {
-        const double2 v = part[(size_t)t * tot + e];
-        re += v.x;
-        im += v.y;
-    }
-    if (e < m * m)
-        gram[e] = make_double2(re, im);
-    else
-        rhs[e - m * m] = make_double2(re, im);
-}
+constexpr int kMaxWorkgroups = 64;
 
 }  // namespace
 
 size_t coeffs_workspace_bytes(int d, int n, int m) {
-    const int64_t N = ipow(n + 1, d);
-    const int64_t tiles = (N + kRows - 1) / kRows;
-    return align_up((size_t)tiles * (m * m + m) * sizeof(double2), 256);
+    (void)d;
+    (void)n;
+    return align_up((size_t)kMaxWorkgroups * (m * m + m) * sizeof(double2), 256);
 }
 
 }  // namespace prony
@@ -125,20 +154,18 @@ extern "C" prony_status_t prony_coeffs(prony_handle_t h, int d, int n, int m, co
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     if ((st = ensure_workspace(h, coeffs_workspace_bytes(d, n, m))) != PRONY_OK) return st;
-    const int tiles = (int)((N + kRows - 1) / kRows);
+    const int nchunks = (int)((N + kRows - 1) / kRows);
+    const int chunks = (nchunks + kMaxWorkgroups - 1) / kMaxWorkgroups;
+    const int wgs = (nchunks + chunks - 1) / chunks;
     double2* part = static_cast<double2*>(h->ws);
     {
         ProfileScope prof(h, "coeffs_tiles");
-        coeffs_tiles<<<tiles, kThreads, 0, h->stream>>>(d, n, (int)N, m, reinterpret_cast<const double2*>(z),
-                                                        reinterpret_cast<const double2*>(f),
-                                                        reinterpret_cast<double2*>(AT_out), part);
+        coeffs_tiles<<<wgs, kThreads, 0, h->stream>>>(d, n, (int)N, m, chunks, reinterpret_cast<const double2*>(z),
+                                                      reinterpret_cast<const double2*>(f),
+                                                      reinterpret_cast<double2*>(AT_out), part,
+                                                      h->counters + (kCounterSlots - 1),
+                                                      reinterpret_cast<double2*>(gram),
+                                                      reinterpret_cast<double2*>(rhs));
     }
-    if ((st = check_launch(h, "coeffs_tiles")) != PRONY_OK) return st;
-    const int tot = m * m + m;
-    {
-        ProfileScope prof(h, "coeffs_reduce");
-        coeffs_reduce<<<(tot + kThreads - 1) / kThreads, kThreads, 0, h->stream>>>(
-            m, tiles, part, reinterpret_cast<double2*>(gram), reinterpret_cast<double2*>(rhs));
-    }
-    return check_launch(h, "coeffs_reduce");
+    return check_launch(h, "coeffs_tiles");
 }
