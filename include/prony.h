@@ -93,7 +93,7 @@ prony_status_t prony_reserve(prony_handle_t handle, int d_max, int n_max, int m_
    by the handle is bracketed by a pair of HIP events recorded on the handle's
    stream; NULL stops recording. Each call discards earlier records.
    Kernel names: "samples", "toeplitz", "pencil_pack", "pencil_tiles",
-   "coeffs_tiles". */
+   "pencil_tiles_batched", "coeffs_tiles", "adjoint_pack", "adjoint_tiles". */
 prony_status_t prony_profile_enable(prony_handle_t handle, const char* kernel);
 
 /* Synchronise the stream and report the recorded launches of the profiled kernel:
@@ -158,6 +158,65 @@ prony_status_t prony_build_S(prony_handle_t handle, int d, int n, int m, const d
 prony_status_t prony_coeffs(prony_handle_t handle, int d, int n, int m,
                             const double* z, const double* f,
                             double* gram, double* rhs, double* AT_out);
+
+/* Adjoint of the pencil map (system pattern: differentiation). With U, Sigma, V
+   held fixed, f -> S_l = U^* T_l(f) V Sigma^{-1} (Sec. 1, eq. generateSl) is
+   complex-linear, so for a real loss L with gS_l = dL/dS_l in PyTorch's
+   convention (dL/dRe + i dL/dIm) the gradient on the sample grid is
+     gf(p) = sum_l sum_{k - h + e_l = p} [U gS_l Sigma^{-1} V^*]_{k,h}.
+   U, V, sigma, strides: as for prony_build_S. gS: d x m x m complex128 (gradient
+   of S_1..S_d). gf: (2n+2)^d complex128, overwritten. prec selects the MFMA and
+   tile-accumulation type (FP32 or FP64); the window sums are added to gf in
+   FP64. Summation order inside a window bin is not fixed (LDS atomics), so
+   repeated runs agree to rounding, not bitwise. Requires 1 <= m <= min(N, 32). */
+prony_status_t prony_build_S_adjoint(prony_handle_t handle, int d, int n, int m,
+                                     const double* U, int64_t u_rs, int64_t u_cs,
+                                     const double* sigma,
+                                     const double* V, int64_t v_rs, int64_t v_cs,
+                                     const double* gS, prony_prec_t prec, double* gf);
+
+/* ---- many instances: one planned launch sequence, graph capture ------------- */
+
+typedef struct prony_batch_s* prony_batch_t;
+
+/* One S-build of a batch (Sec. 1, eq. generateSl, per instance). Pointers are
+   device pointers owned by the caller; they must stay valid, and keep their
+   shapes, for every launch of the batch. */
+typedef struct {
+    int d, n, m;          /* 1 <= d <= 3, n >= 1, 1 <= m <= min(N, 32)        */
+    const double* f;      /* sample grid, (2n+2)^d complex128                */
+    const double* U;      /* N x m complex128, row-major, contiguous          */
+    const double* sigma;  /* m doubles > 0                                    */
+    const double* V;      /* N x m complex128, row-major, contiguous          */
+    double* S;            /* output: d x m x m complex128 (S_1..S_d)          */
+} prony_instance_t;
+
+/* Plan the S-build of `count` (1..65535) instances (host array of descriptors, copied):
+   validates every descriptor, chooses tiles per instance, groups the instances
+   by column-block count, orders them by decreasing work, allocates the batch's
+   own device workspace and uploads its work table (synchronously on the
+   handle's stream). Errors name the offending instance. */
+prony_status_t prony_batch_create(prony_handle_t handle, int count, const prony_instance_t* instances,
+                                  prony_prec_t prec, prony_batch_t* batch);
+
+/* Free a batch (waits for the stream of the handle that created it). */
+prony_status_t prony_batch_destroy(prony_batch_t batch);
+
+/* Enqueue the S-build of every instance of the batch on the handle's stream:
+   one packing launch for all instances, then one launch per column-block class.
+   Allocates nothing and records no memset, so it can be captured. The handle
+   must be the one that created the batch. */
+prony_status_t prony_build_S_batched(prony_handle_t handle, prony_batch_t batch);
+
+/* Capture prony_build_S_batched(handle, batch) into a HIP graph (on a private
+   stream) and instantiate it; *graph_exec receives a hipGraphExec_t. */
+prony_status_t prony_graph_capture(prony_handle_t handle, prony_batch_t batch, void** graph_exec);
+
+/* Launch an instantiated graph on the handle's stream. */
+prony_status_t prony_graph_launch(prony_handle_t handle, void* graph_exec);
+
+/* Destroy an instantiated graph. */
+prony_status_t prony_graph_destroy(void* graph_exec);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,13 @@ PRONY_FP64 = 0
 PRONY_FP32 = 1
 PRONY_WITH_S0 = 1
 
+class InstanceDesc(ctypes.Structure):
+    """prony_instance_t."""
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int), ("m", ctypes.c_int),
+                ("f", ctypes.c_void_p), ("U", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("V", ctypes.c_void_p), ("S", ctypes.c_void_p)]
+
+
 _c_int = ctypes.c_int
 _c_i64 = ctypes.c_int64
 _ptr = ctypes.c_void_p
@@ -43,6 +50,14 @@ SIGNATURES = {
                        _c_int, ctypes.c_uint, _ptr], _c_int),
     "prony_coeffs": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _ptr, _ptr, _ptr], _c_int),
     "prony_profile_enable": ([_ptr, ctypes.c_char_p], _c_int),
+    "prony_build_S_adjoint": ([_ptr, _c_int, _c_int, _c_int, _ptr, _c_i64, _c_i64, _ptr, _ptr, _c_i64, _c_i64,
+                               _ptr, _c_int, _ptr], _c_int),
+    "prony_batch_create": ([_ptr, _c_int, ctypes.POINTER(InstanceDesc), _c_int, ctypes.POINTER(_ptr)], _c_int),
+    "prony_batch_destroy": ([_ptr], _c_int),
+    "prony_build_S_batched": ([_ptr, _ptr], _c_int),
+    "prony_graph_capture": ([_ptr, _ptr, ctypes.POINTER(_ptr)], _c_int),
+    "prony_graph_launch": ([_ptr, _ptr], _c_int),
+    "prony_graph_destroy": ([_ptr], _c_int),
     "prony_profile_read": ([_ptr, ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_double)], _c_int),
 }
 

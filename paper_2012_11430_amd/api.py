@@ -142,6 +142,34 @@ def build_S(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tenso
     return out
 
 
+def build_S_adjoint(gS: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,
+                    prec: str = "fp32", out: torch.Tensor | None = None) -> torch.Tensor:
+    """Gradient on the sample grid of a loss with dL/dS_l = gS[l-1] (prony_build_S_adjoint)."""
+    _require(gS, "gS", torch.complex128)
+    dev = gS.device
+    _require(U, "U", torch.complex128, dev, contiguous=False)
+    _require(V, "V", torch.complex128, dev, contiguous=False)
+    _require(sigma, "sigma", torch.float64, dev)
+    N = (n + 1) ** d
+    if U.dim() != 2 or U.shape[0] != N or V.shape != U.shape:
+        raise ValueError("U and V must be N x m")
+    m = U.shape[1]
+    if gS.shape != (d, m, m) or sigma.shape != (m,):
+        raise ValueError("gS must be (d, m, m) and sigma (m,)")
+    if prec not in ("fp64", "fp32"):
+        raise ValueError("prec must be 'fp64' or 'fp32'")
+    if out is None:
+        out = torch.empty(grid_size(d, n), dtype=torch.complex128, device=dev)
+    else:
+        _require(out, "out", torch.complex128, dev)
+        if out.numel() != grid_size(d, n):
+            raise ValueError("out must hold (2n+2)^d values")
+    _call("prony_build_S_adjoint", dev, d, n, m, _ptr(U), U.stride(0), U.stride(1), _ptr(sigma),
+          _ptr(V), V.stride(0), V.stride(1), _ptr(gS), _lib.PRONY_FP32 if prec == "fp32" else _lib.PRONY_FP64,
+          _ptr(out))
+    return out
+
+
 def coeffs(z: torch.Tensor, f: torch.Tensor, d: int, n: int, want_AT: bool = False):
     """Gram (A^T)^* A^T and rhs (A^T)^* f_I (prony_coeffs); optionally A^T (N x m)."""
     _require(z, "z", torch.complex128)
@@ -179,3 +207,75 @@ def profile_read(device: torch.device):
     total = ctypes.c_double()
     _call("prony_profile_read", device, ctypes.byref(launches), ctypes.byref(total))
     return launches.value, total.value
+
+
+class Batch:
+    """A planned S-build of many instances (prony_batch_create).
+
+    instances: sequence of (d, n, f, U, sigma, V) with U, V contiguous N x m
+    complex128 device tensors; the outputs S (d, m, m) are allocated here and
+    exposed as `batch.S`. The tensors are referenced for the batch's lifetime.
+    """
+
+    def __init__(self, instances, prec: str = "fp32"):
+        if prec not in ("fp64", "fp32"):
+            raise ValueError("prec must be 'fp64' or 'fp32'")
+        if not instances:
+            raise ValueError("empty batch")
+        dev = instances[0][2].device
+        descs = (_lib.InstanceDesc * len(instances))()
+        self._keep = []
+        self.S = []
+        for i, (d, n, f, U, sigma, V) in enumerate(instances):
+            N = (n + 1) ** d
+            _require(f, "f", torch.complex128, dev)
+            _require(U, "U", torch.complex128, dev)
+            _require(V, "V", torch.complex128, dev)
+            _require(sigma, "sigma", torch.float64, dev)
+            if f.numel() != grid_size(d, n) or U.dim() != 2 or U.shape[0] != N or V.shape != U.shape:
+                raise ValueError(f"instance {i}: shapes do not match d={d}, n={n}")
+            m = U.shape[1]
+            S = torch.empty((d, m, m), dtype=torch.complex128, device=dev)
+            descs[i] = _lib.InstanceDesc(d, n, m, f.data_ptr(), U.data_ptr(), sigma.data_ptr(),
+                                         V.data_ptr(), S.data_ptr())
+            self._keep += [f, U, sigma, V, S]
+            self.S.append(S)
+        self.device = dev
+        self.prec = prec
+        self.graph = None
+        out = ctypes.c_void_p()
+        _call("prony_batch_create", dev, len(instances), descs,
+              _lib.PRONY_FP32 if prec == "fp32" else _lib.PRONY_FP64, ctypes.byref(out))
+        self.handle = out
+
+    def run(self) -> None:
+        """Enqueue the S-build of every instance (prony_build_S_batched)."""
+        _call("prony_build_S_batched", self.device, self.handle)
+
+    def capture(self) -> None:
+        """Capture run() into a HIP graph (prony_graph_capture)."""
+        if self.graph is None:
+            g = ctypes.c_void_p()
+            _call("prony_graph_capture", self.device, self.handle, ctypes.byref(g))
+            self.graph = g
+
+    def replay(self) -> None:
+        """Launch the captured graph on torch's current stream (prony_graph_launch)."""
+        if self.graph is None:
+            self.capture()
+        _call("prony_graph_launch", self.device, self.graph)
+
+    def close(self) -> None:
+        lib = _lib.load()
+        if self.graph is not None:
+            lib.prony_graph_destroy(self.graph)
+            self.graph = None
+        if self.handle is not None and self.handle.value:
+            lib.prony_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,327 @@
+// Adjoint of the pencil map f -> S_l = U^* T_l(f) V Sigma^{-1} (Sec. 1, eq.
+// generateSl), with U, Sigma, V held fixed: given gS_l = dL/dS_l (PyTorch's
+// convention, grad = dL/dRe + i dL/dIm), the gradient on the sample grid is
+//     grad(p) = sum_l sum_{k - h + e_l = p} X_l[k, h],   X_l = U gS_l Sigma^{-1} V^*.
+// With h' = h - e_l as in the forward kernel, all d terms are one product of
+//     Z = [U gS_1 Sigma^{-1} | ... | U gS_d Sigma^{-1}]      (N x d m)
+// with the stacked conjugated shifted factors W_l[h', q] = conj(V[h'+e_l, q]):
+//     grad(p) = sum_{k - h' = p} (Z W^T)[k, h'],
+// i.e. the N x (n+2)^d product is summed along its Toeplitz diagonals.
+//
+// adjoint_pack   forms Z (FP64, stored in T), packs W in the MFMA pair layout,
+//                writes the G(h') table and zeroes the gradient;
+// adjoint_tiles  one workgroup = 64 rows k x one chunk of h': for every block of
+//                16 h' the tile of Z W^T is formed on MFMA (K = d m), and each
+//                entry is added (LDS atomics, accumulation in T) to the bin of
+//                its diagonal in an LDS copy of the workgroup's grid window; the
+//                window is then added to the gradient in FP64 (device atomics).
+// The accumulation order inside a bin is not fixed: results agree to rounding,
+// not bitwise, between runs.
+#include <algorithm>
+
+#include "common.h"
+#include "mfma.h"
+
+namespace prony {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kRows = kWaves * 16;
+constexpr int kThreads = kWaves * 64;
+constexpr int kHBlock = 16;          // h' per MFMA output block (32 real columns)
+
+struct AdjPlan {
+    int d, n, N, m, C;
+    int cp;        // complex K padded to a multiple of 8 (2 * KS... see ksteps)
+    int ksteps;    // cp / 4
+    int kb, kc, sk, rt, nwg, win_cap, c0, gsize;
+    size_t lds_bytes;
+    size_t off_z, off_w, off_g, ws_bytes;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void adjoint_pack(AdjPlan P, const double2* __restrict__ U, int64_t u_rs,
+                                                    int64_t u_cs, const double* __restrict__ sigma,
+                                                    const double2* __restrict__ V, int64_t v_rs, int64_t v_cs,
+                                                    const double2* __restrict__ gS, pair_t<T>* __restrict__ zp,
+                                                    pair_t<T>* __restrict__ wp, int* __restrict__ gt,
+                                                    double2* __restrict__ gf) {
+    using T2 = pair_t<T>;
+    const int stride = gridDim.x * blockDim.x;
+    const int first = blockIdx.x * blockDim.x + threadIdx.x;
+    const int kbp = P.sk * P.kc;
+    if (blockIdx.y == 0) {
+        // Z[k][c] = sum_i U[k,i] gS_l[i,q] / sigma_q, c = (l-1) m + q; rows padded to
+        // whole tiles and columns to cp with zeros
+        const int nz = P.rt * kRows * P.cp;
+        for (int e = first; e < nz; e += stride) {
+            const int k = e / P.cp, c = e - (e / P.cp) * P.cp;
+            double re = 0.0, im = 0.0;
+            if (k < P.N && c < P.C) {
+                const int li = c / P.m, q = c - li * P.m;
+                for (int i = 0; i < P.m; ++i) {
+                    const double2 u = U[k * u_rs + i * u_cs];
+                    const double2 gv = gS[((size_t)li * P.m + i) * P.m + q];
+                    re = fma(u.x, gv.x, fma(-u.y, gv.y, re));
+                    im = fma(u.x, gv.y, fma(u.y, gv.x, im));
+                }
+                const double s = sigma[q];
+                re /= s;
+                im /= s;
+            }
+            zp[e] = T2{(T)re, (T)im};
+        }
+    } else if (blockIdx.y == 1) {
+        // W pairs, row c, column j = 2 h' + part: (Re Z) multiplies .x, (Im Z) .y
+        const int E = P.n + 2, Pn = P.n + 1;
+        const int row = 2 * kbp;
+        const int nw = P.cp * row;
+        for (int e = first; e < nw; e += stride) {
+            const int c = e / row, j = e - (e / row) * row;
+            const int hx = j >> 1;
+            double wr = 0.0, wi = 0.0;
+            if (hx < P.kb && c < P.C) {
+                const int li = c / P.m, q = c - li * P.m;
+                const int ell = li + 1;
+                int rem = hx, idx = 0, scale = 1;
+                bool inside = true;
+                for (int l = P.d - 1; l >= 0; --l) {
+                    const int qq = rem / E;
+                    const int coord = rem - qq * E - 1 + (l == ell - 1 ? 1 : 0);
+                    rem = qq;
+                    inside = inside && coord >= 0 && coord <= P.n;
+                    idx += coord * scale;
+                    scale *= Pn;
+                }
+                if (inside) {
+                    const double2 v = V[idx * v_rs + q * v_cs];
+                    wr = v.x;
+                    wi = -v.y;   // conj
+                }
+            }
+            wp[e] = (j & 1) ? T2{(T)wi, (T)wr} : T2{(T)wr, (T)(-wi)};
+        }
+    } else {
+        for (int hx = first; hx < kbp; hx += stride) gt[hx] = ext_offset(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
+        for (int p = first; p < P.gsize; p += stride) gf[p] = make_double2(0.0, 0.0);
+    }
+}
+
+__device__ __forceinline__ void lds_add(float* a, float v) { atomicAdd(a, v); }
+__device__ __forceinline__ void lds_add(double* a, double v) { atomicAdd(a, v); }
+
+template <typename T, int KS>
+__global__ __launch_bounds__(kThreads) void adjoint_tiles(AdjPlan P, const pair_t<T>* __restrict__ zp,
+                                                          const pair_t<T>* __restrict__ wp,
+                                                          const int* __restrict__ gtab, double2* __restrict__ gf) {
+    using T2 = pair_t<T>;
+    using M = Mfma<T>;
+    using acc_t = typename M::acc_t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* bins = reinterpret_cast<T*>(smem);                                        // 2 * win_cap
+    int* gt = reinterpret_cast<int*>(smem + align_up(2 * sizeof(T) * (size_t)P.win_cap, 16));  // kc
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const int L = blockIdx.x;
+    const int sk_i = L / P.rt, rt_i = L - (L / P.rt) * P.rt;
+    const int k_first = rt_i * kRows;
+    const int k_last = min(k_first + kRows - 1, P.N - 1);
+    const int h_first = sk_i * P.kc;
+    const int h_last = min(h_first + P.kc, P.kb) - 1;
+    const int lo = grid_offset_of_index(k_first, P.d, P.n) - gtab[h_last] + P.c0;
+    const int hi = grid_offset_of_index(k_last, P.d, P.n) - gtab[h_first] + P.c0;
+    const int W = hi - lo + 1;
+    for (int i = tid; i < 2 * W; i += kThreads) bins[i] = T(0);
+    for (int i = tid; i < P.kc; i += kThreads) gt[i] = gtab[min(h_first + i, h_last)];
+
+    // A operand (rows of Z) for all K steps, kept in registers
+    const int krow_raw = k_first + wave * 16;
+    T2 a[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) a[s] = zp[(size_t)(krow_raw + col) * P.cp + 4 * s + g];
+    // diagonal bin base of the rows this lane's accumulator elements hold
+    int gk[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        gk[r] = grid_offset_of_index(min(krow_raw + M::row(g, r), P.N - 1), P.d, P.n) + P.c0 - lo;
+    __syncthreads();
+
+    const int rowlen = 2 * P.sk * P.kc;
+    const int nblk = P.kc / kHBlock;
+    for (int hb = 0; hb < nblk; ++hb) {
+        acc_t acc[2] = {acc_t{0, 0, 0, 0}, acc_t{0, 0, 0, 0}};
+        const T2* wcol = wp + (size_t)g * rowlen + 2 * (h_first + hb * kHBlock) + col;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const T2 b0 = wcol[(size_t)(4 * s) * rowlen];
+            const T2 b1 = wcol[(size_t)(4 * s) * rowlen + 16];
+            acc[0] = M::fma(a[s].x, b0.x, acc[0]);
+            acc[1] = M::fma(a[s].x, b1.x, acc[1]);
+            acc[0] = M::fma(a[s].y, b0.y, acc[0]);
+            acc[1] = M::fma(a[s].y, b1.y, acc[1]);
+        }
+        // element r of lane (g, col) in block cb: row row(g,r), real column
+        // j = 16 cb + col, i.e. h' = hb*16 + j/2 and part j&1
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int j = cb * 16 + col;
+            const int hl = hb * kHBlock + (j >> 1);
+            const int gh = gt[hl];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds_add(&bins[2 * (gk[r] - gh) + (j & 1)], acc[cb][r]);
+        }
+    }
+    __syncthreads();
+    double* out = reinterpret_cast<double*>(gf + lo);
+    for (int i = tid; i < 2 * W; i += kThreads) {
+        const T v = bins[i];
+        if (v != T(0)) unsafeAtomicAdd(&out[i], (double)v);
+    }
+}
+
+prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize, AdjPlan& P) {
+    P = AdjPlan{};
+    P.d = d;
+    P.n = n;
+    P.N = (int)ipow(n + 1, d);
+    P.m = m;
+    P.C = d * m;
+    P.cp = (int)align_up((size_t)P.C, 8);
+    P.ksteps = P.cp / 4;
+    P.kb = (int)ipow(n + 2, d);
+    P.rt = (P.N + kRows - 1) / kRows;
+    P.c0 = grid_center(d, n);
+    P.gsize = (int)ipow(2 * n + 2, d);
+    const size_t budget = std::min<size_t>(h->lds_per_block, 64 * 1024);
+    const int target = 4 * h->num_cus;
+    const int sk_target = std::max(1, target / P.rt);
+    int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), kHBlock);
+    kc = std::max(kc, std::min(256, (int)align_up((size_t)P.kb, kHBlock)));
+    auto span = [&](int count, int len, bool ext) {
+        int best = 0;
+        for (int s = 0; s < count; s += len) {
+            const int e = std::min(s + len, count) - 1;
+            const int a = ext ? ext_offset(s, d, n) : grid_offset_of_index(s, d, n);
+            const int b = ext ? ext_offset(e, d, n) : grid_offset_of_index(e, d, n);
+            best = std::max(best, b - a);
+        }
+        return best;
+    };
+    const int rowspan = span(P.N, kRows, false);
+    for (;;) {
+        const int win = rowspan + span(P.kb, kc, true) + 1;
+        const size_t lds = align_up(2 * tsize * (size_t)win, 16) + 4 * (size_t)kc;
+        if (lds <= budget) {
+            P.kc = kc;
+            P.sk = (P.kb + kc - 1) / kc;
+            P.win_cap = win;
+            P.lds_bytes = lds;
+            break;
+        }
+        if (kc <= kHBlock) return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint: window does not fit in LDS");
+        kc = (int)align_up((size_t)(kc / 2), kHBlock);
+    }
+    P.nwg = P.rt * P.sk;
+    const size_t t2 = 2 * tsize;
+    if ((int64_t)P.cp * 2 * P.sk * P.kc >= (int64_t(1) << 31))
+        return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint: problem too large");
+    size_t off = 0;
+    P.off_z = off;
+    off = align_up(off + t2 * (size_t)P.rt * kRows * P.cp, 256);
+    P.off_w = off;
+    off = align_up(off + t2 * (size_t)P.cp * 2 * P.sk * P.kc, 256);
+    P.off_g = off;
+    off = align_up(off + 4 * (size_t)P.sk * P.kc, 256);
+    P.ws_bytes = off;
+    return PRONY_OK;
+}
+
+template <typename T, int KS>
+prony_status_t launch_adj_tiles(prony_handle_t h, const AdjPlan& P, const pair_t<T>* zp, const pair_t<T>* wp,
+                                const int* gt, double2* gf) {
+    ProfileScope prof(h, "adjoint_tiles");
+    adjoint_tiles<T, KS><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, zp, wp, gt, gf);
+    return PRONY_OK;
+}
+
+template <typename T>
+prony_status_t launch_adjoint(prony_handle_t h, const AdjPlan& P, const double* U, int64_t u_rs, int64_t u_cs,
+                              const double* sigma, const double* V, int64_t v_rs, int64_t v_cs, const double* gS,
+                              double* gf) {
+    using T2 = pair_t<T>;
+    prony_status_t st = ensure_workspace(h, P.ws_bytes);
+    if (st != PRONY_OK) return st;
+    unsigned char* ws = static_cast<unsigned char*>(h->ws);
+    T2* zp = reinterpret_cast<T2*>(ws + P.off_z);
+    T2* wp = reinterpret_cast<T2*>(ws + P.off_w);
+    int* gt = reinterpret_cast<int*>(ws + P.off_g);
+    const int64_t largest = std::max<int64_t>({(int64_t)P.rt * kRows * P.cp, (int64_t)P.cp * 2 * P.sk * P.kc,
+                                               (int64_t)P.gsize});
+    const int blocks = (int)std::min<int64_t>((largest + 255) / 256, 2 * (int64_t)h->num_cus);
+    {
+        ProfileScope prof(h, "adjoint_pack");
+        adjoint_pack<T><<<dim3(blocks, 3), 256, 0, h->stream>>>(
+            P, reinterpret_cast<const double2*>(U), u_rs, u_cs, sigma, reinterpret_cast<const double2*>(V), v_rs,
+            v_cs, reinterpret_cast<const double2*>(gS), zp, wp, gt, reinterpret_cast<double2*>(gf));
+    }
+    if ((st = check_launch(h, "adjoint_pack")) != PRONY_OK) return st;
+    double2* g2 = reinterpret_cast<double2*>(gf);
+    switch (P.ksteps) {
+#define PRONY_ADJ_CASE(K) \
+    case K:               \
+        st = launch_adj_tiles<T, K>(h, P, zp, wp, gt, g2); \
+        break;
+        PRONY_ADJ_CASE(2)
+        PRONY_ADJ_CASE(4)
+        PRONY_ADJ_CASE(6)
+        PRONY_ADJ_CASE(8)
+        PRONY_ADJ_CASE(10)
+        PRONY_ADJ_CASE(12)
+        PRONY_ADJ_CASE(14)
+        PRONY_ADJ_CASE(16)
+        PRONY_ADJ_CASE(18)
+        PRONY_ADJ_CASE(20)
+        PRONY_ADJ_CASE(22)
+        PRONY_ADJ_CASE(24)
+#undef PRONY_ADJ_CASE
+        default:
+            return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint: d*m too large");
+    }
+    if (st != PRONY_OK) return st;
+    return check_launch(h, "adjoint_tiles");
+}
+
+}  // namespace
+}  // namespace prony
+
+using namespace prony;
+
+extern "C" prony_status_t prony_build_S_adjoint(prony_handle_t h, int d, int n, int m, const double* U,
+                                                int64_t u_rs, int64_t u_cs, const double* sigma, const double* V,
+                                                int64_t v_rs, int64_t v_cs, const double* gS, prony_prec_t prec,
+                                                double* gf) {
+    if (!h) return PRONY_EINVAL;
+    prony_status_t st = check_dn(h, d, n);
+    if (st != PRONY_OK) return st;
+    const int64_t N = ipow(n + 1, d);
+    if (m < 1 || m > N) return fail(h, PRONY_EINVAL, "prony_build_S_adjoint: m must be in 1..N");
+    if (m > 32) return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint: m > 32 is not supported");
+    if (!U || !V || !sigma || !gS || !gf) return fail(h, PRONY_EINVAL, "prony_build_S_adjoint: null pointer");
+    if (u_rs < 1 || u_cs < 1 || v_rs < 1 || v_cs < 1)
+        return fail(h, PRONY_EINVAL, "prony_build_S_adjoint: strides must be >= 1");
+    if ((N - 1) * u_rs + (m - 1) * u_cs >= (int64_t(1) << 40) || (N - 1) * v_rs + (m - 1) * v_cs >= (int64_t(1) << 40))
+        return fail(h, PRONY_EINVAL, "prony_build_S_adjoint: strides out of range");
+    if (prec != PRONY_FP64 && prec != PRONY_FP32) return fail(h, PRONY_EINVAL, "prony_build_S_adjoint: bad precision");
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    AdjPlan P;
+    if (prec == PRONY_FP32) {
+        if ((st = make_adj_plan(h, d, n, m, sizeof(float), P)) != PRONY_OK) return st;
+        return launch_adjoint<float>(h, P, U, u_rs, u_cs, sigma, V, v_rs, v_cs, gS, gf);
+    }
+    if ((st = make_adj_plan(h, d, n, m, sizeof(double), P)) != PRONY_OK) return st;
+    return launch_adjoint<double>(h, P, U, u_rs, u_cs, sigma, V, v_rs, v_cs, gS, gf);
+}

@@ -23,9 +23,13 @@
 //                 FP64 (no separate reduction launch).
 #include <algorithm>
 #include <cmath>
+#include <new>
+#include <string>
 #include <type_traits>
+#include <vector>
 
 #include "common.h"
+#include "mfma.h"
 
 namespace prony {
 namespace {
@@ -34,39 +38,6 @@ constexpr int kWaves = 4;               // waves per workgroup
 constexpr int kRowsPerWave = 16;        // MFMA M dimension
 constexpr int kRowsPerTile = kWaves * kRowsPerWave;
 constexpr int kThreads = kWaves * 64;
-
-template <typename T>
-struct Pair;
-template <>
-struct Pair<float> {
-    using type = float2;
-};
-template <>
-struct Pair<double> {
-    using type = double2;
-};
-template <typename T>
-using pair_t = typename Pair<T>::type;
-
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<float> {
-    typedef float acc_t __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc_t fma(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    // Row of the 16x16 result held in accumulator element r by lanes 16g..16g+15.
-    static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
-};
-template <>
-struct Mfma<double> {
-    typedef double acc_t __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc_t fma(double a, double b, acc_t c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
-};
 
 // The K loop keeps operands of kDepth K steps (4 h' each) in flight; it reads
 // up to kPrefetchRows h' past the end of a chunk (packed rows padded with zeros,
@@ -90,24 +61,12 @@ struct PencilPlan {
     int win_cap;    // window capacity (complex elements)
     int c0;         // grid offset of the origin shift
     int gs;         // workgroups per first-level reduction group
-    int ngroups;    // first-level groups
+    int ngroups;    // nodes of the reduction tree above the leaves
     size_t lds_bytes;
     // workspace offsets (bytes)
     size_t off_v, off_u, off_g, off_p, off_gp, ws_bytes;
 };
 
-// Grid offset of the extended index h' (row-major over {-1..n}^d).
-__host__ __device__ inline int ext_offset(int hx, int d, int n) {
-    const int E = n + 2, Q = 2 * n + 2;
-    int g = 0, scale = 1;
-    for (int l = d - 1; l >= 0; --l) {
-        const int q = hx / E;
-        g += (hx - q * E - 1) * scale;
-        hx = q;
-        scale *= Q;
-    }
-    return g;
-}
 
 // Packs, per call: (y = 0) the stacked shifted factors V_l in the pair layout,
 // rows h' of the extended index set padded with zeros to sk*kc + kPrefetchRows;
@@ -115,15 +74,15 @@ __host__ __device__ inline int ext_offset(int hx, int d, int n) {
 // columns to 16*mbi; (y = 2) the grid offsets G(h') and the zeroed reduction
 // counters. All index arithmetic fits in 32 bits (checked by the host plan).
 template <typename T>
-__global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* __restrict__ U, int64_t u_rs,
-                                                   int64_t u_cs, const double2* __restrict__ V, int64_t v_rs,
-                                                   int64_t v_cs, pair_t<T>* __restrict__ vp, pair_t<T>* __restrict__ up,
-                                                   int* __restrict__ gt, unsigned* __restrict__ counters) {
+__device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __restrict__ U, int64_t u_rs,
+                                          int64_t u_cs, const double2* __restrict__ V, int64_t v_rs, int64_t v_cs,
+                                          pair_t<T>* __restrict__ vp, pair_t<T>* __restrict__ up,
+                                          int* __restrict__ gt, unsigned* __restrict__ counters, int section) {
     using T2 = pair_t<T>;
     const int kbp = P.sk * P.kc + kPrefetchRows;
     const int stride = gridDim.x * blockDim.x;
     const int first = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.y == 0) {
+    if (section == 0) {
         const int E = P.n + 2, Pn = P.n + 1;
         const int nv = kbp * P.nrp;
         for (int i = first; i < nv; i += stride) {
@@ -153,7 +112,7 @@ __global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* 
             // (Re a) multiplies the first member, (Im a) the second.
             vp[i] = (j & 1) ? T2{(T)vi, (T)vr} : T2{(T)vr, (T)(-vi)};
         }
-    } else if (blockIdx.y == 1) {
+    } else if (section == 1) {
         const int mup = P.mbi * 16;
         const int nu = P.rt * kRowsPerTile * mup;
         for (int r = first; r < nu; r += stride) {
@@ -173,17 +132,77 @@ __global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* 
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* __restrict__ U, int64_t u_rs,
+                                                   int64_t u_cs, const double2* __restrict__ V, int64_t v_rs,
+                                                   int64_t v_cs, pair_t<T>* __restrict__ vp, pair_t<T>* __restrict__ up,
+                                                   int* __restrict__ gt, unsigned* __restrict__ counters) {
+    pack_body<T>(P, U, u_rs, u_cs, V, v_rs, v_cs, vp, up, gt, counters, blockIdx.y);
+}
 
+
+// Fan-in of the partial-sum tree of prony_build_S.
+constexpr int kFanIn = 16;
+
+// Sum of rows [beg, end) (at most kFanIn) of a row-major array of `tot` pairs,
+// column o, in FP64 and row order; all loads are issued before the additions.
+template <typename P2>
+__device__ __forceinline__ void sum_rows(const P2* __restrict__ src, int tot, int beg, int end, int o, double& re,
+                                         double& im) {
+    P2 v[kFanIn];
+#pragma unroll
+    for (int u = 0; u < kFanIn; ++u)
+        if (beg + u < end) v[u] = src[(size_t)(beg + u) * tot + o];
+    re = 0.0;
+    im = 0.0;
+#pragma unroll
+    for (int u = 0; u < kFanIn; ++u)
+        if (beg + u < end) {
+            re += (double)v[u].x;
+            im += (double)v[u].y;
+        }
+}
+
+// Output o = i*C + c of the summed m x (ells m) block: S_l(i, q) = sum / sigma_q.
+__device__ __forceinline__ void store_s(const PencilPlan& P, const double* __restrict__ sigma,
+                                        double2* __restrict__ S, int o, double re, double im) {
+    const int i = o / P.C, c = o - (o / P.C) * P.C;
+    const int li = c / P.m, q = c - li * P.m;
+    const double sq = sigma[q];
+    S[((size_t)li * P.m + i) * P.m + q] = make_double2(re / sq, im / sq);
+}
+
+// Device pointers of one S-build: inputs, packed operands and reduction scratch.
+template <typename T>
+struct TilePtrs {
+    const double2* grid;
+    const pair_t<T>* vp;
+    const pair_t<T>* up;
+    const int* gtab;
+    pair_t<T>* part;
+    double2* gpart;
+    unsigned* counters;
+    const double* sigma;
+    double2* S;
+};
+
+// One workgroup tile of the S-build: rows 64 rt_i .. +63 of I_n against chunk
+// sk_i of the extended indices h', where L = sk_i * rt + rt_i. See the file
+// comment for the formulation.
 template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const double2* __restrict__ grid,
-                                                         const pair_t<T>* __restrict__ vp,
-                                                         const pair_t<T>* __restrict__ up,
-                                                         const int* __restrict__ gtab, pair_t<T>* __restrict__ part,
-                                                         double2* __restrict__ gpart, unsigned* __restrict__ counters,
-                                                         const double* __restrict__ sigma, double2* __restrict__ S) {
+__device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>& ptr, const int L) {
     using T2 = pair_t<T>;
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
+    const double2* __restrict__ grid = ptr.grid;
+    const T2* __restrict__ vp = ptr.vp;
+    const T2* __restrict__ up = ptr.up;
+    const int* __restrict__ gtab = ptr.gtab;
+    T2* __restrict__ part = ptr.part;
+    double2* __restrict__ gpart = ptr.gpart;
+    unsigned* __restrict__ counters = ptr.counters;
+    const double* __restrict__ sigma = ptr.sigma;
+    double2* __restrict__ S = ptr.S;
     extern __shared__ __align__(16) unsigned char smem[];
     // Phase 1 (K loop): grid window + h' offsets. Phase 2 (U^* reduction): the
     // same bytes hold the per-workgroup sum of the wave results.
@@ -196,11 +215,6 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const dou
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, col = lane & 15;
     const bool odd = lane & 1;
-
-    // Workgroups are dealt to the 8 XCDs round-robin; map consecutive ids of one
-    // XCD to the same chunk of h' so that its packed V rows stay in that L2.
-    const int id = blockIdx.x;
-    const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
     const int sk_i = L / P.rt, rt_i = L - (L / P.rt) * P.rt;
 
     const int k_first = rt_i * kRowsPerTile;
@@ -327,49 +341,101 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, const dou
         out[o] = T2{esum[i * P.nrp + 2 * c], esum[i * P.nrp + 2 * c + 1]};
     }
 
-    // Deterministic two-level reduction of the workgroup partials: the last
-    // workgroup to finish in a group of P.gs sums that group's partials in slot
-    // order; the last group to finish sums the group results in order and
-    // applies Sigma^{-1}. Release/acquire fences make the partials written on
-    // other XCDs visible; counters return to zero for the next launch.
-    __threadfence();
+    // Deterministic tree reduction of the workgroup partials with fan-in kFanIn:
+    // the last workgroup to finish in a group sums that group's rows in slot
+    // order (FP64) into the next level; the last workgroup of the top level
+    // applies Sigma^{-1} and writes S. Release/acquire fences make rows written
+    // on other XCDs visible; every counter returns to zero before the launch ends.
     __syncthreads();
-    const int grp = L / P.gs;
-    const int s_begin = grp * P.gs;
-    const int s_end = min(s_begin + P.gs, P.nwg);
-    if (tid == 0) s_last = atomicAdd(&counters[grp], 1u) == (unsigned)(s_end - s_begin - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    for (int o = tid; o < tot; o += kThreads) {
-        double re = 0.0, im = 0.0;
-        for (int s2 = s_begin; s2 < s_end; ++s2) {
-            const T2 v = part[(size_t)s2 * tot + o];
-            re += (double)v.x;
-            im += (double)v.y;
+    if (P.nwg == 1) {
+        for (int o = tid; o < tot; o += kThreads) {
+            const int i = o / P.C, c = o - (o / P.C) * P.C;
+            store_s(P, sigma, S, o, (double)esum[i * P.nrp + 2 * c], (double)esum[i * P.nrp + 2 * c + 1]);
         }
-        gpart[(size_t)grp * tot + o] = make_double2(re, im);
+        return;
     }
-    if (tid == 0) counters[grp] = 0u;
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&counters[P.ngroups], 1u) == (unsigned)(P.ngroups - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    for (int o = tid; o < tot; o += kThreads) {
-        double re = 0.0, im = 0.0;
-        for (int q2 = 0; q2 < P.ngroups; ++q2) {
-            const double2 v = gpart[(size_t)q2 * tot + o];
-            re += v.x;
-            im += v.y;
+    int count = P.nwg, slot = L, cbase = 0, rbase = 0;
+    bool first_level = true;
+    for (;;) {
+        __threadfence();
+        __syncthreads();
+        const int grp = slot / kFanIn;
+        const int beg = grp * kFanIn;
+        const int end = min(beg + kFanIn, count);
+        if (tid == 0) s_last = atomicAdd(&counters[cbase + grp], 1u) == (unsigned)(end - beg - 1);
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        const int groups = (count + kFanIn - 1) / kFanIn;
+        double2* dst = gpart + (size_t)(rbase + grp) * tot;
+        for (int o = tid; o < tot; o += kThreads) {
+            double re, im;
+            if (first_level)
+                sum_rows(part, tot, beg, end, o, re, im);
+            else
+                sum_rows(gpart + (size_t)(rbase - count) * tot, tot, beg, end, o, re, im);
+            if (groups == 1)
+                store_s(P, sigma, S, o, re, im);
+            else
+                dst[o] = make_double2(re, im);
         }
-        const int i = o / P.C, c = o - (o / P.C) * P.C;
-        const int li = c / P.m, q = c - li * P.m;
-        const double sq = sigma[q];
-        S[((size_t)li * P.m + i) * P.m + q] = make_double2(re / sq, im / sq);
+        if (tid == 0) counters[cbase + grp] = 0u;
+        if (groups == 1) return;
+        cbase += groups;
+        rbase += groups;
+        count = groups;
+        slot = grp;
+        first_level = false;
     }
-    if (tid == 0) counters[P.ngroups] = 0u;
+}
+
+// Single-instance launch: one workgroup per tile. Workgroups are dealt to the
+// 8 XCDs round-robin; consecutive ids of one XCD get the same chunk of h' so
+// that its packed rows stay in that XCD's L2.
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, TilePtrs<T> ptr) {
+    const int id = blockIdx.x;
+    const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
+    tile_body<T, NB>(P, ptr, L);
+}
+
+// One instance of a batch: its plan, its pointers and the first global tile
+// index of the instance within its launch.
+template <typename T>
+struct BatchEntry {
+    PencilPlan P;
+    TilePtrs<T> ptr;
+    const double2* U;
+    const double2* V;
+    int tile_begin;
+};
+
+// Packing for every instance of a batch: grid (x, 3, instances).
+template <typename T>
+__global__ __launch_bounds__(256) void pencil_pack_batched(const BatchEntry<T>* __restrict__ entries) {
+    const BatchEntry<T>& e = entries[blockIdx.z];
+    pack_body<T>(e.P, e.U, e.P.m, 1, e.V, e.P.m, 1, const_cast<pair_t<T>*>(e.ptr.vp),
+                 const_cast<pair_t<T>*>(e.ptr.up), const_cast<int*>(e.ptr.gtab), e.ptr.counters, blockIdx.y);
+}
+
+// Batched launch over the instances of one column-block class, ordered by
+// decreasing work: workgroup `id` finds its instance by binary search over the
+// tile offsets (the hardware dispatches workgroups in id order, so the longest
+// tiles start first).
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntry<T>* __restrict__ entries,
+                                                                 int count) {
+    const int id = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (entries[mid].tile_begin <= id)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchEntry<T>& e = entries[lo];
+    tile_body<T, NB>(e.P, e.ptr, id - e.tile_begin);
 }
 
 size_t lds_bytes_for(int win, int kc, int mbi, int nrp, size_t tsize) {
@@ -391,7 +457,11 @@ int max_span(int count, int len, int d, int n, bool ext) {
     return best;
 }
 
-prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P) {
+// target_wgs: workgroups the split of the h' range aims at (single instances
+// fill the GPU with one launch; batch members use target 1, i.e. no split
+// beyond what the LDS window imposes).
+prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P,
+                         int target_wgs = 0) {
     P = PencilPlan{};
     P.d = d;
     P.n = n;
@@ -408,7 +478,7 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.c0 = grid_center(d, n);
 
     const size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
-    const int target = 4 * h->num_cus;
+    const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
     int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), 16);
     kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, 16)));
@@ -431,8 +501,11 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     if (((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp >= (int64_t(1) << 31) ||
         (int64_t)P.nwg * P.m * P.C >= (int64_t(1) << 31))
         return fail(h, PRONY_ENOTSUP, "prony_build_S: problem too large for 32-bit tile indexing");
-    P.gs = std::max(1, (int)std::ceil(std::sqrt((double)P.nwg)));
-    P.ngroups = (P.nwg + P.gs - 1) / P.gs;
+    // reduction tree: gs = fan-in, ngroups = nodes above the leaves (rows of
+    // gpart and counters used)
+    P.gs = kFanIn;
+    P.ngroups = 0;
+    for (int c = P.nwg; c > 1; c = (c + kFanIn - 1) / kFanIn) P.ngroups += (c + kFanIn - 1) / kFanIn;
     const size_t t2 = 2 * tsize;
     const size_t tot = (size_t)P.m * P.C;
     size_t off = 0;
@@ -452,48 +525,56 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
 }
 
 template <typename T, int NB>
-prony_status_t launch_tiles(prony_handle_t h, const PencilPlan& P, const double2* grid, const pair_t<T>* vp,
-                            const pair_t<T>* up, const int* gt, pair_t<T>* part, double2* gpart, unsigned* counters,
-                            const double* sigma, double2* S) {
+prony_status_t launch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
     if (P.lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, NB>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
         if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
     }
     ProfileScope prof(h, "pencil_tiles");
-    pencil_tiles<T, NB><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, grid, vp, up, gt, part, gpart, counters,
-                                                                      sigma, S);
+    pencil_tiles<T, NB><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
     return PRONY_OK;
 }
 
+template <typename T, int NB>
+prony_status_t launch_batched(prony_handle_t h, const BatchEntry<T>* entries, int count, int tiles, size_t lds) {
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles_batched<T, NB>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+    }
+    ProfileScope prof(h, "pencil_tiles_batched");
+    pencil_tiles_batched<T, NB><<<tiles, kThreads, lds, h->stream>>>(entries, count);
+    return PRONY_OK;
+}
+
+#define PRONY_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
 template <typename T>
-prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const double2* grid, const pair_t<T>* vp,
-                              const pair_t<T>* up, const int* gt, pair_t<T>* part, double2* gpart,
-                              unsigned* counters, const double* sigma, double2* S) {
-#define PRONY_TILES_CASE(NBV) \
-    case NBV:                 \
-        return launch_tiles<T, NBV>(h, P, grid, vp, up, gt, part, gpart, counters, sigma, S);
+prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
     switch (P.nb) {
-        PRONY_TILES_CASE(1)
-        PRONY_TILES_CASE(2)
-        PRONY_TILES_CASE(3)
-        PRONY_TILES_CASE(4)
-        PRONY_TILES_CASE(5)
-        PRONY_TILES_CASE(6)
-        PRONY_TILES_CASE(7)
-        PRONY_TILES_CASE(8)
-        PRONY_TILES_CASE(9)
-        PRONY_TILES_CASE(10)
-        PRONY_TILES_CASE(11)
-        PRONY_TILES_CASE(12)
-        PRONY_TILES_CASE(13)
-        PRONY_TILES_CASE(14)
-        PRONY_TILES_CASE(15)
-        PRONY_TILES_CASE(16)
+#define PRONY_CASE(NBV) \
+    case NBV:           \
+        return launch_tiles<T, NBV>(h, P, ptr);
+        PRONY_NB_CASES(PRONY_CASE)
+#undef PRONY_CASE
         default:
             return fail(h, PRONY_ENOTSUP, "prony_build_S: too many columns");
     }
-#undef PRONY_TILES_CASE
+}
+
+template <typename T>
+prony_status_t dispatch_batched(prony_handle_t h, int nb, const BatchEntry<T>* entries, int count, int tiles,
+                                size_t lds) {
+    switch (nb) {
+#define PRONY_CASE(NBV) \
+    case NBV:           \
+        return launch_batched<T, NBV>(h, entries, count, tiles, lds);
+        PRONY_NB_CASES(PRONY_CASE)
+#undef PRONY_CASE
+        default:
+            return fail(h, PRONY_ENOTSUP, "prony_build_S_batched: too many columns");
+    }
 }
 
 template <typename T>
@@ -521,8 +602,9 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, const double
             up, gt, counters);
     }
     if ((st = check_launch(h, "pencil_pack")) != PRONY_OK) return st;
-    st = dispatch_tiles<T>(h, P, reinterpret_cast<const double2*>(f), vp, up, gt, part, gpart, counters, sigma,
-                           reinterpret_cast<double2*>(S));
+    const TilePtrs<T> ptr{reinterpret_cast<const double2*>(f), vp, up, gt, part, gpart, counters, sigma,
+                          reinterpret_cast<double2*>(S)};
+    st = dispatch_tiles<T>(h, P, ptr);
     if (st != PRONY_OK) return st;
     return check_launch(h, "pencil_tiles");
 }
@@ -588,4 +670,262 @@ extern "C" prony_status_t prony_reserve(prony_handle_t h, int d_max, int n_max, 
         need = std::max(need, coeffs_workspace_bytes(d, n_max, m));
     }
     return ensure_workspace(h, need);
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+struct prony_batch_s {
+    prony_handle_t owner = nullptr;
+    int count = 0;
+    prony_prec_t prec = PRONY_FP64;
+    void* ws = nullptr;           // entries + per-instance operands and scratch
+    size_t ws_bytes = 0;
+    void* entries = nullptr;      // device BatchEntry<T>[count], grouped by class
+    int pack_x = 1;               // pack blocks per (instance, section)
+    struct ClassLaunch {
+        int nb, first, count, tiles;
+        size_t lds;
+    };
+    std::vector<ClassLaunch> launches;
+};
+
+namespace prony {
+namespace {
+
+template <typename T>
+prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* inst, prony_batch_s* B) {
+    using T2 = pair_t<T>;
+    std::vector<PencilPlan> plans(count);
+    for (int i = 0; i < count; ++i) {
+        const prony_instance_t& x = inst[i];
+        const std::string who = "instance " + std::to_string(i) + ": ";
+        if (x.d < 1 || x.d > 3 || x.n < 1) return fail(h, PRONY_EINVAL, who + "bad d or n");
+        if (ipow(2 * (int64_t)x.n + 2, x.d) > (int64_t(1) << 30))
+            return fail(h, PRONY_ENOTSUP, who + "sample grid larger than 2^30 points");
+        const int64_t N = ipow(x.n + 1, x.d);
+        if (x.m < 1 || x.m > N) return fail(h, PRONY_EINVAL, who + "m must be in 1..N");
+        if (x.m > 32) return fail(h, PRONY_ENOTSUP, who + "m > 32 is not supported");
+        if (!x.f || !x.U || !x.sigma || !x.V || !x.S) return fail(h, PRONY_EINVAL, who + "null pointer");
+        prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], 1);
+        if (st != PRONY_OK) return fail(h, st, who + h->err);
+    }
+    // classes by column-block count; inside a class, longest tiles first
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (plans[a].nb != plans[b].nb) return plans[a].nb < plans[b].nb;
+        return (int64_t)plans[a].kc > (int64_t)plans[b].kc;
+    });
+    // workspace layout: entries, then per instance vp | up | gt | part | gpart | counters
+    const size_t t2 = 2 * sizeof(T);
+    size_t off = align_up(sizeof(BatchEntry<T>) * (size_t)count, 256);
+    std::vector<BatchEntry<T>> host(count);
+    std::vector<size_t> base(count);
+    for (int pos = 0; pos < count; ++pos) {
+        const PencilPlan& P = plans[order[pos]];
+        base[pos] = off;
+        const size_t tot = (size_t)P.m * P.C;
+        off = align_up(off + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
+        off = align_up(off + t2 * (size_t)P.rt * kRowsPerTile * P.mbi * 16, 256);
+        off = align_up(off + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
+        off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
+        off = align_up(off + sizeof(double2) * (size_t)P.ngroups * tot, 256);
+        off = align_up(off + sizeof(unsigned) * ((size_t)P.ngroups + 1), 256);
+    }
+    void* ws = nullptr;
+    hipError_t e = hipMalloc(&ws, off);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, PRONY_ENOMEM, std::string("batch workspace allocation failed: ") + hipGetErrorString(e));
+    }
+    B->ws = ws;
+    B->ws_bytes = off;
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    int first = 0;
+    int largest = 1;
+    for (int pos = 0; pos < count; ++pos) {
+        const int i = order[pos];
+        const PencilPlan& P = plans[i];
+        const prony_instance_t& x = inst[i];
+        const size_t tot = (size_t)P.m * P.C;
+        size_t o = base[pos];
+        BatchEntry<T>& E = host[pos];
+        E.P = P;
+        E.ptr.grid = reinterpret_cast<const double2*>(x.f);
+        E.ptr.vp = reinterpret_cast<const T2*>(w + o);
+        o = align_up(o + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
+        E.ptr.up = reinterpret_cast<const T2*>(w + o);
+        o = align_up(o + t2 * (size_t)P.rt * kRowsPerTile * P.mbi * 16, 256);
+        E.ptr.gtab = reinterpret_cast<const int*>(w + o);
+        o = align_up(o + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
+        E.ptr.part = reinterpret_cast<T2*>(w + o);
+        o = align_up(o + t2 * (size_t)P.nwg * tot, 256);
+        E.ptr.gpart = reinterpret_cast<double2*>(w + o);
+        o = align_up(o + sizeof(double2) * (size_t)P.ngroups * tot, 256);
+        E.ptr.counters = reinterpret_cast<unsigned*>(w + o);
+        E.ptr.sigma = x.sigma;
+        E.ptr.S = reinterpret_cast<double2*>(x.S);
+        E.U = reinterpret_cast<const double2*>(x.U);
+        E.V = reinterpret_cast<const double2*>(x.V);
+        const bool new_class = pos == 0 || plans[order[pos - 1]].nb != P.nb;
+        if (new_class) {
+            B->launches.push_back({P.nb, pos, 0, 0, 0});
+            first = 0;
+        }
+        auto& cl = B->launches.back();
+        E.tile_begin = first;
+        first += P.nwg;
+        cl.count += 1;
+        cl.tiles = first;
+        cl.lds = std::max(cl.lds, P.lds_bytes);
+        const int64_t big = std::max<int64_t>(((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp,
+                                              (int64_t)P.rt * kRowsPerTile * P.mbi * 16);
+        largest = (int)std::max<int64_t>(largest, (big + 255) / 256);
+    }
+    B->pack_x = std::min(largest, 64);
+    B->entries = ws;
+    e = hipMemcpyAsync(ws, host.data(), sizeof(BatchEntry<T>) * (size_t)count, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "batch work table upload");
+    return PRONY_OK;
+}
+
+template <typename T>
+prony_status_t batch_launch(prony_handle_t h, prony_batch_s* B) {
+    const BatchEntry<T>* entries = static_cast<const BatchEntry<T>*>(B->entries);
+    {
+        ProfileScope prof(h, "pencil_pack");
+        pencil_pack_batched<T><<<dim3(B->pack_x, 3, B->count), 256, 0, h->stream>>>(entries);
+    }
+    prony_status_t st = check_launch(h, "pencil_pack_batched");
+    if (st != PRONY_OK) return st;
+    for (const auto& cl : B->launches) {
+        st = dispatch_batched<T>(h, cl.nb, entries + cl.first, cl.count, cl.tiles, cl.lds);
+        if (st != PRONY_OK) return st;
+        if ((st = check_launch(h, "pencil_tiles_batched")) != PRONY_OK) return st;
+    }
+    return PRONY_OK;
+}
+
+}  // namespace
+}  // namespace prony
+
+extern "C" prony_status_t prony_batch_create(prony_handle_t h, int count, const prony_instance_t* instances,
+                                             prony_prec_t prec, prony_batch_t* batch) {
+    if (!h || !batch) return PRONY_EINVAL;
+    *batch = nullptr;
+    if (count < 1 || count > 65535 || !instances)
+        return fail(h, PRONY_EINVAL, "prony_batch_create: count must be in 1..65535");
+    if (prec != PRONY_FP64 && prec != PRONY_FP32) return fail(h, PRONY_EINVAL, "prony_batch_create: bad precision");
+    if (h->device < 0) {
+        // validate only
+        for (int i = 0; i < count; ++i) {
+            const prony_instance_t& x = instances[i];
+            const std::string who = "instance " + std::to_string(i) + ": ";
+            if (x.d < 1 || x.d > 3 || x.n < 1) return fail(h, PRONY_EINVAL, who + "bad d or n");
+            const int64_t N = ipow(x.n + 1, x.d);
+            if (x.m < 1 || x.m > N) return fail(h, PRONY_EINVAL, who + "m must be in 1..N");
+            if (x.m > 32) return fail(h, PRONY_ENOTSUP, who + "m > 32 is not supported");
+            if (!x.f || !x.U || !x.sigma || !x.V || !x.S) return fail(h, PRONY_EINVAL, who + "null pointer");
+        }
+        return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    }
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    prony_batch_s* B = new (std::nothrow) prony_batch_s();
+    if (!B) return fail(h, PRONY_ENOMEM, "prony_batch_create: out of host memory");
+    B->owner = h;
+    B->count = count;
+    B->prec = prec;
+    const prony_status_t st = prec == PRONY_FP32 ? batch_build<float>(h, count, instances, B)
+                                                 : batch_build<double>(h, count, instances, B);
+    if (st != PRONY_OK) {
+        if (B->ws) (void)hipFree(B->ws);
+        delete B;
+        return st;
+    }
+    *batch = B;
+    return PRONY_OK;
+}
+
+extern "C" prony_status_t prony_batch_destroy(prony_batch_t B) {
+    if (!B) return PRONY_EINVAL;
+    prony_status_t st = PRONY_OK;
+    if (B->ws) {
+        DeviceGuard g(B->owner->device);
+        if (hipStreamSynchronize(B->owner->stream) != hipSuccess) st = PRONY_EHIP;
+        if (hipFree(B->ws) != hipSuccess) st = PRONY_EHIP;
+    }
+    delete B;
+    return st;
+}
+
+extern "C" prony_status_t prony_build_S_batched(prony_handle_t h, prony_batch_t B) {
+    if (!h || !B) return PRONY_EINVAL;
+    if (B->owner != h) return fail(h, PRONY_EINVAL, "prony_build_S_batched: batch belongs to another handle");
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    return B->prec == PRONY_FP32 ? batch_launch<float>(h, B) : batch_launch<double>(h, B);
+}
+
+extern "C" prony_status_t prony_graph_capture(prony_handle_t h, prony_batch_t B, void** graph_exec) {
+    if (!h || !B || !graph_exec) return PRONY_EINVAL;
+    *graph_exec = nullptr;
+    if (B->owner != h) return fail(h, PRONY_EINVAL, "prony_graph_capture: batch belongs to another handle");
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamCreateWithFlags");
+    // the captured stream must first see everything already queued on the handle's stream
+    hipStream_t user = h->stream;
+    e = hipStreamSynchronize(user);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return hip_fail(h, e, "hipStreamSynchronize");
+    }
+    const std::string saved_prof = h->prof_kernel;
+    h->prof_kernel.clear();     // no event records inside the graph
+    h->stream = cap;
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    prony_status_t st = PRONY_OK;
+    if (e != hipSuccess) {
+        st = hip_fail(h, e, "hipStreamBeginCapture");
+    } else {
+        st = prony_build_S_batched(h, B);
+        hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (st == PRONY_OK && e2 != hipSuccess) st = hip_fail(h, e2, "hipStreamEndCapture");
+    }
+    h->stream = user;
+    h->prof_kernel = saved_prof;
+    (void)hipStreamDestroy(cap);
+    if (st != PRONY_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGraphInstantiate");
+    *graph_exec = exec;
+    return PRONY_OK;
+}
+
+extern "C" prony_status_t prony_graph_launch(prony_handle_t h, void* graph_exec) {
+    if (!h || !graph_exec) return PRONY_EINVAL;
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    hipError_t e = hipGraphLaunch(static_cast<hipGraphExec_t>(graph_exec), h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
+    return PRONY_OK;
+}
+
+extern "C" prony_status_t prony_graph_destroy(void* graph_exec) {
+    if (!graph_exec) return PRONY_EINVAL;
+    return hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec)) == hipSuccess ? PRONY_OK : PRONY_EHIP;
 }

@@ -100,3 +100,36 @@ def test_null_handle_and_error_text():
     assert lib.prony_build_S(NULL, 2, 15, 5, P, P, 5, 1, P, P, 5, 1, 0, 0, P) == _lib.PRONY_EINVAL
     assert lib.prony_last_error(NULL) == b"invalid handle"
     assert lib.prony_create(None, 0) == _lib.PRONY_EINVAL
+
+
+def _desc(d, n, m, ptr=P):
+    return _lib.InstanceDesc(d, n, m, ptr.value, ptr.value, ptr.value, ptr.value, ptr.value)
+
+
+def test_batch_validation(vhandle):
+    lib, h = vhandle
+    arr = (_lib.InstanceDesc * 3)(_desc(2, 15, 5), _desc(1, 100, 32), _desc(3, 3, 8))
+    out = ctypes.c_void_p()
+    assert lib.prony_batch_create(h, 3, arr, _lib.PRONY_FP32, ctypes.byref(out)) == _lib.PRONY_ENODEV
+    bad = (_lib.InstanceDesc * 3)(_desc(2, 15, 5), _desc(2, 15, 5), _desc(1, 3, 5))
+    assert lib.prony_batch_create(h, 3, bad, _lib.PRONY_FP32, ctypes.byref(out)) == _lib.PRONY_EINVAL
+    assert "instance 2" in _err(lib, h)
+    big = (_lib.InstanceDesc * 1)(_desc(2, 15, 40))
+    assert lib.prony_batch_create(h, 1, big, _lib.PRONY_FP64, ctypes.byref(out)) == _lib.PRONY_ENOTSUP
+    nul = (_lib.InstanceDesc * 1)(_desc(2, 15, 5, NULL))
+    assert lib.prony_batch_create(h, 1, nul, _lib.PRONY_FP64, ctypes.byref(out)) == _lib.PRONY_EINVAL
+    assert lib.prony_batch_create(h, 0, arr, _lib.PRONY_FP64, ctypes.byref(out)) == _lib.PRONY_EINVAL
+    assert lib.prony_batch_create(h, 3, arr, 9, ctypes.byref(out)) == _lib.PRONY_EINVAL
+    assert lib.prony_build_S_batched(h, NULL) == _lib.PRONY_EINVAL
+    assert lib.prony_graph_launch(h, NULL) == _lib.PRONY_EINVAL
+    assert lib.prony_graph_destroy(NULL) == _lib.PRONY_EINVAL
+
+
+def test_adjoint_validation(vhandle):
+    lib, h = vhandle
+    assert lib.prony_build_S_adjoint(h, 2, 47, 16, P, 16, 1, P, P, 16, 1, P, _lib.PRONY_FP32, P) == _lib.PRONY_ENODEV
+    assert lib.prony_build_S_adjoint(h, 2, 47, 33, P, 33, 1, P, P, 33, 1, P, 0, P) == _lib.PRONY_ENOTSUP
+    assert lib.prony_build_S_adjoint(h, 1, 3, 5, P, 5, 1, P, P, 5, 1, P, 0, P) == _lib.PRONY_EINVAL
+    assert lib.prony_build_S_adjoint(h, 2, 47, 16, P, 16, 1, P, P, 16, 1, NULL, 0, P) == _lib.PRONY_EINVAL
+    assert lib.prony_build_S_adjoint(h, 2, 47, 16, P, 0, 1, P, P, 16, 1, P, 0, P) == _lib.PRONY_EINVAL
+    assert lib.prony_build_S_adjoint(h, 2, 47, 16, P, 16, 1, P, P, 16, 1, P, 5, P) == _lib.PRONY_EINVAL
