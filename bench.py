@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2"])
     ap.add_argument("--cpu-sample-steps", type=int, default=3,
                     help="oracle steps timed for the CPU baseline (0 skips it)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched (c3) and adjoint (c4) measurements")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default split targets)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (a reference dispatch "
                          "of known traffic for hardware-counter calibration)")
@@ -76,7 +79,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2012_11430_amd import _lib, api, host
+    from paper_2012_11430_amd import _lib, api, autotune, host
     from workload import config_instances, random_orthonormal
 
     _lib.load()   # fails loudly when the HIP library is missing
@@ -112,6 +115,12 @@ def main():
     api.build_S(f, d, n, Ud, sd, Vd, prec="fp64", out=Sbuf)
     z, _ = host.nodes(Sbuf.cpu().numpy(), inst.mu)
     z_d = to_dev(z)
+
+    tuned = {}
+    if not args.no_tune:
+        for prec in ("fp32", "fp64"):
+            times = autotune.tune_single(dev, d, n, m, prec, reps=5)
+            tuned[prec] = min(times, key=times.get)
 
     def step(prec):
         api.samples(t_d, c_d, n, noise=noise_d, out=f)
@@ -202,13 +211,140 @@ def main():
             "flops_per_launch": tile_flops(d, N, m),
         },
         "s_build": sbuild,
+        "tuned_split_targets": tuned,
         "wall_s_timed": round(wall, 4),
     }
+    if not args.no_extra:
+        result["batched"] = batched_c3(dev, args)
+        result["adjoint"] = adjoint_c4(dev, args)
 
     if args.cpu_sample_steps > 0:
         result["cpu_baseline"] = cpu_baseline(inst, U, sig, V, z, S_out, args.cpu_sample_steps,
                                               f.cpu().numpy())
     print(json.dumps(result), flush=True)
+
+
+def _closed_form_factors(t, c, d, n):
+    """Input preparation: exact reduced SVD of the noise-free T = V_z diag(c) V_z^*
+    from V_z = Q R (host, O(N m^2))."""
+    import itertools
+
+    import numpy as np
+    ks = np.array(list(itertools.product(range(n + 1), repeat=d)), dtype=float)
+    Q, R = np.linalg.qr(np.exp(-2j * np.pi * (ks @ t.T)))
+    Ub, s, Vbh = np.linalg.svd(R @ np.diag(c) @ R.conj().T)
+    return Q @ Ub, s, Q @ Vbh.conj().T
+
+
+def batched_c3(dev, args):
+    """c3: 512 uneven instances; FP32 batched S-build replayed from a HIP graph vs
+    the plain FP64 per-instance loop. Returns instances/s and TFLOP/s."""
+    import numpy as np
+    import torch
+
+    from paper_2012_11430_amd import api, autotune
+    from workload import config_instances
+
+    insts = config_instances("c3")
+    dev_inst = []
+    flops = 0.0
+    for inst in insts:
+        U, s, V = _closed_form_factors(inst.t, inst.c, inst.d, inst.n)
+        f = api.samples(torch.from_numpy(inst.t).to(dev), torch.from_numpy(inst.c).to(dev), inst.n,
+                        noise=torch.from_numpy(inst.noise()).to(dev))
+        dev_inst.append((inst.d, inst.n, f, torch.from_numpy(U).to(dev), torch.from_numpy(s).to(dev),
+                         torch.from_numpy(V).to(dev)))
+        flops += s_flops(inst.d, inst.N, inst.m)
+    tuned = None
+    if not args.no_tune:
+        times = autotune.tune_batch(dev_inst, "fp32", reps=2)
+        tuned = min(times, key=times.get)
+    batch = api.Batch(dev_inst, prec="fp32")
+    batch.capture()
+    reps = max(3, args.steps // 4)
+    for _ in range(2):
+        batch.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        batch.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / reps
+
+    outs = [torch.empty_like(S) for S in batch.S]
+
+    def loop64():
+        for (d, n, f, U, s, V), o in zip(dev_inst, outs):
+            api.build_S(f, d, n, U, s, V, prec="fp64", out=o)
+    loop64()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        loop64()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_loop = e0.elapsed_time(e1) / reps
+    rel = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(batch.S, outs))
+    batch.close()
+    n_inst = len(insts)
+    return {
+        "workload": "c3: 512 instances, d~U{1,2,3}, N log-uniform in [64,4096], m~U{2..32}, noise 1e-7",
+        "instances_per_s_fp32_batched_graph": round(n_inst / (ms_graph * 1e-3), 1),
+        "instances_per_s_fp64_per_instance_loop": round(n_inst / (ms_loop * 1e-3), 1),
+        "speedup": round(ms_loop / ms_graph, 2),
+        "ms_fp32_graph": round(ms_graph, 4),
+        "ms_fp64_loop": round(ms_loop, 4),
+        "tflops_fp32_graph": round(flops / (ms_graph * 1e-3) / 1e12, 3),
+        "rel_err_fp32_vs_fp64": float(f"{rel:.3e}"),
+        "tuned_chunks_per_instance": tuned,
+    }
+
+
+def adjoint_c4(dev, args):
+    """c4: 64 instances (d=2, n=47, m=16); forward FP32 S-build + hand-written
+    adjoint (FP32 accumulate) through torch.autograd. Returns ms per instance."""
+    import numpy as np
+    import torch
+
+    from paper_2012_11430_amd import api
+    from paper_2012_11430_amd.autograd import pencil
+    from workload import config_instances
+
+    insts = config_instances("c4")
+    data = []
+    for inst in insts:
+        U, s, V = _closed_form_factors(inst.t, inst.c, inst.d, inst.n)
+        t_d, c_d = torch.from_numpy(inst.t).to(dev), torch.from_numpy(inst.c).to(dev)
+        clean = api.samples(t_d, c_d, inst.n)
+        noisy = api.samples(t_d, c_d, inst.n, noise=torch.from_numpy(inst.noise()).to(dev))
+        Ud, sd, Vd = torch.from_numpy(U).to(dev), torch.from_numpy(s).to(dev), torch.from_numpy(V).to(dev)
+        ref = api.build_S(clean, inst.d, inst.n, Ud, sd, Vd, prec="fp64")
+        data.append((inst, noisy, Ud, sd, Vd, ref))
+
+    def fwd_bwd():
+        for inst, noisy, Ud, sd, Vd, ref in data:
+            f = noisy.detach().requires_grad_(True)
+            S = pencil(f, inst.d, inst.n, Ud, sd, Vd, "fp32", "fp32")
+            torch.sum(torch.abs(S - ref) ** 2).backward()
+    fwd_bwd()
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fwd_bwd()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    inst = insts[0]
+    flops = len(insts) * 2 * s_flops(inst.d, inst.N, inst.m)
+    return {
+        "workload": "c4: 64 instances of d=2, n=47, m=16, noise 1e-6; L = sum_l ||S_l - S_l^ref||_F^2",
+        "ms_forward_backward_64": round(ms, 4),
+        "tflops_forward_plus_adjoint": round(flops / (ms * 1e-3) / 1e12, 3),
+    }
 
 
 def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, grid_gpu):

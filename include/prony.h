@@ -100,6 +100,17 @@ prony_status_t prony_profile_enable(prony_handle_t handle, const char* kernel);
    their count and the sum of their event-to-event times in milliseconds. */
 prony_status_t prony_profile_read(prony_handle_t handle, int* launches, double* total_ms);
 
+/* Tile selection (filled by the autotuner). prony_build_S splits the extended
+   index range {-1..n}^d of one instance into chunks so that about `target_wgs`
+   workgroups run (default 4 per compute unit). With flag PRONY_TUNE_BATCHED the
+   entry applies to instances of that shape inside batches and gives the number
+   of chunks per instance (default 1: split only as far as the LDS window
+   requires). target_wgs = 0 removes the entry.
+   Entries live in the handle. */
+#define PRONY_TUNE_BATCHED 1u
+prony_status_t prony_tune_set(prony_handle_t handle, int d, int n, int m, prony_prec_t prec, unsigned flags,
+                              int target_wgs);
+
 /* ---- Algorithm 1, GPU steps -------------------------------------------------- */
 
 /* Samples of the exponential sum (Sec. 1, eq. exp_sum), with the additive noise

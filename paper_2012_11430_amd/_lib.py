@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "PRONY_OK", 1: "PRONY_EINVAL", 2: "PRONY_ENOTSUP", 3: "PRONY_
 PRONY_FP64 = 0
 PRONY_FP32 = 1
 PRONY_WITH_S0 = 1
+PRONY_TUNE_BATCHED = 1
 
 class InstanceDesc(ctypes.Structure):
     """prony_instance_t."""
@@ -50,6 +51,7 @@ SIGNATURES = {
                        _c_int, ctypes.c_uint, _ptr], _c_int),
     "prony_coeffs": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _ptr, _ptr, _ptr], _c_int),
     "prony_profile_enable": ([_ptr, ctypes.c_char_p], _c_int),
+    "prony_tune_set": ([_ptr, _c_int, _c_int, _c_int, _c_int, ctypes.c_uint, _c_int], _c_int),
     "prony_build_S_adjoint": ([_ptr, _c_int, _c_int, _c_int, _ptr, _c_i64, _c_i64, _ptr, _ptr, _c_i64, _c_i64,
                                _ptr, _c_int, _ptr], _c_int),
     "prony_batch_create": ([_ptr, _c_int, ctypes.POINTER(InstanceDesc), _c_int, ctypes.POINTER(_ptr)], _c_int),

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "prony.h"
@@ -18,6 +20,8 @@ struct prony_handle_s {
     int num_cus = 256;
     size_t lds_per_block = 65536;
     std::string err;
+    // tuned split targets: (d, n, m, prec, batched) -> workgroups to aim at
+    std::map<std::tuple<int, int, int, int, int>, int> split_targets;
     // profiling: events around launches of one named kernel
     std::string prof_kernel;
     std::vector<hipEvent_t> prof_events;   // pool, pairs (start, stop)

@@ -30,6 +30,7 @@
 
 #include "common.h"
 #include "mfma.h"
+#include "reduce.h"
 
 namespace prony {
 namespace {
@@ -140,28 +141,6 @@ __global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* 
     pack_body<T>(P, U, u_rs, u_cs, V, v_rs, v_cs, vp, up, gt, counters, blockIdx.y);
 }
 
-
-// Fan-in of the partial-sum tree of prony_build_S.
-constexpr int kFanIn = 16;
-
-// Sum of rows [beg, end) (at most kFanIn) of a row-major array of `tot` pairs,
-// column o, in FP64 and row order; all loads are issued before the additions.
-template <typename P2>
-__device__ __forceinline__ void sum_rows(const P2* __restrict__ src, int tot, int beg, int end, int o, double& re,
-                                         double& im) {
-    P2 v[kFanIn];
-#pragma unroll
-    for (int u = 0; u < kFanIn; ++u)
-        if (beg + u < end) v[u] = src[(size_t)(beg + u) * tot + o];
-    re = 0.0;
-    im = 0.0;
-#pragma unroll
-    for (int u = 0; u < kFanIn; ++u)
-        if (beg + u < end) {
-            re += (double)v[u].x;
-            im += (double)v[u].y;
-        }
-}
 
 // Output o = i*C + c of the summed m x (ells m) block: S_l(i, q) = sum / sigma_q.
 __device__ __forceinline__ void store_s(const PencilPlan& P, const double* __restrict__ sigma,
@@ -341,11 +320,8 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         out[o] = T2{esum[i * P.nrp + 2 * c], esum[i * P.nrp + 2 * c + 1]};
     }
 
-    // Deterministic tree reduction of the workgroup partials with fan-in kFanIn:
-    // the last workgroup to finish in a group sums that group's rows in slot
-    // order (FP64) into the next level; the last workgroup of the top level
-    // applies Sigma^{-1} and writes S. Release/acquire fences make rows written
-    // on other XCDs visible; every counter returns to zero before the launch ends.
+    // Deterministic tree reduction of the workgroup partials (reduce.h); the
+    // workgroup holding the total applies Sigma^{-1} and writes S.
     __syncthreads();
     if (P.nwg == 1) {
         for (int o = tid; o < tot; o += kThreads) {
@@ -354,39 +330,8 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         }
         return;
     }
-    int count = P.nwg, slot = L, cbase = 0, rbase = 0;
-    bool first_level = true;
-    for (;;) {
-        __threadfence();
-        __syncthreads();
-        const int grp = slot / kFanIn;
-        const int beg = grp * kFanIn;
-        const int end = min(beg + kFanIn, count);
-        if (tid == 0) s_last = atomicAdd(&counters[cbase + grp], 1u) == (unsigned)(end - beg - 1);
-        __syncthreads();
-        if (!s_last) return;
-        __threadfence();
-        const int groups = (count + kFanIn - 1) / kFanIn;
-        double2* dst = gpart + (size_t)(rbase + grp) * tot;
-        for (int o = tid; o < tot; o += kThreads) {
-            double re, im;
-            if (first_level)
-                sum_rows(part, tot, beg, end, o, re, im);
-            else
-                sum_rows(gpart + (size_t)(rbase - count) * tot, tot, beg, end, o, re, im);
-            if (groups == 1)
-                store_s(P, sigma, S, o, re, im);
-            else
-                dst[o] = make_double2(re, im);
-        }
-        if (tid == 0) counters[cbase + grp] = 0u;
-        if (groups == 1) return;
-        cbase += groups;
-        rbase += groups;
-        count = groups;
-        slot = grp;
-        first_level = false;
-    }
+    tree_reduce<kThreads>(part, gpart, counters, P.nwg, L, tot, &s_last,
+                          [&](int o, double re, double im) { store_s(P, sigma, S, o, re, im); });
 }
 
 // Single-instance launch: one workgroup per tile. Workgroups are dealt to the
@@ -457,6 +402,12 @@ int max_span(int count, int len, int d, int n, bool ext) {
     return best;
 }
 
+// Registered split target for a shape class (0 if none).
+int tuned_target(prony_handle_t h, int d, int n, int m, int prec, int batched) {
+    auto it = h->split_targets.find(std::make_tuple(d, n, m, prec, batched));
+    return it == h->split_targets.end() ? 0 : it->second;
+}
+
 // target_wgs: workgroups the split of the h' range aims at (single instances
 // fill the GPU with one launch; batch members use target 1, i.e. no split
 // beyond what the LDS window imposes).
@@ -504,8 +455,7 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     // reduction tree: gs = fan-in, ngroups = nodes above the leaves (rows of
     // gpart and counters used)
     P.gs = kFanIn;
-    P.ngroups = 0;
-    for (int c = P.nwg; c > 1; c = (c + kFanIn - 1) / kFanIn) P.ngroups += (c + kFanIn - 1) / kFanIn;
+    P.ngroups = tree_nodes(P.nwg);
     const size_t t2 = 2 * tsize;
     const size_t tot = (size_t)P.m * P.C;
     size_t off = 0;
@@ -648,10 +598,12 @@ extern "C" prony_status_t prony_build_S(prony_handle_t h, int d, int n, int m, c
     const bool s0 = (flags & PRONY_WITH_S0) != 0;
     PencilPlan P;
     if (prec == PRONY_FP32) {
-        if ((st = make_plan(h, d, n, m, s0, sizeof(float), P)) != PRONY_OK) return st;
+        if ((st = make_plan(h, d, n, m, s0, sizeof(float), P, tuned_target(h, d, n, m, prec, 0))) != PRONY_OK)
+            return st;
         return launch_pencil<float>(h, P, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
     }
-    if ((st = make_plan(h, d, n, m, s0, sizeof(double), P)) != PRONY_OK) return st;
+    if ((st = make_plan(h, d, n, m, s0, sizeof(double), P, tuned_target(h, d, n, m, prec, 0))) != PRONY_OK)
+        return st;
     return launch_pencil<double>(h, P, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
 }
 
@@ -708,7 +660,10 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         if (x.m < 1 || x.m > N) return fail(h, PRONY_EINVAL, who + "m must be in 1..N");
         if (x.m > 32) return fail(h, PRONY_ENOTSUP, who + "m > 32 is not supported");
         if (!x.f || !x.U || !x.sigma || !x.V || !x.S) return fail(h, PRONY_EINVAL, who + "null pointer");
-        prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], 1);
+        // batch members: split into the tuned number of chunks (default 1)
+        const int chunks = tuned_target(h, x.d, x.n, x.m, sizeof(T) == 4 ? PRONY_FP32 : PRONY_FP64, 1);
+        const int rt = (int)((N + kRowsPerTile - 1) / kRowsPerTile);
+        prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], std::max(1, chunks) * rt);
         if (st != PRONY_OK) return fail(h, st, who + h->err);
     }
     // classes by column-block count; inside a class, longest tiles first
@@ -928,4 +883,19 @@ extern "C" prony_status_t prony_graph_launch(prony_handle_t h, void* graph_exec)
 extern "C" prony_status_t prony_graph_destroy(void* graph_exec) {
     if (!graph_exec) return PRONY_EINVAL;
     return hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec)) == hipSuccess ? PRONY_OK : PRONY_EHIP;
+}
+
+extern "C" prony_status_t prony_tune_set(prony_handle_t h, int d, int n, int m, prony_prec_t prec, unsigned flags,
+                                         int target_wgs) {
+    if (!h) return PRONY_EINVAL;
+    if (d < 1 || d > 3 || n < 1 || m < 1 || m > 32) return fail(h, PRONY_EINVAL, "prony_tune_set: bad shape");
+    if (prec != PRONY_FP64 && prec != PRONY_FP32) return fail(h, PRONY_EINVAL, "prony_tune_set: bad precision");
+    if (flags & ~PRONY_TUNE_BATCHED) return fail(h, PRONY_EINVAL, "prony_tune_set: unknown flag");
+    if (target_wgs < 0 || target_wgs > (1 << 20)) return fail(h, PRONY_EINVAL, "prony_tune_set: bad target");
+    const auto key = std::make_tuple(d, n, m, (int)prec, (flags & PRONY_TUNE_BATCHED) ? 1 : 0);
+    if (target_wgs == 0)
+        h->split_targets.erase(key);
+    else
+        h->split_targets[key] = target_wgs;
+    return PRONY_OK;
 }

@@ -5,10 +5,12 @@
 // coeffs_tiles: a workgroup evaluates rows of A^T into LDS 64 at a time
 //               (integer powers by binary exponentiation), optionally writes
 //               them out, and accumulates its part of the Gram matrix and
-//               right-hand side; the last workgroup adds the parts in order.
+//               right-hand side; the parts are summed by the deterministic
+//               tree reduction of reduce.h.
 #include <algorithm>
 
 #include "common.h"
+#include "reduce.h"
 
 namespace prony {
 namespace {
@@ -34,6 +36,15 @@ __device__ __forceinline__ double2 cpow_int(double2 z, int e) {
 
 constexpr int kEntries = (kMaxM * kMaxM + kMaxM + kThreads - 1) / kThreads;
 
+// Entry e of (A^T)^* [A^T | f_I]: the first m*m are the Gram matrix, the last m the rhs.
+__device__ __forceinline__ void emit_gram(int m, double2* __restrict__ gram, double2* __restrict__ rhs, int e,
+                                          double re, double im) {
+    if (e < m * m)
+        gram[e] = make_double2(re, im);
+    else
+        rhs[e - m * m] = make_double2(re, im);
+}
+
 // One workgroup takes `chunks` consecutive 64-row chunks of I_n. Per chunk the
 // rows of A^T are evaluated into LDS, then every thread accumulates its fixed
 // entries of (A^T)^* [A^T | f_I] over the chunk in FP64 registers. The
@@ -42,8 +53,9 @@ constexpr int kEntries = (kMaxM * kMaxM + kMaxM + kThreads - 1) / kThreads;
 __global__ __launch_bounds__(kThreads) void coeffs_tiles(int d, int n, int N, int m, int chunks,
                                                          const double2* __restrict__ z,
                                                          const double2* __restrict__ f, double2* __restrict__ at_out,
-                                                         double2* __restrict__ part, unsigned* __restrict__ counter,
-                                                         double2* __restrict__ gram, double2* __restrict__ rhs) {
+                                                         double2* __restrict__ part, double2* __restrict__ upper,
+                                                         unsigned* __restrict__ counters, double2* __restrict__ gram,
+                                                         double2* __restrict__ rhs) {
     __shared__ double2 sz[kMaxM * 3];
     __shared__ double2 sa[kRows * kMaxM];
     __shared__ double2 sf[kRows];
@@ -106,25 +118,17 @@ __global__ __launch_bounds__(kThreads) void coeffs_tiles(int d, int n, int N, in
         const int e = tid + u * kThreads;
         if (e < tot) out[e] = make_double2(re[u], im[u]);
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    for (int e = tid; e < tot; e += kThreads) {
-        double sr = 0.0, si = 0.0;
-        for (int w = 0; w < (int)gridDim.x; ++w) {
-            const double2 v = part[(size_t)w * tot + e];
-            sr += v.x;
-            si += v.y;
+    if (gridDim.x == 1) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kEntries; ++u) {
+            const int e = tid + u * kThreads;
+            if (e < tot) emit_gram(m, gram, rhs, e, re[u], im[u]);
         }
-        if (e < m * m)
-            gram[e] = make_double2(sr, si);
-        else
-            rhs[e - m * m] = make_double2(sr, si);
+        return;
     }
-    if (tid == 0) *counter = 0u;
+    tree_reduce<kThreads>(part, upper, counters, (int)gridDim.x, (int)blockIdx.x, tot, &s_last,
+                          [&](int e, double sr, double si) { emit_gram(m, gram, rhs, e, sr, si); });
 }
 
 constexpr int kMaxWorkgroups = 64;
@@ -134,7 +138,7 @@ constexpr int kMaxWorkgroups = 64;
 size_t coeffs_workspace_bytes(int d, int n, int m) {
     (void)d;
     (void)n;
-    return align_up((size_t)kMaxWorkgroups * (m * m + m) * sizeof(double2), 256);
+    return align_up((size_t)(kMaxWorkgroups + tree_nodes(kMaxWorkgroups)) * (m * m + m) * sizeof(double2), 256);
 }
 
 }  // namespace prony
@@ -158,12 +162,13 @@ extern "C" prony_status_t prony_coeffs(prony_handle_t h, int d, int n, int m, co
     const int chunks = (nchunks + kMaxWorkgroups - 1) / kMaxWorkgroups;
     const int wgs = (nchunks + chunks - 1) / chunks;
     double2* part = static_cast<double2*>(h->ws);
+    double2* upper = part + (size_t)wgs * (m * m + m);
     {
         ProfileScope prof(h, "coeffs_tiles");
         coeffs_tiles<<<wgs, kThreads, 0, h->stream>>>(d, n, (int)N, m, chunks, reinterpret_cast<const double2*>(z),
                                                       reinterpret_cast<const double2*>(f),
-                                                      reinterpret_cast<double2*>(AT_out), part,
-                                                      h->counters + (kCounterSlots - 1),
+                                                      reinterpret_cast<double2*>(AT_out), part, upper,
+                                                      h->counters,
                                                       reinterpret_cast<double2*>(gram),
                                                       reinterpret_cast<double2*>(rhs));
     }

@@ -1,0 +1,68 @@
+"""Autotuner: candidates are timed, the winner is registered and cached, the
+cache reloads in a fresh handle entry, and tuned plans stay correct."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import prony_oracle as O
+from paper_2012_11430_amd import api, autotune
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def test_tune_single_registers_caches_and_stays_correct(tmp_path):
+    path = str(tmp_path / "tune.json")
+    d, n, m = 2, 31, 12
+    times = autotune.tune_single(DEV, d, n, m, "fp32", reps=3, path=path)
+    assert len(times) == len(autotune.SINGLE_CANDIDATES) and all(t > 0 for t in times.values())
+    data = json.load(open(path))
+    entries = next(iter(data["devices"].values()))
+    assert entries[f"{d},{n},{m},fp32,single"] in times
+    assert autotune.load_cache(DEV, path) == 1
+    rng = np.random.Generator(np.random.PCG64(5))
+    N = (n + 1) ** d
+    grid = rng.standard_normal((2 * n + 2) ** d) + 1j * rng.standard_normal((2 * n + 2) ** d)
+    U = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+    V = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+    s = rng.uniform(0.5, 2, m)
+    ref = O.pencil_matrices(grid, d, n, U, s, V)
+    for target in (256, 2048):      # plans at both ends of the candidate range
+        autotune.register(DEV, d, n, m, "fp32", False, target)
+        got = api.build_S(_dev(grid), d, n, _dev(U), _dev(s), _dev(V), prec="fp32").cpu().numpy()
+        assert max(np.linalg.norm(got[l] - ref[l]) / np.linalg.norm(ref[l]) for l in range(d)) <= 1e-5
+    autotune.register(DEV, d, n, m, "fp32", False, 0)
+
+
+def test_tune_batch(tmp_path):
+    path = str(tmp_path / "tune.json")
+    rng = np.random.Generator(np.random.PCG64(6))
+    inst = []
+    refs = []
+    for d, n, m in [(1, 300, 7), (2, 20, 9), (3, 7, 5), (2, 20, 9)]:
+        N = (n + 1) ** d
+        grid = rng.standard_normal((2 * n + 2) ** d) + 1j * rng.standard_normal((2 * n + 2) ** d)
+        U = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+        V = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+        s = rng.uniform(0.5, 2, m)
+        inst.append((d, n, _dev(grid), _dev(U), _dev(s), _dev(V)))
+        refs.append(O.pencil_matrices(grid, d, n, U, s, V))
+    times = autotune.tune_batch(inst, "fp32", reps=2, path=path)
+    assert set(times) == set(autotune.BATCH_CANDIDATES)
+    for chunks in autotune.BATCH_CANDIDATES:
+        for d, n, f, U, s, V in inst:
+            autotune.register(DEV, d, n, U.shape[1], "fp32", True, chunks)
+        b = api.Batch(inst, prec="fp32")
+        b.run()
+        torch.cuda.synchronize()
+        for S, ref in zip(b.S, refs):
+            got = S.cpu().numpy()
+            assert max(np.linalg.norm(got[l] - ref[l]) / np.linalg.norm(ref[l]) for l in range(len(ref))) <= 1e-5
+        b.close()
