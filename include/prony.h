@@ -86,7 +86,8 @@ prony_status_t prony_synchronize(prony_handle_t handle);
 const char* prony_last_error(prony_handle_t handle);
 
 /* Pre-size the workspace for problems up to (d_max, n_max, m_max) so that later
-   calls allocate nothing (needed before capturing a stream into a HIP graph). */
+   single-instance calls (samples, build_T, build_S, build_S_adjoint, coeffs)
+   allocate nothing (needed before capturing such calls into a HIP graph). */
 prony_status_t prony_reserve(prony_handle_t handle, int d_max, int n_max, int m_max);
 
 /* Profiling aid. With a non-NULL `kernel` name, every later launch of that kernel

@@ -294,6 +294,16 @@ prony_status_t launch_adjoint(prony_handle_t h, const AdjPlan& P, const double* 
 }
 
 }  // namespace
+
+size_t adjoint_workspace_bytes(prony_handle_t h, int d, int n, int m) {
+    size_t best = 0;
+    for (size_t ts : {sizeof(float), sizeof(double)}) {
+        AdjPlan P;
+        if (make_adj_plan(h, d, n, m, ts, P) == PRONY_OK) best = std::max(best, P.ws_bytes);
+    }
+    return best;
+}
+
 }  // namespace prony
 
 using namespace prony;

@@ -78,6 +78,7 @@ __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a -
 // Workspace bytes of one prony_build_S / prony_coeffs call (largest precision/flag).
 size_t pencil_workspace_bytes(prony_handle_t h, int d, int n, int m);
 size_t coeffs_workspace_bytes(int d, int n, int m);
+size_t adjoint_workspace_bytes(prony_handle_t h, int d, int n, int m);
 
 // Common argument validation for (d, n): 1 <= d <= 3, n >= 1, sizes within int32.
 prony_status_t check_dn(prony_handle_t h, int d, int n);

@@ -618,7 +618,10 @@ extern "C" prony_status_t prony_reserve(prony_handle_t h, int d_max, int n_max, 
     size_t need = 0;
     for (int d = 1; d <= d_max; ++d) {
         const int m = std::min<int64_t>(m_max, ipow(n_max + 1, d));
-        if (m <= 32) need = std::max(need, pencil_workspace_bytes(h, d, n_max, m));
+        if (m <= 32) {
+            need = std::max(need, pencil_workspace_bytes(h, d, n_max, m));
+            need = std::max(need, adjoint_workspace_bytes(h, d, n_max, m));
+        }
         need = std::max(need, coeffs_workspace_bytes(d, n_max, m));
     }
     return ensure_workspace(h, need);

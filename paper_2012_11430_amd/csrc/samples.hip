@@ -5,8 +5,8 @@
 namespace prony {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kTermsPerStage = 512;   // nodes/coefficients staged in LDS per pass
+constexpr int kThreads = 64;    // small blocks: grids of 1e4 points still spread over all CUs
+constexpr int kTermsPerStage = 256;   // nodes/coefficients staged in LDS per pass
 
 // One thread per grid point p; the m terms are staged through LDS in groups.
 __global__ __launch_bounds__(kThreads) void samples_kernel(int d, int n, int m, int gsize,
