@@ -320,14 +320,14 @@ def adjoint_c4(dev, args):
         clean = api.samples(t_d, c_d, inst.n)
         noisy = api.samples(t_d, c_d, inst.n, noise=torch.from_numpy(inst.noise()).to(dev))
         Ud, sd, Vd = torch.from_numpy(U).to(dev), torch.from_numpy(s).to(dev), torch.from_numpy(V).to(dev)
-        ref = api.build_S(clean, inst.d, inst.n, Ud, sd, Vd, prec="fp64")
-        data.append((inst, noisy, Ud, sd, Vd, ref))
+        # S_l(f) - S_l^ref = S_l(f - f0): the loss is formed from the sample difference
+        data.append((inst, noisy - clean, Ud, sd, Vd))
 
     def fwd_bwd():
-        for inst, noisy, Ud, sd, Vd, ref in data:
-            f = noisy.detach().requires_grad_(True)
+        for inst, delta, Ud, sd, Vd in data:
+            f = delta.detach().requires_grad_(True)
             S = pencil(f, inst.d, inst.n, Ud, sd, Vd, "fp32", "fp32")
-            torch.sum(torch.abs(S - ref) ** 2).backward()
+            torch.sum(torch.abs(S) ** 2).backward()
     fwd_bwd()
     reps = 3
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -341,7 +341,8 @@ def adjoint_c4(dev, args):
     inst = insts[0]
     flops = len(insts) * 2 * s_flops(inst.d, inst.N, inst.m)
     return {
-        "workload": "c4: 64 instances of d=2, n=47, m=16, noise 1e-6; L = sum_l ||S_l - S_l^ref||_F^2",
+        "workload": "c4: 64 instances of d=2, n=47, m=16, noise 1e-6; L = sum_l ||S_l - S_l^ref||_F^2 "
+                    "= sum_l ||S_l(f - f0)||_F^2",
         "ms_forward_backward_64": round(ms, 4),
         "tflops_forward_plus_adjoint": round(flops / (ms * 1e-3) / 1e12, 3),
     }
