@@ -45,14 +45,16 @@ def _c4_case(index=0):
                                       tol=inst.N * O.EPS64, rank=inst.m)
     ref = O.pencil_matrices(clean, inst.d, inst.n, U, s, V)
     S = O.pencil_matrices(noisy, inst.d, inst.n, U, s, V)
-    grad = O.pencil_adjoint(2 * (S - ref), inst.d, inst.n, U, s, V)
-    return inst, clean, noisy, U, s, V, ref, S, grad
+    # dL/dS = 2 (S - S^ref) = 2 S(f - f0): formed from the sample difference (no cancellation)
+    gS = 2 * O.pencil_matrices(noisy - clean, inst.d, inst.n, U, s, V)
+    grad = O.pencil_adjoint(gS, inst.d, inst.n, U, s, V)
+    return inst, clean, noisy, U, s, V, ref, gS, grad
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_adjoint_matches_oracle_c4(prec):
-    inst, clean, noisy, U, s, V, ref, S, grad = _c4_case()
-    got = api.build_S_adjoint(_dev(2 * (S - ref)), inst.d, inst.n, _dev(U), _dev(s), _dev(V), prec=prec)
+    inst, clean, noisy, U, s, V, ref, gS, grad = _c4_case()
+    got = api.build_S_adjoint(_dev(gS), inst.d, inst.n, _dev(U), _dev(s), _dev(V), prec=prec)
     err = _rel(got.cpu().numpy(), grad)
     print(f"adjoint c4 {prec}: rel err {err:.3e}", flush=True)
     assert err <= TOL[prec]
@@ -89,7 +91,7 @@ def test_adjoint_dot_product_identity_against_oracle_forward():
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_autograd_gradient_matches_finite_differences(prec):
-    inst, clean, noisy, U, s, V, ref, S, grad = _c4_case()
+    inst, clean, noisy, U, s, V, ref, gS, grad = _c4_case()
     # S_l(f) - S_l^ref = S_l(f - f0) (linear in f): the loss is formed from the
     # sample difference, so the forward's rounding is relative to S(f - f0) and not
     # to S(f), which would cancel against S^ref
@@ -112,7 +114,7 @@ def test_autograd_gradient_matches_finite_differences(prec):
 
 
 def test_autograd_rejects_factor_gradients():
-    inst, clean, noisy, U, s, V, ref, S, grad = _c4_case()
+    inst, clean, noisy, U, s, V, ref, gS, grad = _c4_case()
     Ud = _dev(U).requires_grad_(True)
     with pytest.raises(ValueError):
         pencil(_dev(noisy), inst.d, inst.n, Ud, _dev(s), _dev(V))
@@ -121,6 +123,6 @@ def test_autograd_rejects_factor_gradients():
 def test_adjoint_batch_of_c4_instances():
     # several instances of the 64-instance batch; each gradient against the oracle
     for idx in (1, 2, 3):
-        inst, clean, noisy, U, s, V, ref, S, grad = _c4_case(idx)
-        got = api.build_S_adjoint(_dev(2 * (S - ref)), inst.d, inst.n, _dev(U), _dev(s), _dev(V), prec="fp32")
+        inst, clean, noisy, U, s, V, ref, gS, grad = _c4_case(idx)
+        got = api.build_S_adjoint(_dev(gS), inst.d, inst.n, _dev(U), _dev(s), _dev(V), prec="fp32")
         assert _rel(got.cpu().numpy(), grad) <= TOL["fp32"]
