@@ -61,7 +61,8 @@ def parse():
                     help="oracle steps timed for the CPU baseline (0 skips it)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched (c3) and adjoint (c4) measurements")
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default split targets)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="do not run the autotuner; use the tuning cache if one exists")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (a reference dispatch "
                          "of known traffic for hardware-counter calibration)")
@@ -121,6 +122,8 @@ def main():
         for prec in ("fp32", "fp64"):
             times = autotune.tune_single(dev, d, n, m, prec, reps=5)
             tuned[prec] = min(times, key=times.get)
+    else:
+        tuned["cache_entries_loaded"] = autotune.load_cache(dev)
 
     def step(prec):
         api.samples(t_d, c_d, n, noise=noise_d, out=f)
@@ -259,6 +262,8 @@ def batched_c3(dev, args):
     if not args.no_tune:
         times = autotune.tune_batch(dev_inst, "fp32", reps=2)
         tuned = min(times, key=times.get)
+    else:
+        autotune.load_cache(dev)
     batch = api.Batch(dev_inst, prec="fp32")
     batch.capture()
     reps = max(3, args.steps // 4)

@@ -317,7 +317,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     T2* out = part + (size_t)L * tot;
     for (int o = tid; o < tot; o += kThreads) {
         const int i = o / P.C, c = o - (o / P.C) * P.C;
-        out[o] = T2{esum[i * P.nrp + 2 * c], esum[i * P.nrp + 2 * c + 1]};
+        store_coherent(&out[o], T2{esum[i * P.nrp + 2 * c], esum[i * P.nrp + 2 * c + 1]});
     }
 
     // Deterministic tree reduction of the workgroup partials (reduce.h); the

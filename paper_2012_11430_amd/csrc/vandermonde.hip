@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void coeffs_tiles(int d, int n, int N, in
 #pragma unroll
     for (int u = 0; u < kEntries; ++u) {
         const int e = tid + u * kThreads;
-        if (e < tot) out[e] = make_double2(re[u], im[u]);
+        if (e < tot) store_coherent(&out[e], make_double2(re[u], im[u]));
     }
     if (gridDim.x == 1) {
         __syncthreads();
