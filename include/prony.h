@@ -94,7 +94,8 @@ prony_status_t prony_reserve(prony_handle_t handle, int d_max, int n_max, int m_
    by the handle is bracketed by a pair of HIP events recorded on the handle's
    stream; NULL stops recording. Each call discards earlier records.
    Kernel names: "samples", "toeplitz", "pencil_pack", "pencil_tiles",
-   "pencil_tiles_batched", "coeffs_tiles", "adjoint_pack", "adjoint_tiles". */
+   "pencil_tiles_batched", "pencil_finish", "coeffs_tiles", "coeffs_finish",
+   "adjoint_pack", "adjoint_tiles". */
 prony_status_t prony_profile_enable(prony_handle_t handle, const char* kernel);
 
 /* Synchronise the stream and report the recorded launches of the profiled kernel:

@@ -16,7 +16,6 @@ struct prony_handle_s {
     hipStream_t stream = nullptr;
     void* ws = nullptr;          // device workspace owned by the handle
     size_t ws_bytes = 0;
-    unsigned* counters = nullptr;  // kCounterSlots device counters, zero between launches
     int num_cus = 256;
     size_t lds_per_block = 65536;
     std::string err;
@@ -29,10 +28,6 @@ struct prony_handle_s {
 };
 
 namespace prony {
-
-// Device counters of the last-workgroup reductions (allocated and zeroed once per
-// handle; every kernel that uses some returns them to zero before it ends).
-constexpr int kCounterSlots = 4096;
 
 prony_status_t fail(prony_handle_t h, prony_status_t st, const std::string& msg);
 prony_status_t hip_fail(prony_handle_t h, hipError_t e, const char* what);

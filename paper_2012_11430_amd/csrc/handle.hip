@@ -129,18 +129,6 @@ extern "C" prony_status_t prony_create(prony_handle_t* handle, int device) {
         h->num_cus = prop.multiProcessorCount;
         h->lds_per_block = prop.sharedMemPerBlock;
     }
-    {
-        DeviceGuard g(device);
-        void* c = nullptr;
-        if (!g.ok || hipMalloc(&c, sizeof(unsigned) * kCounterSlots) != hipSuccess ||
-            hipMemset(c, 0, sizeof(unsigned) * kCounterSlots) != hipSuccess ||
-            hipDeviceSynchronize() != hipSuccess) {
-            if (c) (void)hipFree(c);
-            delete h;
-            return PRONY_EHIP;
-        }
-        h->counters = static_cast<unsigned*>(c);
-    }
     *handle = h;
     return PRONY_OK;
 }
@@ -156,10 +144,6 @@ extern "C" prony_status_t prony_destroy(prony_handle_t h) {
     if (h->ws) {
         if (hipStreamSynchronize(h->stream) != hipSuccess) st = PRONY_EHIP;
         if (hipFree(h->ws) != hipSuccess) st = PRONY_EHIP;
-    }
-    if (h->counters) {
-        if (hipStreamSynchronize(h->stream) != hipSuccess) st = PRONY_EHIP;
-        if (hipFree(h->counters) != hipSuccess) st = PRONY_EHIP;
     }
     for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
     delete h;

@@ -61,24 +61,21 @@ struct PencilPlan {
     int nwg;        // rt * sk workgroups
     int win_cap;    // window capacity (complex elements)
     int c0;         // grid offset of the origin shift
-    int gs;         // workgroups per first-level reduction group
-    int ngroups;    // nodes of the reduction tree above the leaves
     size_t lds_bytes;
     // workspace offsets (bytes)
-    size_t off_v, off_u, off_g, off_p, off_gp, ws_bytes;
+    size_t off_v, off_u, off_g, off_p, ws_bytes;
 };
 
 
 // Packs, per call: (y = 0) the stacked shifted factors V_l in the pair layout,
 // rows h' of the extended index set padded with zeros to sk*kc + kPrefetchRows;
 // (y = 1) the (Re U, Im U) pairs, rows padded to whole 64-row tiles and
-// columns to 16*mbi; (y = 2) the grid offsets G(h') and the zeroed reduction
-// counters. All index arithmetic fits in 32 bits (checked by the host plan).
+// columns to 16*mbi; (y = 2) the grid offsets G(h'). All index arithmetic fits in 32 bits (checked by the host plan).
 template <typename T>
 __device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __restrict__ U, int64_t u_rs,
                                           int64_t u_cs, const double2* __restrict__ V, int64_t v_rs, int64_t v_cs,
                                           pair_t<T>* __restrict__ vp, pair_t<T>* __restrict__ up,
-                                          int* __restrict__ gt, unsigned* __restrict__ counters, int section) {
+                                          int* __restrict__ gt, int section) {
     using T2 = pair_t<T>;
     const int kbp = P.sk * P.kc + kPrefetchRows;
     const int stride = gridDim.x * blockDim.x;
@@ -129,7 +126,6 @@ __device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __
         }
     } else {
         for (int hx = first; hx < kbp; hx += stride) gt[hx] = ext_offset(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
-        for (int i = first; i <= P.ngroups; i += stride) counters[i] = 0u;
     }
 }
 
@@ -137,8 +133,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void pencil_pack(PencilPlan P, const double2* __restrict__ U, int64_t u_rs,
                                                    int64_t u_cs, const double2* __restrict__ V, int64_t v_rs,
                                                    int64_t v_cs, pair_t<T>* __restrict__ vp, pair_t<T>* __restrict__ up,
-                                                   int* __restrict__ gt, unsigned* __restrict__ counters) {
-    pack_body<T>(P, U, u_rs, u_cs, V, v_rs, v_cs, vp, up, gt, counters, blockIdx.y);
+                                                   int* __restrict__ gt) {
+    pack_body<T>(P, U, u_rs, u_cs, V, v_rs, v_cs, vp, up, gt, blockIdx.y);
 }
 
 
@@ -159,8 +155,6 @@ struct TilePtrs {
     const pair_t<T>* up;
     const int* gtab;
     pair_t<T>* part;
-    double2* gpart;
-    unsigned* counters;
     const double* sigma;
     double2* S;
 };
@@ -178,17 +172,13 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     const T2* __restrict__ up = ptr.up;
     const int* __restrict__ gtab = ptr.gtab;
     T2* __restrict__ part = ptr.part;
-    double2* __restrict__ gpart = ptr.gpart;
-    unsigned* __restrict__ counters = ptr.counters;
-    const double* __restrict__ sigma = ptr.sigma;
-    double2* __restrict__ S = ptr.S;
+
     extern __shared__ __align__(16) unsigned char smem[];
     // Phase 1 (K loop): grid window + h' offsets. Phase 2 (U^* reduction): the
     // same bytes hold the per-workgroup sum of the wave results.
     T2* win = reinterpret_cast<T2*>(smem);
     int* gt = reinterpret_cast<int*>(smem + align_up(sizeof(T2) * (size_t)P.win_cap, 16));
     T* esum = reinterpret_cast<T*>(smem);
-    __shared__ int s_last;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -317,21 +307,9 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     T2* out = part + (size_t)L * tot;
     for (int o = tid; o < tot; o += kThreads) {
         const int i = o / P.C, c = o - (o / P.C) * P.C;
-        store_coherent(&out[o], T2{esum[i * P.nrp + 2 * c], esum[i * P.nrp + 2 * c + 1]});
+        out[o] = T2{esum[i * P.nrp + 2 * c], esum[i * P.nrp + 2 * c + 1]};
     }
 
-    // Deterministic tree reduction of the workgroup partials (reduce.h); the
-    // workgroup holding the total applies Sigma^{-1} and writes S.
-    __syncthreads();
-    if (P.nwg == 1) {
-        for (int o = tid; o < tot; o += kThreads) {
-            const int i = o / P.C, c = o - (o / P.C) * P.C;
-            store_s(P, sigma, S, o, (double)esum[i * P.nrp + 2 * c], (double)esum[i * P.nrp + 2 * c + 1]);
-        }
-        return;
-    }
-    tree_reduce<kThreads>(part, gpart, counters, P.nwg, L, tot, &s_last,
-                          [&](int o, double re, double im) { store_s(P, sigma, S, o, re, im); });
 }
 
 // Single-instance launch: one workgroup per tile. Workgroups are dealt to the
@@ -360,7 +338,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void pencil_pack_batched(const BatchEntry<T>* __restrict__ entries) {
     const BatchEntry<T>& e = entries[blockIdx.z];
     pack_body<T>(e.P, e.U, e.P.m, 1, e.V, e.P.m, 1, const_cast<pair_t<T>*>(e.ptr.vp),
-                 const_cast<pair_t<T>*>(e.ptr.up), const_cast<int*>(e.ptr.gtab), e.ptr.counters, blockIdx.y);
+                 const_cast<pair_t<T>*>(e.ptr.up), const_cast<int*>(e.ptr.gtab), blockIdx.y);
 }
 
 // Batched launch over the instances of one column-block class, ordered by
@@ -452,10 +430,6 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     if (((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp >= (int64_t(1) << 31) ||
         (int64_t)P.nwg * P.m * P.C >= (int64_t(1) << 31))
         return fail(h, PRONY_ENOTSUP, "prony_build_S: problem too large for 32-bit tile indexing");
-    // reduction tree: gs = fan-in, ngroups = nodes above the leaves (rows of
-    // gpart and counters used)
-    P.gs = kFanIn;
-    P.ngroups = tree_nodes(P.nwg);
     const size_t t2 = 2 * tsize;
     const size_t tot = (size_t)P.m * P.C;
     size_t off = 0;
@@ -467,11 +441,27 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     off = align_up(off + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
     P.off_p = off;
     off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
-    P.off_gp = off;
-    off = align_up(off + sizeof(double2) * (size_t)P.ngroups * tot, 256);
     P.ws_bytes = off;
-    if (P.ngroups + 1 > kCounterSlots) return fail(h, PRONY_ENOTSUP, "prony_build_S: too many workgroups");
     return PRONY_OK;
+}
+
+// Sum of the workgroup partials (reduce.h) and Sigma^{-1}: S_l(i, q) = sum / sigma_q.
+template <typename T>
+__global__ __launch_bounds__(kFinishThreads) void pencil_finish(PencilPlan P, const pair_t<T>* __restrict__ part,
+                                                                const double* __restrict__ sigma,
+                                                                double2* __restrict__ S) {
+    finish_rows(part, P.nwg, P.m * P.C, blockIdx.x * kFinishOuts,
+                [&](int o, double re, double im) { store_s(P, sigma, S, o, re, im); });
+}
+
+// Same for every instance of a batch: grid (slices, instances).
+template <typename T>
+__global__ __launch_bounds__(kFinishThreads) void pencil_finish_batched(const BatchEntry<T>* __restrict__ entries) {
+    const BatchEntry<T>& e = entries[blockIdx.y];
+    const int tot = e.P.m * e.P.C;
+    if ((int)blockIdx.x * kFinishOuts >= tot) return;
+    finish_rows(e.ptr.part, e.P.nwg, tot, blockIdx.x * kFinishOuts,
+                [&](int o, double re, double im) { store_s(e.P, e.ptr.sigma, e.ptr.S, o, re, im); });
 }
 
 template <typename T, int NB>
@@ -539,8 +529,6 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, const double
     T2* up = reinterpret_cast<T2*>(ws + P.off_u);
     int* gt = reinterpret_cast<int*>(ws + P.off_g);
     T2* part = reinterpret_cast<T2*>(ws + P.off_p);
-    double2* gpart = reinterpret_cast<double2*>(ws + P.off_gp);
-    unsigned* counters = h->counters;
 
     const int64_t kbp = (int64_t)P.sk * P.kc + kPrefetchRows;
     const int64_t largest = std::max<int64_t>(kbp * P.nrp, (int64_t)P.rt * kRowsPerTile * P.mbi * 16);
@@ -549,14 +537,21 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, const double
         ProfileScope prof(h, "pencil_pack");
         pencil_pack<T><<<dim3(pack_blocks, 3), 256, 0, h->stream>>>(
             P, reinterpret_cast<const double2*>(U), u_rs, u_cs, reinterpret_cast<const double2*>(V), v_rs, v_cs, vp,
-            up, gt, counters);
+            up, gt);
     }
     if ((st = check_launch(h, "pencil_pack")) != PRONY_OK) return st;
-    const TilePtrs<T> ptr{reinterpret_cast<const double2*>(f), vp, up, gt, part, gpart, counters, sigma,
+    const TilePtrs<T> ptr{reinterpret_cast<const double2*>(f), vp, up, gt, part, sigma,
                           reinterpret_cast<double2*>(S)};
     st = dispatch_tiles<T>(h, P, ptr);
     if (st != PRONY_OK) return st;
-    return check_launch(h, "pencil_tiles");
+    if ((st = check_launch(h, "pencil_tiles")) != PRONY_OK) return st;
+    {
+        ProfileScope prof(h, "pencil_finish");
+        const int tot = P.m * P.C;
+        pencil_finish<T><<<(tot + kFinishOuts - 1) / kFinishOuts, kFinishThreads, 0, h->stream>>>(
+            P, part, sigma, reinterpret_cast<double2*>(S));
+    }
+    return check_launch(h, "pencil_finish");
 }
 
 }  // namespace
@@ -639,6 +634,7 @@ struct prony_batch_s {
     size_t ws_bytes = 0;
     void* entries = nullptr;      // device BatchEntry<T>[count], grouped by class
     int pack_x = 1;               // pack blocks per (instance, section)
+    int finish_x = 1;             // finishing workgroups per instance (largest instance)
     struct ClassLaunch {
         int nb, first, count, tiles;
         size_t lds;
@@ -676,7 +672,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         if (plans[a].nb != plans[b].nb) return plans[a].nb < plans[b].nb;
         return (int64_t)plans[a].kc > (int64_t)plans[b].kc;
     });
-    // workspace layout: entries, then per instance vp | up | gt | part | gpart | counters
+    // workspace layout: entries, then per instance vp | up | gt | part
     const size_t t2 = 2 * sizeof(T);
     size_t off = align_up(sizeof(BatchEntry<T>) * (size_t)count, 256);
     std::vector<BatchEntry<T>> host(count);
@@ -689,8 +685,6 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         off = align_up(off + t2 * (size_t)P.rt * kRowsPerTile * P.mbi * 16, 256);
         off = align_up(off + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
         off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
-        off = align_up(off + sizeof(double2) * (size_t)P.ngroups * tot, 256);
-        off = align_up(off + sizeof(unsigned) * ((size_t)P.ngroups + 1), 256);
     }
     void* ws = nullptr;
     hipError_t e = hipMalloc(&ws, off);
@@ -719,10 +713,6 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         E.ptr.gtab = reinterpret_cast<const int*>(w + o);
         o = align_up(o + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
         E.ptr.part = reinterpret_cast<T2*>(w + o);
-        o = align_up(o + t2 * (size_t)P.nwg * tot, 256);
-        E.ptr.gpart = reinterpret_cast<double2*>(w + o);
-        o = align_up(o + sizeof(double2) * (size_t)P.ngroups * tot, 256);
-        E.ptr.counters = reinterpret_cast<unsigned*>(w + o);
         E.ptr.sigma = x.sigma;
         E.ptr.S = reinterpret_cast<double2*>(x.S);
         E.U = reinterpret_cast<const double2*>(x.U);
@@ -743,6 +733,8 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         largest = (int)std::max<int64_t>(largest, (big + 255) / 256);
     }
     B->pack_x = std::min(largest, 64);
+    for (int i = 0; i < count; ++i)
+        B->finish_x = std::max(B->finish_x, (plans[i].m * plans[i].C + kFinishOuts - 1) / kFinishOuts);
     B->entries = ws;
     e = hipMemcpyAsync(ws, host.data(), sizeof(BatchEntry<T>) * (size_t)count, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -764,7 +756,11 @@ prony_status_t batch_launch(prony_handle_t h, prony_batch_s* B) {
         if (st != PRONY_OK) return st;
         if ((st = check_launch(h, "pencil_tiles_batched")) != PRONY_OK) return st;
     }
-    return PRONY_OK;
+    {
+        ProfileScope prof(h, "pencil_finish");
+        pencil_finish_batched<T><<<dim3(B->finish_x, B->count), kFinishThreads, 0, h->stream>>>(entries);
+    }
+    return check_launch(h, "pencil_finish_batched");
 }
 
 }  // namespace

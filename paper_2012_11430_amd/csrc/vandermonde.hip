@@ -5,8 +5,8 @@
 // coeffs_tiles: a workgroup evaluates rows of A^T into LDS 64 at a time
 //               (integer powers by binary exponentiation), optionally writes
 //               them out, and accumulates its part of the Gram matrix and
-//               right-hand side; the parts are summed by the deterministic
-//               tree reduction of reduce.h.
+//               right-hand side.
+// coeffs_finish: sums the parts in a fixed order (reduce.h).
 #include <algorithm>
 
 #include "common.h"
@@ -53,13 +53,10 @@ __device__ __forceinline__ void emit_gram(int m, double2* __restrict__ gram, dou
 __global__ __launch_bounds__(kThreads) void coeffs_tiles(int d, int n, int N, int m, int chunks,
                                                          const double2* __restrict__ z,
                                                          const double2* __restrict__ f, double2* __restrict__ at_out,
-                                                         double2* __restrict__ part, double2* __restrict__ upper,
-                                                         unsigned* __restrict__ counters, double2* __restrict__ gram,
-                                                         double2* __restrict__ rhs) {
+                                                         double2* __restrict__ part) {
     __shared__ double2 sz[kMaxM * 3];
     __shared__ double2 sa[kRows * kMaxM];
     __shared__ double2 sf[kRows];
-    __shared__ int s_last;
     const int tid = threadIdx.x;
     const int tot = m * m + m;
     for (int i = tid; i < m * d; i += kThreads) sz[i] = z[i];
@@ -116,19 +113,16 @@ __global__ __launch_bounds__(kThreads) void coeffs_tiles(int d, int n, int N, in
 #pragma unroll
     for (int u = 0; u < kEntries; ++u) {
         const int e = tid + u * kThreads;
-        if (e < tot) store_coherent(&out[e], make_double2(re[u], im[u]));
+        if (e < tot) out[e] = make_double2(re[u], im[u]);
     }
-    if (gridDim.x == 1) {
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kEntries; ++u) {
-            const int e = tid + u * kThreads;
-            if (e < tot) emit_gram(m, gram, rhs, e, re[u], im[u]);
-        }
-        return;
-    }
-    tree_reduce<kThreads>(part, upper, counters, (int)gridDim.x, (int)blockIdx.x, tot, &s_last,
-                          [&](int e, double sr, double si) { emit_gram(m, gram, rhs, e, sr, si); });
+}
+
+// Sum of the workgroup parts (reduce.h) into gram and rhs.
+__global__ __launch_bounds__(kFinishThreads) void coeffs_finish(int m, int rows, const double2* __restrict__ part,
+                                                                double2* __restrict__ gram,
+                                                                double2* __restrict__ rhs) {
+    finish_rows(part, rows, m * m + m, blockIdx.x * kFinishOuts,
+                [&](int e, double re, double im) { emit_gram(m, gram, rhs, e, re, im); });
 }
 
 constexpr int kMaxWorkgroups = 64;
@@ -138,7 +132,7 @@ constexpr int kMaxWorkgroups = 64;
 size_t coeffs_workspace_bytes(int d, int n, int m) {
     (void)d;
     (void)n;
-    return align_up((size_t)(kMaxWorkgroups + tree_nodes(kMaxWorkgroups)) * (m * m + m) * sizeof(double2), 256);
+    return align_up((size_t)kMaxWorkgroups * (m * m + m) * sizeof(double2), 256);
 }
 
 }  // namespace prony
@@ -162,15 +156,18 @@ extern "C" prony_status_t prony_coeffs(prony_handle_t h, int d, int n, int m, co
     const int chunks = (nchunks + kMaxWorkgroups - 1) / kMaxWorkgroups;
     const int wgs = (nchunks + chunks - 1) / chunks;
     double2* part = static_cast<double2*>(h->ws);
-    double2* upper = part + (size_t)wgs * (m * m + m);
     {
         ProfileScope prof(h, "coeffs_tiles");
         coeffs_tiles<<<wgs, kThreads, 0, h->stream>>>(d, n, (int)N, m, chunks, reinterpret_cast<const double2*>(z),
                                                       reinterpret_cast<const double2*>(f),
-                                                      reinterpret_cast<double2*>(AT_out), part, upper,
-                                                      h->counters,
-                                                      reinterpret_cast<double2*>(gram),
-                                                      reinterpret_cast<double2*>(rhs));
+                                                      reinterpret_cast<double2*>(AT_out), part);
     }
-    return check_launch(h, "coeffs_tiles");
+    if ((st = check_launch(h, "coeffs_tiles")) != PRONY_OK) return st;
+    {
+        ProfileScope prof(h, "coeffs_finish");
+        const int tot = m * m + m;
+        coeffs_finish<<<(tot + kFinishOuts - 1) / kFinishOuts, kFinishThreads, 0, h->stream>>>(
+            m, wgs, part, reinterpret_cast<double2*>(gram), reinterpret_cast<double2*>(rhs));
+    }
+    return check_launch(h, "coeffs_finish");
 }
