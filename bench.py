@@ -44,7 +44,7 @@ def tile_flops(d, N, m):
 
 def source_digest():
     h = hashlib.sha256()
-    for name in ("pencil.hip", "common.h"):
+    for name in ("pencil.hip", "common.h", "mfma.h", "reduce.h"):
         with open(os.path.join(ROOT, "paper_2012_11430_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

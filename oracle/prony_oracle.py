@@ -204,7 +204,7 @@ def pencil_matrices(grid: np.ndarray, d: int, n: int, U: np.ndarray, sigma: np.n
 
 
 # ---------------------------------------------------------------------------
-# Nodes from the pencil (Sec. 1, Algorithm 1 lines 4-6; Sec. 4 z -> t)
+# Nodes from the pencil (Sec. 1, Algorithm 1, eigenvalue step; Sec. 4 z -> t)
 # ---------------------------------------------------------------------------
 
 
@@ -232,7 +232,7 @@ def nodes_from_pencil(S: np.ndarray, mu: np.ndarray):
 
 
 # ---------------------------------------------------------------------------
-# Coefficients (Sec. 1 eq. ls_probl, Algorithm 1 line 7)
+# Coefficients (Sec. 1 eq. ls_probl, Algorithm 1, coefficient step)
 # ---------------------------------------------------------------------------
 
 

@@ -3,9 +3,9 @@
 * reduced SVD of T: LAPACK for small N, the block power method with rank
   determination (Sec. 2.2, Algorithm 3) for large N;
 * eigendecomposition of the random combination C_mu and extraction of the
-  nodes z_j, t_j (Algorithm 1, lines 4-6);
+  nodes z_j, t_j (Algorithm 1, eigenvalue step);
 * the m x m solve of the normal equations gram c = rhs formed on the GPU
-  (Algorithm 1, line 7).
+  (Algorithm 1, coefficient step).
 
 `solve` chains these with the GPU calls of `api` into Algorithm 1.
 """
