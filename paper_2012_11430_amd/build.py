@@ -18,6 +18,9 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: keeps the K loops free of copies
+    # between the accumulator and architectural register files
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-result",
 ]
 

@@ -31,6 +31,8 @@ struct Mfma<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+    static __device__ __forceinline__ int group_of_row(int i) { return i >> 2; }
+    static __device__ __forceinline__ int elem_of_row(int i) { return i & 3; }
 };
 template <>
 struct Mfma<double> {
@@ -39,7 +41,22 @@ struct Mfma<double> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+    static __device__ __forceinline__ int group_of_row(int i) { return i & 3; }
+    static __device__ __forceinline__ int elem_of_row(int i) { return i >> 2; }
 };
+
+// Value of the neighbouring lane (lane ^ 1) through a DPP quad permutation
+// [1, 0, 3, 2]; every lane of the wave must be active.
+constexpr int kDppSwapPairs = 0xB1;
+__device__ __forceinline__ float swap_lane_pair(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), kDppSwapPairs, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double swap_lane_pair(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(v & 0xffffffffll), kDppSwapPairs, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), kDppSwapPairs, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // Grid offset of the extended index h' (row-major over {-1..n}^d).
 __host__ __device__ inline int ext_offset(int hx, int d, int n) {

@@ -46,6 +46,10 @@ constexpr int kThreads = kWaves * 64;
 constexpr int kDepth = 4;
 constexpr int kPrefetchRows = 4 * kDepth;
 
+// Two 16-row fragments per wave (each B operand feeds twice the MFMAs) while
+// the accumulators of both still fit the register file next to the operand ring.
+constexpr bool rf2_supported(size_t tsize, int nb) { return nb <= (tsize == 4 ? 8 : 5); }
+
 struct PencilPlan {
     int d, n, N, m;
     int ells;       // stacked matrices: d, or d + 1 with S_0
@@ -57,7 +61,10 @@ struct PencilPlan {
     int kb;         // (n+2)^d extended indices h'
     int kc;         // h' per chunk (multiple of 16)
     int sk;         // chunks
-    int rt;         // 64-row tiles
+    int rf;         // 16-row fragments per wave (1 or 2)
+    int rows;       // rows k per tile: 64 rf
+    int rt;         // row tiles
+    int nbp;        // 16-column blocks per pass of the cross-wave sum
     int nwg;        // rt * sk workgroups
     int win_cap;    // window capacity (complex elements)
     int c0;         // grid offset of the origin shift
@@ -112,7 +119,7 @@ __device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __
         }
     } else if (section == 1) {
         const int mup = P.mbi * 16;
-        const int nu = P.rt * kRowsPerTile * mup;
+        const int nu = P.rt * P.rows * mup;
         for (int r = first; r < nu; r += stride) {
             const int k = r / mup;
             const int col = r - k * mup;
@@ -162,7 +169,7 @@ struct TilePtrs {
 // One workgroup tile of the S-build: rows 64 rt_i .. +63 of I_n against chunk
 // sk_i of the extended indices h', where L = sk_i * rt + rt_i. See the file
 // comment for the formulation.
-template <typename T, int NB>
+template <typename T, int NB, int RF>
 __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>& ptr, const int L) {
     using T2 = pair_t<T>;
     using M = Mfma<T>;
@@ -172,13 +179,14 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     const T2* __restrict__ up = ptr.up;
     const int* __restrict__ gtab = ptr.gtab;
     T2* __restrict__ part = ptr.part;
+    constexpr int kRows = kRowsPerTile * RF;   // rows k of the tile; RF 16-row fragments per wave
 
     extern __shared__ __align__(16) unsigned char smem[];
     // Phase 1 (K loop): grid window + h' offsets. Phase 2 (U^* reduction): the
-    // same bytes hold the per-workgroup sum of the wave results.
+    // same bytes hold one slab of results per wave.
     T2* win = reinterpret_cast<T2*>(smem);
     int* gt = reinterpret_cast<int*>(smem + align_up(sizeof(T2) * (size_t)P.win_cap, 16));
-    T* esum = reinterpret_cast<T*>(smem);
+    T* slab = reinterpret_cast<T*>(smem);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -186,140 +194,198 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     const bool odd = lane & 1;
     const int sk_i = L / P.rt, rt_i = L - (L / P.rt) * P.rt;
 
-    const int k_first = rt_i * kRowsPerTile;
-    const int k_last = min(k_first + kRowsPerTile - 1, P.N - 1);
+    const int k_first = rt_i * kRows;
+    const int k_last = min(k_first + kRows - 1, P.N - 1);
     const int h_first = sk_i * P.kc;
     const int h_last = min(h_first + P.kc, P.kb) - 1;
-    const int lo = grid_offset_of_index(k_first, P.d, P.n) - gtab[h_last] + P.c0;
-    const int hi = grid_offset_of_index(k_last, P.d, P.n) - gtab[h_first] + P.c0;
+    const int lo = grid_offset_of_index(k_first, P.d, P.n) - ext_offset(h_last, P.d, P.n) + P.c0;
+    const int hi = grid_offset_of_index(k_last, P.d, P.n) - ext_offset(h_first, P.d, P.n) + P.c0;
     const int W = hi - lo + 1;
 
-    for (int w = tid; w < W; w += kThreads) {
-        const double2 v = grid[lo + w];
-        win[w] = T2{(T)v.x, (T)v.y};
+    // Stage the window (converted to T) and the h' offsets, kStage loads per
+    // thread in flight. The offsets are stored transposed per lane group:
+    // gt[g * stride + s] = G(h' = h_first + 4 s + g), so one 16-byte LDS read
+    // gives a lane the offsets of four consecutive K steps.
+    constexpr int kStage = 8;
+    const int ngt = P.kc + kPrefetchRows;
+    const int gstride = ngt >> 2;
+    for (int base = 0; base < max(W, ngt); base += kStage * kThreads) {
+        double2 v[kStage];
+        int o[kStage];
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) {
+            const int w = base + j * kThreads + tid;
+            if (w < W) v[j] = grid[lo + w];
+            if (w < ngt) o[j] = gtab[min(h_first + w, h_last)];
+        }
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) {
+            const int w = base + j * kThreads + tid;
+            if (w < W) win[w] = T2{(T)v[j].x, (T)v[j].y};
+            if (w < ngt) gt[(w & 3) * gstride + (w >> 2)] = o[j];
+        }
     }
-    // h' offsets transposed per lane group: gt[g * stride + s] = G(h' = h_first + 4 s + g),
-    // so one 16-byte LDS read gives a lane the offsets of four consecutive K steps.
-    const int gstride = (P.kc + kPrefetchRows) >> 2;
-    for (int i = tid; i < P.kc + kPrefetchRows; i += kThreads)
-        gt[(i & 3) * gstride + (i >> 2)] = gtab[min(h_first + i, h_last)];
     __syncthreads();
 
-    const int krow = min(k_first + wave * kRowsPerWave + col, P.N - 1);
-    const int gk = grid_offset_of_index(krow, P.d, P.n) + P.c0 - lo;
-
-    acc_t acc[NB];
+    // Rows of this wave: k_first + 16 (RF wave + f) + col for fragment f.
+    const int krow0 = k_first + kRowsPerWave * RF * wave + col;
+    int gk[RF];
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
+    for (int f = 0; f < RF; ++f)
+        gk[f] = grid_offset_of_index(min(krow0 + kRowsPerWave * f, P.N - 1), P.d, P.n) + P.c0 - lo;
+
+    acc_t acc[RF][NB];
+#pragma unroll
+    for (int f = 0; f < RF; ++f)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[f][cb] = acc_t{0, 0, 0, 0};
 
     // K loop over this chunk, 4 h' per step (lane group g takes h' = 4 ks + g).
     // Operands rotate through kDepth register buffers: while the MFMAs of step
-    // ks run, the loads of steps ks+1 .. ks+kDepth-1 are in flight.
+    // ks run, the loads of steps ks+1 .. ks+kDepth-1 are in flight. Every B
+    // operand feeds the RF fragments of the wave.
     const T2* vrow = vp + (size_t)(h_first + g) * P.nrp + col;
     const size_t kstride = (size_t)4 * P.nrp;
     const int nks = P.kc >> 2;
     const int4* gq = reinterpret_cast<const int4*>(gt + g * gstride);
-    T2 a[kDepth];
+    T2 a[kDepth][RF];
     T2 b[kDepth][NB];
+    auto load_a = [&](T2* dst, int off) {
+#pragma unroll
+        for (int f = 0; f < RF; ++f) dst[f] = win[gk[f] - off];
+    };
     auto load_b = [&](T2* dst, int step) {
         const T2* src = vrow + (size_t)step * kstride;
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) dst[cb] = src[cb * 16];
     };
-    auto mma = [&](const T2& av, const T2* bv) {
+    auto mma = [&](const T2* av, const T2* bv) {
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[cb] = M::fma(av.x, bv[cb].x, acc[cb]);
+        for (int f = 0; f < RF; ++f)
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[cb] = M::fma(av.y, bv[cb].y, acc[cb]);
+            for (int cb = 0; cb < NB; ++cb) acc[f][cb] = M::fma(av[f].x, bv[cb].x, acc[f][cb]);
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) acc[f][cb] = M::fma(av[f].y, bv[cb].y, acc[f][cb]);
     };
     int4 gc = gq[0];
-    a[0] = win[gk - gc.x];
-    a[1] = win[gk - gc.y];
-    a[2] = win[gk - gc.z];
+    load_a(a[0], gc.x);
+    load_a(a[1], gc.y);
+    load_a(a[2], gc.z);
     load_b(b[0], 0);
     load_b(b[1], 1);
     load_b(b[2], 2);
     // sched_barrier keeps the compiler from sinking the prefetches next to their use.
     for (int ks = 0; ks < nks; ks += kDepth) {
         const int4 gn = gq[(ks >> 2) + 1];
-        a[3] = win[gk - gc.w];
+        load_a(a[3], gc.w);
         load_b(b[3], ks + 3);
         __builtin_amdgcn_sched_barrier(0);
         mma(a[0], b[0]);
         __builtin_amdgcn_sched_barrier(0);
-        a[0] = win[gk - gn.x];
+        load_a(a[0], gn.x);
         load_b(b[0], ks + 4);
         __builtin_amdgcn_sched_barrier(0);
         mma(a[1], b[1]);
         __builtin_amdgcn_sched_barrier(0);
-        a[1] = win[gk - gn.y];
+        load_a(a[1], gn.y);
         load_b(b[1], ks + 5);
         __builtin_amdgcn_sched_barrier(0);
         mma(a[2], b[2]);
         __builtin_amdgcn_sched_barrier(0);
-        a[2] = win[gk - gn.z];
+        load_a(a[2], gn.z);
         load_b(b[2], ks + 6);
         __builtin_amdgcn_sched_barrier(0);
         mma(a[3], b[3]);
         __builtin_amdgcn_sched_barrier(0);
         gc = gn;
     }
-    __syncthreads();   // the window is dead from here on; its bytes become esum
 
-    // U^* reduction over this wave's 16 rows. The accumulators are the second
-    // MFMA operand directly: element r of lane (g, col) is Y[row(g,r)][16cb+col].
+    // U^* reduction over this wave's rows. The accumulators are the second
+    // MFMA operand directly: element r of lane (g, col) of fragment f is
+    // Y[16 f + row(g,r)][16cb+col] (rows relative to the wave's first row).
     // Output column 2c gets Re(U^* Y)_c and 2c+1 gets Im: with the partner lane's
     // value y' (column j^1), Re = Ur.Yr + Ui.Yi and Im = Ur.Yi - Ui.Yr.
+    // The U pairs of the first kUPre 16-row blocks of U^* are requested before
+    // the barrier, so their latency overlaps the other waves' K loops.
     const int mup = P.mbi * 16;
-    for (int ib = 0; ib < P.mbi; ++ib) {
+    const T2* urow = up + (size_t)(k_first + kRowsPerWave * RF * wave) * mup + col;
+    constexpr int kUPre = RF == 1 ? 2 : 1;
+    T2 upre[kUPre][RF][4];
+#pragma unroll
+    for (int ib = 0; ib < kUPre; ++ib)
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (ib < P.mbi) upre[ib][f][r] = urow[(size_t)(kRowsPerWave * f + M::row(g, r)) * mup + ib * 16];
+    __syncthreads();   // the window is dead from here on; its bytes become the slabs
+
+    // One 16-row block of U^* Y: every wave multiplies its rows and writes its
+    // result into its own slab (lane-major, conflict-free); after a barrier all
+    // threads add the four slabs in wave order and store the block's partial
+    // pairs. The slabs hold nbp column blocks at a time (one pass when they fit).
+    auto reduce_block = [&](int ib, const T2 (&u)[RF][4]) {
         acc_t e[NB];
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) e[cb] = acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int k = k_first + wave * kRowsPerWave + M::row(g, r);
-            const T2 u = up[(size_t)k * mup + ib * 16 + col];
+        for (int f = 0; f < RF; ++f)
 #pragma unroll
-            for (int cb = 0; cb < NB; ++cb) {
-                const T y = acc[cb][r];
-                const T ys = __shfl_xor(y, 1);
-                e[cb] = M::fma(u.x, y, e[cb]);
-                e[cb] = M::fma(u.y, odd ? -ys : ys, e[cb]);
-            }
-        }
-        // Sum the four waves in a fixed order (bitwise reproducible).
-        for (int w = 0; w < kWaves; ++w) {
-            if (wave == w) {
+            for (int r = 0; r < 4; ++r) {
 #pragma unroll
                 for (int cb = 0; cb < NB; ++cb) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        T* dst = &esum[(ib * 16 + M::row(g, r)) * P.nrp + cb * 16 + col];
-                        *dst = (w == 0) ? e[cb][r] : *dst + e[cb][r];
-                    }
+                    const T y = acc[f][cb][r];
+                    const T ys = swap_lane_pair(y);
+                    e[cb] = M::fma(u[f][r].x, y, e[cb]);
+                    e[cb] = M::fma(u[f][r].y, odd ? -ys : ys, e[cb]);
                 }
             }
+        const T2* slab2 = reinterpret_cast<const T2*>(slab);
+        const int rows = min(16, P.m - ib * 16);
+        T2* out = part + (size_t)L * P.m * P.C + (size_t)ib * 16 * P.C;
+        for (int cb0 = 0; cb0 < NB; cb0 += P.nbp) {
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+                if (cb >= cb0 && cb < cb0 + P.nbp)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) slab[((wave * P.nbp + cb - cb0) * 4 + r) * 64 + lane] = e[cb][r];
             __syncthreads();
+            // column pairs c with Re in column 2c of blocks cb0 .. cb0 + nbp - 1
+            const int c_lo = cb0 * 8, nc = min(P.C, (cb0 + P.nbp) * 8) - c_lo;
+            for (int o = tid; o < rows * nc; o += kThreads) {
+                const int il = o / nc, c = c_lo + (o - (o / nc) * nc);
+                const int j = 2 * c;   // Re in column j, Im in column j + 1 (lane + 1)
+                const int s0 = (((j >> 4) - cb0) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 + (j & 15);
+                T2 sum = slab2[s0 >> 1];
+                for (int w = 1; w < kWaves; ++w) {
+                    const T2 v = slab2[(s0 + w * P.nbp * 256) >> 1];
+                    sum.x += v.x;
+                    sum.y += v.y;
+                }
+                out[(size_t)il * P.C + c] = sum;
+            }
+            __syncthreads();   // slabs are rewritten by the next pass
         }
+    };
+#pragma unroll
+    for (int ib = 0; ib < kUPre; ++ib)
+        if (ib < P.mbi) reduce_block(ib, upre[ib]);
+    for (int ib = kUPre; ib < P.mbi; ++ib) {
+        T2 u[RF][4];
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) u[f][r] = urow[(size_t)(kRowsPerWave * f + M::row(g, r)) * mup + ib * 16];
+        reduce_block(ib, u);
     }
-
-    const int tot = P.m * P.C;
-    T2* out = part + (size_t)L * tot;
-    for (int o = tid; o < tot; o += kThreads) {
-        const int i = o / P.C, c = o - (o / P.C) * P.C;
-        out[o] = T2{esum[i * P.nrp + 2 * c], esum[i * P.nrp + 2 * c + 1]};
-    }
-
 }
-
-// Single-instance launch: one workgroup per tile. Workgroups are dealt to the
-// 8 XCDs round-robin; consecutive ids of one XCD get the same chunk of h' so
-// that its packed rows stay in that XCD's L2.
-template <typename T, int NB>
+template <typename T, int NB, int RF>
 __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, TilePtrs<T> ptr) {
     const int id = blockIdx.x;
     const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
-    tile_body<T, NB>(P, ptr, L);
+    tile_body<T, NB, RF>(P, ptr, L);
 }
 
 // One instance of a batch: its plan, its pointers and the first global tile
@@ -358,12 +424,12 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntr
             hi = mid - 1;
     }
     const BatchEntry<T>& e = entries[lo];
-    tile_body<T, NB>(e.P, e.ptr, id - e.tile_begin);
+    tile_body<T, NB, 1>(e.P, e.ptr, id - e.tile_begin);
 }
 
-size_t lds_bytes_for(int win, int kc, int mbi, int nrp, size_t tsize) {
+size_t lds_bytes_for(int win, int kc, int nbp, size_t tsize) {
     const size_t loop = align_up(2 * tsize * (size_t)win, 16) + 4 * ((size_t)kc + kPrefetchRows + 16);
-    const size_t epi = tsize * (size_t)mbi * 16 * nrp;
+    const size_t epi = tsize * (size_t)kWaves * 16 * 16 * nbp;   // one 16 x 16nbp slab per wave
     return align_up(std::max(loop, epi), 16);
 }
 
@@ -390,7 +456,7 @@ int tuned_target(prony_handle_t h, int d, int n, int m, int prec, int batched) {
 // fill the GPU with one launch; batch members use target 1, i.e. no split
 // beyond what the LDS window imposes).
 prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P,
-                         int target_wgs = 0) {
+                         int target_wgs = 0, bool allow_rf2 = false) {
     P = PencilPlan{};
     P.d = d;
     P.n = n;
@@ -403,19 +469,22 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.nrp = 16 * P.nb;
     P.mbi = (m + 15) / 16;
     P.kb = (int)ipow(n + 2, d);
-    P.rt = (P.N + kRowsPerTile - 1) / kRowsPerTile;
+    P.rf = allow_rf2 && rf2_supported(tsize, P.nb) && P.N > kRowsPerTile ? 2 : 1;
+    P.rows = kRowsPerTile * P.rf;
+    P.rt = (P.N + P.rows - 1) / P.rows;
     P.c0 = grid_center(d, n);
 
     const size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
+    P.nbp = std::max(1, std::min(P.nb, (int)(budget / (tsize * kWaves * 16 * 16))));
     const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
     int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), 16);
     kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, 16)));
-    const int rowspan = max_span(P.N, kRowsPerTile, d, n, false);
+    const int rowspan = max_span(P.N, P.rows, d, n, false);
     for (;;) {
         const int colspan = max_span(P.kb, kc, d, n, true);
         const int win = rowspan + colspan + 1;
-        const size_t lds = lds_bytes_for(win, kc, P.mbi, P.nrp, tsize);
+        const size_t lds = lds_bytes_for(win, kc, P.nbp, tsize);
         if (lds <= budget) {
             P.kc = kc;
             P.sk = (P.kb + kc - 1) / kc;
@@ -436,7 +505,7 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.off_v = off;
     off = align_up(off + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
     P.off_u = off;
-    off = align_up(off + t2 * (size_t)P.rt * kRowsPerTile * P.mbi * 16, 256);
+    off = align_up(off + t2 * (size_t)P.rt * P.rows * P.mbi * 16, 256);
     P.off_g = off;
     off = align_up(off + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
     P.off_p = off;
@@ -464,15 +533,15 @@ __global__ __launch_bounds__(kFinishThreads) void pencil_finish_batched(const Ba
                 [&](int o, double re, double im) { store_s(e.P, e.ptr.sigma, e.ptr.S, o, re, im); });
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int RF>
 prony_status_t launch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
     if (P.lds_bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, NB>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, NB, RF>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
         if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
     }
     ProfileScope prof(h, "pencil_tiles");
-    pencil_tiles<T, NB><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
+    pencil_tiles<T, NB, RF><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
     return PRONY_OK;
 }
 
@@ -493,9 +562,11 @@ prony_status_t launch_batched(prony_handle_t h, const BatchEntry<T>* entries, in
 template <typename T>
 prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
     switch (P.nb) {
-#define PRONY_CASE(NBV) \
-    case NBV:           \
-        return launch_tiles<T, NBV>(h, P, ptr);
+#define PRONY_CASE(NBV)                                         \
+    case NBV:                                                   \
+        if constexpr (rf2_supported(sizeof(T), NBV))            \
+            if (P.rf == 2) return launch_tiles<T, NBV, 2>(h, P, ptr); \
+        return launch_tiles<T, NBV, 1>(h, P, ptr);
         PRONY_NB_CASES(PRONY_CASE)
 #undef PRONY_CASE
         default:
@@ -531,7 +602,7 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, const double
     T2* part = reinterpret_cast<T2*>(ws + P.off_p);
 
     const int64_t kbp = (int64_t)P.sk * P.kc + kPrefetchRows;
-    const int64_t largest = std::max<int64_t>(kbp * P.nrp, (int64_t)P.rt * kRowsPerTile * P.mbi * 16);
+    const int64_t largest = std::max<int64_t>(kbp * P.nrp, (int64_t)P.rt * P.rows * P.mbi * 16);
     const int pack_blocks = (int)std::min<int64_t>((largest + 255) / 256, 2 * (int64_t)h->num_cus);
     {
         ProfileScope prof(h, "pencil_pack");
@@ -562,7 +633,7 @@ size_t pencil_workspace_bytes(prony_handle_t h, int d, int n, int m) {
     for (int s0 = 0; s0 < 2; ++s0)
         for (size_t ts : {sizeof(float), sizeof(double)}) {
             PencilPlan P;
-            if (make_plan(h, d, n, m, s0 == 1, ts, P) == PRONY_OK) best = std::max(best, P.ws_bytes);
+            if (make_plan(h, d, n, m, s0 == 1, ts, P, 0, true) == PRONY_OK) best = std::max(best, P.ws_bytes);
         }
     return best;
 }
@@ -593,11 +664,11 @@ extern "C" prony_status_t prony_build_S(prony_handle_t h, int d, int n, int m, c
     const bool s0 = (flags & PRONY_WITH_S0) != 0;
     PencilPlan P;
     if (prec == PRONY_FP32) {
-        if ((st = make_plan(h, d, n, m, s0, sizeof(float), P, tuned_target(h, d, n, m, prec, 0))) != PRONY_OK)
+        if ((st = make_plan(h, d, n, m, s0, sizeof(float), P, tuned_target(h, d, n, m, prec, 0), true)) != PRONY_OK)
             return st;
         return launch_pencil<float>(h, P, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
     }
-    if ((st = make_plan(h, d, n, m, s0, sizeof(double), P, tuned_target(h, d, n, m, prec, 0))) != PRONY_OK)
+    if ((st = make_plan(h, d, n, m, s0, sizeof(double), P, tuned_target(h, d, n, m, prec, 0), true)) != PRONY_OK)
         return st;
     return launch_pencil<double>(h, P, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
 }
@@ -661,7 +732,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         if (!x.f || !x.U || !x.sigma || !x.V || !x.S) return fail(h, PRONY_EINVAL, who + "null pointer");
         // batch members: split into the tuned number of chunks (default 1)
         const int chunks = tuned_target(h, x.d, x.n, x.m, sizeof(T) == 4 ? PRONY_FP32 : PRONY_FP64, 1);
-        const int rt = (int)((N + kRowsPerTile - 1) / kRowsPerTile);
+        const int rt = (int)((N + kRowsPerTile - 1) / kRowsPerTile);   // batch members use one fragment
         prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], std::max(1, chunks) * rt);
         if (st != PRONY_OK) return fail(h, st, who + h->err);
     }
@@ -682,7 +753,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         base[pos] = off;
         const size_t tot = (size_t)P.m * P.C;
         off = align_up(off + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
-        off = align_up(off + t2 * (size_t)P.rt * kRowsPerTile * P.mbi * 16, 256);
+        off = align_up(off + t2 * (size_t)P.rt * P.rows * P.mbi * 16, 256);
         off = align_up(off + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
         off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
     }
@@ -709,7 +780,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         E.ptr.vp = reinterpret_cast<const T2*>(w + o);
         o = align_up(o + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
         E.ptr.up = reinterpret_cast<const T2*>(w + o);
-        o = align_up(o + t2 * (size_t)P.rt * kRowsPerTile * P.mbi * 16, 256);
+        o = align_up(o + t2 * (size_t)P.rt * P.rows * P.mbi * 16, 256);
         E.ptr.gtab = reinterpret_cast<const int*>(w + o);
         o = align_up(o + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
         E.ptr.part = reinterpret_cast<T2*>(w + o);
@@ -729,7 +800,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         cl.tiles = first;
         cl.lds = std::max(cl.lds, P.lds_bytes);
         const int64_t big = std::max<int64_t>(((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp,
-                                              (int64_t)P.rt * kRowsPerTile * P.mbi * 16);
+                                              (int64_t)P.rt * P.rows * P.mbi * 16);
         largest = (int)std::max<int64_t>(largest, (big + 255) / 256);
     }
     B->pack_x = std::min(largest, 64);
