@@ -5,10 +5,23 @@
 namespace prony {
 namespace {
 
-constexpr int kThreads = 64;    // small blocks: grids of 1e4 points still spread over all CUs
+constexpr int kThreads = 256;
+constexpr int kLanesPerPoint = 4;     // the terms of one grid point are split over a lane quad
+constexpr int kPointsPerBlock = kThreads / kLanesPerPoint;
 constexpr int kTermsPerStage = 256;   // nodes/coefficients staged in LDS per pass
 
-// One thread per grid point p; the m terms are staged through LDS in groups.
+// Lane quad q of a block evaluates grid point p; lane s of the quad sums the
+// terms j = s, s+4, ... . The quad adds its four sums in lane order (DPP
+// quad permutations, fixed order), and lane 0 adds the noise and stores.
+template <int S>
+__device__ __forceinline__ double quad_lane(double x) {
+    constexpr int sel = S * 0x55;   // quad_perm [S, S, S, S]
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(v & 0xffffffffll), sel, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), sel, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __global__ __launch_bounds__(kThreads) void samples_kernel(int d, int n, int m, int gsize,
                                                            const double* __restrict__ t,
                                                            const double2* __restrict__ c,
@@ -16,7 +29,8 @@ __global__ __launch_bounds__(kThreads) void samples_kernel(int d, int n, int m, 
                                                            double2* __restrict__ f) {
     __shared__ double st[kTermsPerStage * 3];
     __shared__ double2 sc[kTermsPerStage];
-    const int gidx = blockIdx.x * kThreads + threadIdx.x;
+    const int sub = threadIdx.x & (kLanesPerPoint - 1);
+    const int gidx = blockIdx.x * kPointsPerBlock + threadIdx.x / kLanesPerPoint;
     const int Q = 2 * n + 2;
     double p[3] = {0.0, 0.0, 0.0};
     {
@@ -34,7 +48,7 @@ __global__ __launch_bounds__(kThreads) void samples_kernel(int d, int n, int m, 
         for (int i = threadIdx.x; i < cnt * d; i += kThreads) st[i] = t[base * d + i];
         for (int i = threadIdx.x; i < cnt; i += kThreads) sc[i] = c[base + i];
         __syncthreads();
-        for (int j = 0; j < cnt; ++j) {
+        for (int j = sub; j < cnt; j += kLanesPerPoint) {
             double theta = 0.0;
             for (int l = 0; l < d; ++l) theta = fma(st[j * d + l], p[l], theta);
             theta -= rint(theta);   // exp(-2 pi i x) has period 1 in x
@@ -46,13 +60,17 @@ __global__ __launch_bounds__(kThreads) void samples_kernel(int d, int n, int m, 
             im = fma(cj.y, co, fma(-cj.x, s, im));
         }
     }
-    if (gidx < gsize) {
+    // every lane of the block is active here (no early exit above)
+    const double re_sum = ((quad_lane<0>(re) + quad_lane<1>(re)) + quad_lane<2>(re)) + quad_lane<3>(re);
+    const double im_sum = ((quad_lane<0>(im) + quad_lane<1>(im)) + quad_lane<2>(im)) + quad_lane<3>(im);
+    if (sub == 0 && gidx < gsize) {
+        double2 v = make_double2(re_sum, im_sum);
         if (noise) {
             const double2 nz = noise[gidx];
-            re += nz.x;
-            im += nz.y;
+            v.x += nz.x;
+            v.y += nz.y;
         }
-        f[gidx] = make_double2(re, im);
+        f[gidx] = v;
     }
 }
 
@@ -72,7 +90,7 @@ extern "C" prony_status_t prony_samples(prony_handle_t h, int d, int n, int m, c
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     const int gsize = (int)ipow(2 * n + 2, d);
-    const int blocks = (gsize + kThreads - 1) / kThreads;
+    const int blocks = (gsize + kPointsPerBlock - 1) / kPointsPerBlock;
     {
         ProfileScope prof(h, "samples");
         samples_kernel<<<blocks, kThreads, 0, h->stream>>>(d, n, m, gsize, t, reinterpret_cast<const double2*>(c),

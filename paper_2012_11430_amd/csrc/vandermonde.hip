@@ -2,7 +2,7 @@
 // Algorithm 1, last line): A^T[k,j] = prod_l z_j(l)^{k_l}, gram = (A^T)^* A^T and
 // rhs = (A^T)^* f_I, reduced over k in I_n. FP64 throughout.
 //
-// coeffs_tiles: a workgroup evaluates rows of A^T into LDS 64 at a time
+// coeffs_tiles: a workgroup evaluates rows of A^T into LDS 16 at a time
 //               (integer powers by binary exponentiation), optionally writes
 //               them out, and accumulates its part of the Gram matrix and
 //               right-hand side.
@@ -15,7 +15,7 @@
 namespace prony {
 namespace {
 
-constexpr int kRows = 64;
+constexpr int kRows = 16;        // rows of A^T per chunk
 constexpr int kThreads = 256;
 constexpr int kMaxM = 64;
 
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kFinishThreads) void coeffs_finish(int m, int rows,
                 [&](int e, double re, double im) { emit_gram(m, gram, rhs, e, re, im); });
 }
 
-constexpr int kMaxWorkgroups = 64;
+constexpr int kMaxWorkgroups = 256;   // one 16-row chunk each for N <= 4096
 
 }  // namespace
 
