@@ -34,6 +34,7 @@ struct AdjPlan {
     int d, n, N, m, C;
     int cp;        // complex K padded to a multiple of 8 (2 * KS... see ksteps)
     int ksteps;    // cp / 4
+    int rf, rows;  // 16-row fragments per wave, rows k per tile (64 rf)
     int kb, kc, sk, rt, nwg, win_cap, c0, gsize;
     size_t lds_bytes;
     size_t off_z, off_w, off_g, ws_bytes;
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(256) void adjoint_pack(AdjPlan P, const double2* __
     if (blockIdx.y == 0) {
         // Z[k][c] = sum_i U[k,i] gS_l[i,q] / sigma_q, c = (l-1) m + q; rows padded to
         // whole tiles and columns to cp with zeros
-        const int nz = P.rt * kRows * P.cp;
+        const int nz = P.rt * P.rows * P.cp;
         for (int e = first; e < nz; e += stride) {
             const int k = e / P.cp, c = e - (e / P.cp) * P.cp;
             double re = 0.0, im = 0.0;
@@ -110,75 +111,130 @@ __global__ __launch_bounds__(256) void adjoint_pack(AdjPlan P, const double2* __
 __device__ __forceinline__ void lds_add(float* a, float v) { atomicAdd(a, v); }
 __device__ __forceinline__ void lds_add(double* a, double v) { atomicAdd(a, v); }
 
-template <typename T, int KS>
-__global__ __launch_bounds__(kThreads) void adjoint_tiles(AdjPlan P, const pair_t<T>* __restrict__ zp,
-                                                          const pair_t<T>* __restrict__ wp,
-                                                          const int* __restrict__ gtab, double2* __restrict__ gf) {
+// Two 16-row fragments per wave where the rows of Z kept in registers allow it.
+constexpr bool adj_rf2_supported(size_t tsize, int ks) { return ks <= (tsize == 4 ? 16 : 8); }
+
+template <typename T>
+struct AdjPtrs {
+    const pair_t<T>* zp;
+    const pair_t<T>* wp;
+    const int* gtab;
+    double2* gf;
+};
+
+// LDS: diagonal bins (2 win_cap T) | h' offsets (kc ints) | two staging
+// buffers of one W block (cp rows x 32 pairs each).
+__host__ __device__ inline size_t adj_bins_bytes(int win_cap, size_t tsize) { return align_up(2 * tsize * (size_t)win_cap, 16); }
+__host__ __device__ inline size_t adj_gt_bytes(int kc) { return align_up(4 * (size_t)kc, 16); }
+
+template <typename T, int KS, int RF>
+__device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>& ptr, const int L) {
     using T2 = pair_t<T>;
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
+    constexpr int kTileRows = kRows * RF;
+    constexpr int cp = 4 * KS;              // padded complex K
+    constexpr int kStg = cp * 32 / kThreads;   // staged pairs per thread and block
     extern __shared__ __align__(16) unsigned char smem[];
-    T* bins = reinterpret_cast<T*>(smem);                                        // 2 * win_cap
-    int* gt = reinterpret_cast<int*>(smem + align_up(2 * sizeof(T) * (size_t)P.win_cap, 16));  // kc
+    T* bins = reinterpret_cast<T*>(smem);
+    int* gt = reinterpret_cast<int*>(smem + adj_bins_bytes(P.win_cap, sizeof(T)));
+    T2* wst = reinterpret_cast<T2*>(smem + adj_bins_bytes(P.win_cap, sizeof(T)) + adj_gt_bytes(P.kc));
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, col = lane & 15;
-    const int L = blockIdx.x;
     const int sk_i = L / P.rt, rt_i = L - (L / P.rt) * P.rt;
-    const int k_first = rt_i * kRows;
-    const int k_last = min(k_first + kRows - 1, P.N - 1);
+    const int k_first = rt_i * kTileRows;
+    const int k_last = min(k_first + kTileRows - 1, P.N - 1);
     const int h_first = sk_i * P.kc;
     const int h_last = min(h_first + P.kc, P.kb) - 1;
-    const int lo = grid_offset_of_index(k_first, P.d, P.n) - gtab[h_last] + P.c0;
-    const int hi = grid_offset_of_index(k_last, P.d, P.n) - gtab[h_first] + P.c0;
+    const int lo = grid_offset_of_index(k_first, P.d, P.n) - ext_offset(h_last, P.d, P.n) + P.c0;
+    const int hi = grid_offset_of_index(k_last, P.d, P.n) - ext_offset(h_first, P.d, P.n) + P.c0;
     const int W = hi - lo + 1;
-    for (int i = tid; i < 2 * W; i += kThreads) bins[i] = T(0);
-    for (int i = tid; i < P.kc; i += kThreads) gt[i] = gtab[min(h_first + i, h_last)];
-
-    // A operand (rows of Z) for all K steps, kept in registers
-    const int krow_raw = k_first + wave * 16;
-    T2 a[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) a[s] = zp[(size_t)(krow_raw + col) * P.cp + 4 * s + g];
-    // diagonal bin base of the rows this lane's accumulator elements hold
-    int gk[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        gk[r] = grid_offset_of_index(min(krow_raw + M::row(g, r), P.N - 1), P.d, P.n) + P.c0 - lo;
-    __syncthreads();
-
     const int rowlen = 2 * P.sk * P.kc;
     const int nblk = P.kc / kHBlock;
+
+    // W block hb: rows c < cp, 32 pairs from column 2 (h_first + 16 hb); thread
+    // tid moves pairs e = tid + 256 u (row e / 32, pair e % 32)
+    const T2* wsrc = ptr.wp + (size_t)(tid >> 5) * rowlen + (tid & 31) + 2 * h_first;
+    constexpr int kRowStep = kThreads / 32;   // rows advanced per u
+    T2 stg[kStg];
+#pragma unroll
+    for (int u = 0; u < kStg; ++u) stg[u] = wsrc[(size_t)u * kRowStep * rowlen];
+    for (int i = tid; i < 2 * W; i += kThreads) bins[i] = T(0);
+    for (int i = tid; i < P.kc; i += kThreads) gt[i] = ptr.gtab[min(h_first + i, h_last)];
+
+    // A operand (rows of Z) for all K steps, kept in registers
+    const int krow0 = k_first + 16 * RF * wave + col;
+    T2 a[RF][KS];
+#pragma unroll
+    for (int f = 0; f < RF; ++f)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a[f][s] = ptr.zp[(size_t)(krow0 + 16 * f) * cp + 4 * s + g];
+    // diagonal bin base of the rows this lane's accumulator elements hold
+    int gk[RF][4];
+#pragma unroll
+    for (int f = 0; f < RF; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            gk[f][r] = grid_offset_of_index(min(k_first + 16 * RF * wave + 16 * f + M::row(g, r), P.N - 1), P.d,
+                                            P.n) + P.c0 - lo;
+#pragma unroll
+    for (int u = 0; u < kStg; ++u) wst[tid + u * kThreads] = stg[u];
+    __syncthreads();
+
     for (int hb = 0; hb < nblk; ++hb) {
-        acc_t acc[2] = {acc_t{0, 0, 0, 0}, acc_t{0, 0, 0, 0}};
-        const T2* wcol = wp + (size_t)g * rowlen + 2 * (h_first + hb * kHBlock) + col;
+        // next block's W (the last block fetches itself again) lands while the MFMAs run
+        const int nxt = min(hb + 1, nblk - 1);
+#pragma unroll
+        for (int u = 0; u < kStg; ++u) stg[u] = wsrc[(size_t)u * kRowStep * rowlen + 2 * kHBlock * nxt];
+        const T2* wb = wst + (hb & 1) * cp * 32 + g * 32 + col;
+        acc_t acc[RF][2];
+#pragma unroll
+        for (int f = 0; f < RF; ++f) acc[f][0] = acc[f][1] = acc_t{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const T2 b0 = wcol[(size_t)(4 * s) * rowlen];
-            const T2 b1 = wcol[(size_t)(4 * s) * rowlen + 16];
-            acc[0] = M::fma(a[s].x, b0.x, acc[0]);
-            acc[1] = M::fma(a[s].x, b1.x, acc[1]);
-            acc[0] = M::fma(a[s].y, b0.y, acc[0]);
-            acc[1] = M::fma(a[s].y, b1.y, acc[1]);
+            const T2 b0 = wb[4 * s * 32];
+            const T2 b1 = wb[4 * s * 32 + 16];
+#pragma unroll
+            for (int f = 0; f < RF; ++f) {
+                acc[f][0] = M::fma(a[f][s].x, b0.x, acc[f][0]);
+                acc[f][1] = M::fma(a[f][s].x, b1.x, acc[f][1]);
+            }
+#pragma unroll
+            for (int f = 0; f < RF; ++f) {
+                acc[f][0] = M::fma(a[f][s].y, b0.y, acc[f][0]);
+                acc[f][1] = M::fma(a[f][s].y, b1.y, acc[f][1]);
+            }
         }
-        // element r of lane (g, col) in block cb: row row(g,r), real column
-        // j = 16 cb + col, i.e. h' = hb*16 + j/2 and part j&1
+        // element r of lane (g, col) in block cb of fragment f: row 16 f + row(g,r),
+        // real column j = 16 cb + col, i.e. h' = 16 hb + j/2 and part j&1
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             const int j = cb * 16 + col;
-            const int hl = hb * kHBlock + (j >> 1);
-            const int gh = gt[hl];
+            const int gh = gt[hb * kHBlock + (j >> 1)];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) lds_add(&bins[2 * (gk[r] - gh) + (j & 1)], acc[cb][r]);
+            for (int f = 0; f < RF; ++f)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) lds_add(&bins[2 * (gk[f][r] - gh) + (j & 1)], acc[f][cb][r]);
         }
+        // the other buffer was last read before the previous barrier
+#pragma unroll
+        for (int u = 0; u < kStg; ++u) wst[((hb + 1) & 1) * cp * 32 + tid + u * kThreads] = stg[u];
+        __syncthreads();
     }
-    __syncthreads();
-    double* out = reinterpret_cast<double*>(gf + lo);
+    double* out = reinterpret_cast<double*>(ptr.gf + lo);
     for (int i = tid; i < 2 * W; i += kThreads) {
         const T v = bins[i];
         if (v != T(0)) unsafeAtomicAdd(&out[i], (double)v);
     }
+}
+
+template <typename T, int KS, int RF>
+__global__ __launch_bounds__(kThreads) void adjoint_tiles(AdjPlan P, AdjPtrs<T> ptr) {
+    const int id = blockIdx.x;
+    const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
+    adjoint_body<T, KS, RF>(P, ptr, L);
 }
 
 prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize, AdjPlan& P) {
@@ -191,14 +247,17 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
     P.cp = (int)align_up((size_t)P.C, 8);
     P.ksteps = P.cp / 4;
     P.kb = (int)ipow(n + 2, d);
-    P.rt = (P.N + kRows - 1) / kRows;
+    P.rf = adj_rf2_supported(tsize, P.ksteps) && P.N > kRows ? 2 : 1;
+    P.rows = kRows * P.rf;
+    P.rt = (P.N + P.rows - 1) / P.rows;
     P.c0 = grid_center(d, n);
     P.gsize = (int)ipow(2 * n + 2, d);
-    const size_t budget = std::min<size_t>(h->lds_per_block, 64 * 1024);
-    const int target = 4 * h->num_cus;
+    const size_t staging = 2 * (2 * tsize) * (size_t)P.cp * 32;
+    const size_t budget = std::min<size_t>(h->lds_per_block, staging + 64 * 1024);
+    const int target = 2 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
     int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), kHBlock);
-    kc = std::max(kc, std::min(256, (int)align_up((size_t)P.kb, kHBlock)));
+    kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, kHBlock)));
     auto span = [&](int count, int len, bool ext) {
         int best = 0;
         for (int s = 0; s < count; s += len) {
@@ -209,10 +268,10 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
         }
         return best;
     };
-    const int rowspan = span(P.N, kRows, false);
+    const int rowspan = span(P.N, P.rows, false);
     for (;;) {
         const int win = rowspan + span(P.kb, kc, true) + 1;
-        const size_t lds = align_up(2 * tsize * (size_t)win, 16) + 4 * (size_t)kc;
+        const size_t lds = adj_bins_bytes(win, tsize) + adj_gt_bytes(kc) + staging;
         if (lds <= budget) {
             P.kc = kc;
             P.sk = (P.kb + kc - 1) / kc;
@@ -229,7 +288,7 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
         return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint: problem too large");
     size_t off = 0;
     P.off_z = off;
-    off = align_up(off + t2 * (size_t)P.rt * kRows * P.cp, 256);
+    off = align_up(off + t2 * (size_t)P.rt * P.rows * P.cp, 256);
     P.off_w = off;
     off = align_up(off + t2 * (size_t)P.cp * 2 * P.sk * P.kc, 256);
     P.off_g = off;
@@ -238,12 +297,23 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
     return PRONY_OK;
 }
 
-template <typename T, int KS>
-prony_status_t launch_adj_tiles(prony_handle_t h, const AdjPlan& P, const pair_t<T>* zp, const pair_t<T>* wp,
-                                const int* gt, double2* gf) {
+template <typename T, int KS, int RF>
+prony_status_t launch_adj_tiles(prony_handle_t h, const AdjPlan& P, const AdjPtrs<T>& ptr) {
+    if (P.lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adjoint_tiles<T, KS, RF>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+        if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+    }
     ProfileScope prof(h, "adjoint_tiles");
-    adjoint_tiles<T, KS><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, zp, wp, gt, gf);
+    adjoint_tiles<T, KS, RF><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
     return PRONY_OK;
+}
+
+template <typename T, int KS>
+prony_status_t dispatch_adj_tiles(prony_handle_t h, const AdjPlan& P, const AdjPtrs<T>& ptr) {
+    if constexpr (adj_rf2_supported(sizeof(T), KS))
+        if (P.rf == 2) return launch_adj_tiles<T, KS, 2>(h, P, ptr);
+    return launch_adj_tiles<T, KS, 1>(h, P, ptr);
 }
 
 template <typename T>
@@ -257,7 +327,7 @@ prony_status_t launch_adjoint(prony_handle_t h, const AdjPlan& P, const double* 
     T2* zp = reinterpret_cast<T2*>(ws + P.off_z);
     T2* wp = reinterpret_cast<T2*>(ws + P.off_w);
     int* gt = reinterpret_cast<int*>(ws + P.off_g);
-    const int64_t largest = std::max<int64_t>({(int64_t)P.rt * kRows * P.cp, (int64_t)P.cp * 2 * P.sk * P.kc,
+    const int64_t largest = std::max<int64_t>({(int64_t)P.rt * P.rows * P.cp, (int64_t)P.cp * 2 * P.sk * P.kc,
                                                (int64_t)P.gsize});
     const int blocks = (int)std::min<int64_t>((largest + 255) / 256, 2 * (int64_t)h->num_cus);
     {
@@ -267,11 +337,11 @@ prony_status_t launch_adjoint(prony_handle_t h, const AdjPlan& P, const double* 
             v_cs, reinterpret_cast<const double2*>(gS), zp, wp, gt, reinterpret_cast<double2*>(gf));
     }
     if ((st = check_launch(h, "adjoint_pack")) != PRONY_OK) return st;
-    double2* g2 = reinterpret_cast<double2*>(gf);
+    const AdjPtrs<T> ptr{zp, wp, gt, reinterpret_cast<double2*>(gf)};
     switch (P.ksteps) {
 #define PRONY_ADJ_CASE(K) \
     case K:               \
-        st = launch_adj_tiles<T, K>(h, P, zp, wp, gt, g2); \
+        st = dispatch_adj_tiles<T, K>(h, P, ptr); \
         break;
         PRONY_ADJ_CASE(2)
         PRONY_ADJ_CASE(4)
