@@ -309,12 +309,13 @@ def batched_c3(dev, args):
 
 def adjoint_c4(dev, args):
     """c4: 64 instances (d=2, n=47, m=16); forward FP32 S-build + hand-written
-    adjoint (FP32 accumulate) through torch.autograd. Returns ms per instance."""
+    adjoint (FP32 accumulate) through torch.autograd: all instances in one batched
+    forward and one batched adjoint, and, for comparison, one instance at a time."""
     import numpy as np
     import torch
 
     from paper_2012_11430_amd import api
-    from paper_2012_11430_amd.autograd import pencil
+    from paper_2012_11430_amd.autograd import BatchedPencil, pencil
     from workload import config_instances
 
     insts = config_instances("c4")
@@ -328,28 +329,50 @@ def adjoint_c4(dev, args):
         # S_l(f) - S_l^ref = S_l(f - f0): the loss is formed from the sample difference
         data.append((inst, noisy - clean, Ud, sd, Vd))
 
-    def fwd_bwd():
+    bp = BatchedPencil([(inst.d, inst.n, Ud, sd, Vd) for inst, delta, Ud, sd, Vd in data], prec="fp32")
+    delta_all = torch.cat([delta for inst, delta, *_r in data])
+
+    def fwd_bwd_batched():
+        f = delta_all.detach().requires_grad_(True)
+        torch.sum(torch.abs(bp(f)) ** 2).backward()
+        return f.grad
+
+    def fwd_bwd_loop():
         for inst, delta, Ud, sd, Vd in data:
             f = delta.detach().requires_grad_(True)
             S = pencil(f, inst.d, inst.n, Ud, sd, Vd, "fp32", "fp32")
             torch.sum(torch.abs(S) ** 2).backward()
-    fwd_bwd()
-    reps = 3
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        fwd_bwd()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def timed(fn, reps):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_batched = timed(fwd_bwd_batched, max(5, args.steps // 2))
+    ms_loop = timed(fwd_bwd_loop, 3)
+    # adjoint kernels alone (batched): device time of the backward's library launches
+    gS_all = torch.randn(sum(bp.gs_sizes), dtype=torch.complex128, device=dev)
+    ms_adj = timed(lambda: bp.batch.adjoint(gS_all), max(5, args.steps // 2))
+    ms_fwd = timed(bp.batch.run, max(5, args.steps // 2))
+    bp.close()
     inst = insts[0]
-    flops = len(insts) * 2 * s_flops(inst.d, inst.N, inst.m)
+    f1 = s_flops(inst.d, inst.N, inst.m)
+    flops = len(insts) * 2 * f1
     return {
         "workload": "c4: 64 instances of d=2, n=47, m=16, noise 1e-6; L = sum_l ||S_l - S_l^ref||_F^2 "
                     "= sum_l ||S_l(f - f0)||_F^2",
-        "ms_forward_backward_64": round(ms, 4),
-        "tflops_forward_plus_adjoint": round(flops / (ms * 1e-3) / 1e12, 3),
+        "ms_forward_backward_64_batched": round(ms_batched, 4),
+        "tflops_forward_plus_adjoint_batched": round(flops / (ms_batched * 1e-3) / 1e12, 3),
+        "ms_batched_forward_kernels": round(ms_fwd, 4),
+        "ms_batched_adjoint_kernels": round(ms_adj, 4),
+        "tflops_batched_adjoint_kernels": round(len(insts) * f1 / (ms_adj * 1e-3) / 1e12, 3),
+        "ms_forward_backward_64_one_instance_at_a_time": round(ms_loop, 4),
     }
 
 

@@ -216,10 +216,28 @@ prony_status_t prony_batch_create(prony_handle_t handle, int count, const prony_
 prony_status_t prony_batch_destroy(prony_batch_t batch);
 
 /* Enqueue the S-build of every instance of the batch on the handle's stream:
-   one packing launch for all instances, then one launch per column-block class.
+   one packing launch for all instances, one launch per column-block class and
+   one finishing launch (fixed-order sums, Sigma^{-1}) for all instances.
    Allocates nothing and records no memset, so it can be captured. The handle
    must be the one that created the batch. */
 prony_status_t prony_build_S_batched(prony_handle_t handle, prony_batch_t batch);
+
+/* Adjoint of prony_build_S_batched: prony_build_S_adjoint for every instance of
+   the batch, with its U, sigma and V held fixed, in one packing launch and one
+   launch per class of instances with the same d*m.
+   gS: device buffer of the gradients dL/dS of all instances, concatenated in the
+       order given to prony_batch_create; instance i contributes d_i x m_i x m_i
+       complex128 values.
+   gf: device output, the grid gradients of all instances concatenated in the
+       same order; instance i contributes (2n_i+2)^{d_i} complex128 values, all
+       overwritten.
+   Computes in the batch's precision (window sums added in FP64; bin order not
+   fixed, as for prony_build_S_adjoint). The first call on a batch plans it and
+   allocates the batch's adjoint workspace (synchronously on the handle's stream;
+   PRONY_ECAPTURE under stream capture); later calls allocate nothing. The handle
+   must be the one that created the batch. */
+prony_status_t prony_build_S_adjoint_batched(prony_handle_t handle, prony_batch_t batch,
+                                             const double* gS, double* gf);
 
 /* Capture prony_build_S_batched(handle, batch) into a HIP graph (on a private
    stream) and instantiate it; *graph_exec receives a hipGraphExec_t. */

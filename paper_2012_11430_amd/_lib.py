@@ -57,6 +57,7 @@ SIGNATURES = {
     "prony_batch_create": ([_ptr, _c_int, ctypes.POINTER(InstanceDesc), _c_int, ctypes.POINTER(_ptr)], _c_int),
     "prony_batch_destroy": ([_ptr], _c_int),
     "prony_build_S_batched": ([_ptr, _ptr], _c_int),
+    "prony_build_S_adjoint_batched": ([_ptr, _ptr, _ptr, _ptr], _c_int),
     "prony_graph_capture": ([_ptr, _ptr, ctypes.POINTER(_ptr)], _c_int),
     "prony_graph_launch": ([_ptr, _ptr], _c_int),
     "prony_graph_destroy": ([_ptr], _c_int),

@@ -213,11 +213,12 @@ class Batch:
     """A planned S-build of many instances (prony_batch_create).
 
     instances: sequence of (d, n, f, U, sigma, V) with U, V contiguous N x m
-    complex128 device tensors; the outputs S (d, m, m) are allocated here and
-    exposed as `batch.S`. The tensors are referenced for the batch's lifetime.
+    complex128 device tensors; the outputs S (d, m, m) are allocated here (or
+    taken from `outputs`, contiguous (d, m, m) complex128 tensors) and exposed as
+    `batch.S`. The tensors are referenced for the batch's lifetime.
     """
 
-    def __init__(self, instances, prec: str = "fp32"):
+    def __init__(self, instances, prec: str = "fp32", outputs=None):
         if prec not in ("fp64", "fp32"):
             raise ValueError("prec must be 'fp64' or 'fp32'")
         if not instances:
@@ -235,11 +236,20 @@ class Batch:
             if f.numel() != grid_size(d, n) or U.dim() != 2 or U.shape[0] != N or V.shape != U.shape:
                 raise ValueError(f"instance {i}: shapes do not match d={d}, n={n}")
             m = U.shape[1]
-            S = torch.empty((d, m, m), dtype=torch.complex128, device=dev)
+            if outputs is None:
+                S = torch.empty((d, m, m), dtype=torch.complex128, device=dev)
+            else:
+                S = outputs[i]
+                _require(S, "S", torch.complex128, dev)
+                if S.shape != (d, m, m):
+                    raise ValueError(f"instance {i}: output must be ({d}, {m}, {m})")
             descs[i] = _lib.InstanceDesc(d, n, m, f.data_ptr(), U.data_ptr(), sigma.data_ptr(),
                                          V.data_ptr(), S.data_ptr())
             self._keep += [f, U, sigma, V, S]
             self.S.append(S)
+        self.shapes = [(d, n, U.shape[1]) for d, n, f, U, sigma, V in instances]
+        self.gs_sizes = [d * m * m for d, n, m in self.shapes]
+        self.gf_sizes = [grid_size(d, n) for d, n, m in self.shapes]
         self.device = dev
         self.prec = prec
         self.graph = None
@@ -251,6 +261,24 @@ class Batch:
     def run(self) -> None:
         """Enqueue the S-build of every instance (prony_build_S_batched)."""
         _call("prony_build_S_batched", self.device, self.handle)
+
+    def adjoint(self, gS_all: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Grid gradients of all instances from their dL/dS (prony_build_S_adjoint_batched).
+
+        gS_all: the (d, m, m) gradients of all instances flattened and concatenated
+        in instance order (sum of gs_sizes complex128 values). Returns the grid
+        gradients concatenated the same way (sum of gf_sizes values)."""
+        _require(gS_all, "gS_all", torch.complex128, self.device)
+        if gS_all.numel() != sum(self.gs_sizes):
+            raise ValueError("gS_all must hold sum(gs_sizes) values")
+        if out is None:
+            out = torch.empty(sum(self.gf_sizes), dtype=torch.complex128, device=self.device)
+        else:
+            _require(out, "out", torch.complex128, self.device)
+            if out.numel() != sum(self.gf_sizes):
+                raise ValueError("out must hold sum(gf_sizes) values")
+        _call("prony_build_S_adjoint_batched", self.device, self.handle, _ptr(gS_all), _ptr(out))
+        return out
 
     def capture(self) -> None:
         """Capture run() into a HIP graph (prony_graph_capture)."""

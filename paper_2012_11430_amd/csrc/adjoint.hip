@@ -41,17 +41,17 @@ struct AdjPlan {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void adjoint_pack(AdjPlan P, const double2* __restrict__ U, int64_t u_rs,
-                                                    int64_t u_cs, const double* __restrict__ sigma,
-                                                    const double2* __restrict__ V, int64_t v_rs, int64_t v_cs,
-                                                    const double2* __restrict__ gS, pair_t<T>* __restrict__ zp,
-                                                    pair_t<T>* __restrict__ wp, int* __restrict__ gt,
-                                                    double2* __restrict__ gf) {
+__device__ __forceinline__ void adj_pack_body(const AdjPlan& P, const double2* __restrict__ U, int64_t u_rs,
+                                              int64_t u_cs, const double* __restrict__ sigma,
+                                              const double2* __restrict__ V, int64_t v_rs, int64_t v_cs,
+                                              const double2* __restrict__ gS, pair_t<T>* __restrict__ zp,
+                                              pair_t<T>* __restrict__ wp, int* __restrict__ gt,
+                                              double2* __restrict__ gf, int section) {
     using T2 = pair_t<T>;
     const int stride = gridDim.x * blockDim.x;
     const int first = blockIdx.x * blockDim.x + threadIdx.x;
     const int kbp = P.sk * P.kc;
-    if (blockIdx.y == 0) {
+    if (section == 0) {
         // Z[k][c] = sum_i U[k,i] gS_l[i,q] / sigma_q, c = (l-1) m + q; rows padded to
         // whole tiles and columns to cp with zeros
         const int nz = P.rt * P.rows * P.cp;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void adjoint_pack(AdjPlan P, const double2* __
             }
             zp[e] = T2{(T)re, (T)im};
         }
-    } else if (blockIdx.y == 1) {
+    } else if (section == 1) {
         // W pairs, row c, column j = 2 h' + part: (Re Z) multiplies .x, (Im Z) .y
         const int E = P.n + 2, Pn = P.n + 1;
         const int row = 2 * kbp;
@@ -106,6 +106,16 @@ __global__ __launch_bounds__(256) void adjoint_pack(AdjPlan P, const double2* __
         for (int hx = first; hx < kbp; hx += stride) gt[hx] = ext_offset(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
         for (int p = first; p < P.gsize; p += stride) gf[p] = make_double2(0.0, 0.0);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void adjoint_pack(AdjPlan P, const double2* __restrict__ U, int64_t u_rs,
+                                                    int64_t u_cs, const double* __restrict__ sigma,
+                                                    const double2* __restrict__ V, int64_t v_rs, int64_t v_cs,
+                                                    const double2* __restrict__ gS, pair_t<T>* __restrict__ zp,
+                                                    pair_t<T>* __restrict__ wp, int* __restrict__ gt,
+                                                    double2* __restrict__ gf) {
+    adj_pack_body<T>(P, U, u_rs, u_cs, sigma, V, v_rs, v_cs, gS, zp, wp, gt, gf, blockIdx.y);
 }
 
 __device__ __forceinline__ void lds_add(float* a, float v) { atomicAdd(a, v); }
@@ -237,7 +247,51 @@ __global__ __launch_bounds__(kThreads) void adjoint_tiles(AdjPlan P, AdjPtrs<T> 
     adjoint_body<T, KS, RF>(P, ptr, L);
 }
 
-prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize, AdjPlan& P) {
+// One instance of a batched adjoint: its plan, packed operands, inputs and the
+// offsets of its gS / gf blocks in the caller's concatenated buffers.
+template <typename T>
+struct AdjEntry {
+    AdjPlan P;
+    AdjPtrs<T> ptr;        // gf unused (taken from gf_all + gf_off)
+    const double2* U;
+    const double2* V;
+    const double* sigma;
+    int64_t gs_off, gf_off;   // complex elements
+    int tile_begin;           // first workgroup of this instance within its class launch
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void adjoint_pack_batched(const AdjEntry<T>* __restrict__ entries,
+                                                            const double2* __restrict__ gS_all,
+                                                            double2* __restrict__ gf_all) {
+    const AdjEntry<T>& e = entries[blockIdx.z];
+    const int m = e.P.m;
+    adj_pack_body<T>(e.P, e.U, m, 1, e.sigma, e.V, m, 1, gS_all + e.gs_off, const_cast<pair_t<T>*>(e.ptr.zp),
+                     const_cast<pair_t<T>*>(e.ptr.wp), const_cast<int*>(e.ptr.gtab), gf_all + e.gf_off, blockIdx.y);
+}
+
+template <typename T, int KS, int RF>
+__global__ __launch_bounds__(kThreads) void adjoint_tiles_batched(const AdjEntry<T>* __restrict__ entries, int count,
+                                                                  double2* __restrict__ gf_all) {
+    const int id = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (entries[mid].tile_begin <= id)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const AdjEntry<T>& e = entries[lo];
+    AdjPtrs<T> ptr = e.ptr;
+    ptr.gf = gf_all + e.gf_off;
+    adjoint_body<T, KS, RF>(e.P, ptr, id - e.tile_begin);
+}
+
+// A single adjoint aims at two workgroups per CU; a batch member splits its h'
+// range only into chunks of about 256 (long enough to amortise the window flush;
+// the batch fills the GPU).
+prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize, AdjPlan& P, bool batched = false) {
     P = AdjPlan{};
     P.d = d;
     P.n = n;
@@ -254,7 +308,7 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
     P.gsize = (int)ipow(2 * n + 2, d);
     const size_t staging = 2 * (2 * tsize) * (size_t)P.cp * 32;
     const size_t budget = std::min<size_t>(h->lds_per_block, staging + 64 * 1024);
-    const int target = 2 * h->num_cus;
+    const int target = batched ? P.rt * std::max(1, P.kb / 256) : 2 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
     int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), kHBlock);
     kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, kHBlock)));
@@ -363,6 +417,169 @@ prony_status_t launch_adjoint(prony_handle_t h, const AdjPlan& P, const double* 
     return check_launch(h, "adjoint_tiles");
 }
 
+template <typename T, int KS>
+prony_status_t launch_adj_batched_ks(prony_handle_t h, int rf, const AdjEntry<T>* entries, int count, int tiles,
+                                     size_t lds, double2* gf) {
+    if constexpr (adj_rf2_supported(sizeof(T), KS))
+        if (rf == 2) {
+            if (lds > 65536) {
+                hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adjoint_tiles_batched<T, KS, 2>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+            }
+            ProfileScope prof(h, "adjoint_tiles_batched");
+            adjoint_tiles_batched<T, KS, 2><<<tiles, kThreads, lds, h->stream>>>(entries, count, gf);
+            return PRONY_OK;
+        }
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adjoint_tiles_batched<T, KS, 1>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+    }
+    ProfileScope prof(h, "adjoint_tiles_batched");
+    adjoint_tiles_batched<T, KS, 1><<<tiles, kThreads, lds, h->stream>>>(entries, count, gf);
+    return PRONY_OK;
+}
+
+}  // namespace
+
+struct AdjBatch {
+    void* ws = nullptr;           // device AdjEntry<T>[count] (grouped by class), then operands
+    int count = 0;
+    int pack_x = 1;
+    int64_t gs_elems = 0, gf_elems = 0;   // complex elements of the concatenated gS / gf
+    struct ClassLaunch {
+        int ks, rf, first, count, tiles;
+        size_t lds;
+    };
+    std::vector<ClassLaunch> launches;
+};
+
+prony_status_t adj_batch_free(AdjBatch* a) {
+    prony_status_t st = PRONY_OK;
+    if (a->ws && hipFree(a->ws) != hipSuccess) st = PRONY_EHIP;
+    delete a;
+    return st;
+}
+
+namespace {
+
+template <typename T>
+prony_status_t adj_batch_build(prony_handle_t h, const prony_batch_s* B, AdjBatch* A) {
+    using T2 = pair_t<T>;
+    const int count = B->count;
+    std::vector<AdjPlan> plans(count);
+    std::vector<int64_t> gs_off(count), gf_off(count);
+    for (int i = 0; i < count; ++i) {
+        const prony_instance_t& x = B->inst[i];
+        prony_status_t st = make_adj_plan(h, x.d, x.n, x.m, sizeof(T), plans[i], true);
+        if (st != PRONY_OK) return fail(h, st, "instance " + std::to_string(i) + ": " + h->err);
+        gs_off[i] = A->gs_elems;
+        A->gs_elems += (int64_t)x.d * x.m * x.m;
+        gf_off[i] = A->gf_elems;
+        A->gf_elems += plans[i].gsize;
+    }
+    // classes by (K steps, fragments); inside a class, most workgroups first
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (plans[a].ksteps != plans[b].ksteps) return plans[a].ksteps < plans[b].ksteps;
+        if (plans[a].rf != plans[b].rf) return plans[a].rf < plans[b].rf;
+        return plans[a].nwg > plans[b].nwg;
+    });
+    size_t off = align_up(sizeof(AdjEntry<T>) * (size_t)count, 256);
+    std::vector<size_t> base(count);
+    for (int pos = 0; pos < count; ++pos) {
+        base[pos] = off;
+        off = align_up(off + plans[order[pos]].ws_bytes, 256);
+    }
+    hipError_t e = hipMalloc(&A->ws, off);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        A->ws = nullptr;
+        return fail(h, PRONY_ENOMEM, std::string("batch adjoint workspace allocation failed: ") + hipGetErrorString(e));
+    }
+    unsigned char* w = static_cast<unsigned char*>(A->ws);
+    std::vector<AdjEntry<T>> host(count);
+    int first = 0;
+    int64_t largest = 1;
+    for (int pos = 0; pos < count; ++pos) {
+        const int i = order[pos];
+        const AdjPlan& P = plans[i];
+        const prony_instance_t& x = B->inst[i];
+        AdjEntry<T>& E = host[pos];
+        E.P = P;
+        E.ptr.zp = reinterpret_cast<const T2*>(w + base[pos] + P.off_z);
+        E.ptr.wp = reinterpret_cast<const T2*>(w + base[pos] + P.off_w);
+        E.ptr.gtab = reinterpret_cast<const int*>(w + base[pos] + P.off_g);
+        E.ptr.gf = nullptr;
+        E.U = reinterpret_cast<const double2*>(x.U);
+        E.V = reinterpret_cast<const double2*>(x.V);
+        E.sigma = x.sigma;
+        E.gs_off = gs_off[i];
+        E.gf_off = gf_off[i];
+        const bool new_class = pos == 0 || plans[order[pos - 1]].ksteps != P.ksteps ||
+                               plans[order[pos - 1]].rf != P.rf;
+        if (new_class) {
+            A->launches.push_back({P.ksteps, P.rf, pos, 0, 0, 0});
+            first = 0;
+        }
+        auto& cl = A->launches.back();
+        E.tile_begin = first;
+        first += P.nwg;
+        cl.count += 1;
+        cl.tiles = first;
+        cl.lds = std::max(cl.lds, P.lds_bytes);
+        largest = std::max<int64_t>({largest, (int64_t)P.rt * P.rows * P.cp, (int64_t)P.cp * 2 * P.sk * P.kc,
+                                     (int64_t)P.gsize});
+    }
+    A->count = count;
+    A->pack_x = (int)std::min<int64_t>((largest + 255) / 256, 64);
+    e = hipMemcpyAsync(A->ws, host.data(), sizeof(AdjEntry<T>) * (size_t)count, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "batch adjoint work table upload");
+    return PRONY_OK;
+}
+
+template <typename T>
+prony_status_t adj_batch_launch(prony_handle_t h, const AdjBatch* A, const double* gS, double* gf) {
+    const AdjEntry<T>* entries = static_cast<const AdjEntry<T>*>(A->ws);
+    const double2* gs2 = reinterpret_cast<const double2*>(gS);
+    double2* gf2 = reinterpret_cast<double2*>(gf);
+    {
+        ProfileScope prof(h, "adjoint_pack");
+        adjoint_pack_batched<T><<<dim3(A->pack_x, 3, A->count), 256, 0, h->stream>>>(entries, gs2, gf2);
+    }
+    prony_status_t st = check_launch(h, "adjoint_pack_batched");
+    if (st != PRONY_OK) return st;
+    for (const auto& cl : A->launches) {
+        switch (cl.ks) {
+#define PRONY_ADJ_BCASE(K)                                                                              \
+    case K:                                                                                             \
+        st = launch_adj_batched_ks<T, K>(h, cl.rf, entries + cl.first, cl.count, cl.tiles, cl.lds, gf2); \
+        break;
+            PRONY_ADJ_BCASE(2)
+            PRONY_ADJ_BCASE(4)
+            PRONY_ADJ_BCASE(6)
+            PRONY_ADJ_BCASE(8)
+            PRONY_ADJ_BCASE(10)
+            PRONY_ADJ_BCASE(12)
+            PRONY_ADJ_BCASE(14)
+            PRONY_ADJ_BCASE(16)
+            PRONY_ADJ_BCASE(18)
+            PRONY_ADJ_BCASE(20)
+            PRONY_ADJ_BCASE(22)
+            PRONY_ADJ_BCASE(24)
+#undef PRONY_ADJ_BCASE
+            default:
+                return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint_batched: d*m too large");
+        }
+        if (st != PRONY_OK) return st;
+        if ((st = check_launch(h, "adjoint_tiles_batched")) != PRONY_OK) return st;
+    }
+    return PRONY_OK;
+}
+
 }  // namespace
 
 size_t adjoint_workspace_bytes(prony_handle_t h, int d, int n, int m) {
@@ -404,4 +621,32 @@ extern "C" prony_status_t prony_build_S_adjoint(prony_handle_t h, int d, int n, 
     }
     if ((st = make_adj_plan(h, d, n, m, sizeof(double), P)) != PRONY_OK) return st;
     return launch_adjoint<double>(h, P, U, u_rs, u_cs, sigma, V, v_rs, v_cs, gS, gf);
+}
+
+extern "C" prony_status_t prony_build_S_adjoint_batched(prony_handle_t h, prony_batch_t B, const double* gS,
+                                                        double* gf) {
+    if (!h || !B) return PRONY_EINVAL;
+    if (B->owner != h) return fail(h, PRONY_EINVAL, "prony_build_S_adjoint_batched: batch belongs to another handle");
+    if (!gS || !gf) return fail(h, PRONY_EINVAL, "prony_build_S_adjoint_batched: null pointer");
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    if (!B->adj) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(h->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+            return fail(h, PRONY_ECAPTURE,
+                        "prony_build_S_adjoint_batched: the first call on a batch plans and allocates; "
+                        "make it outside stream capture");
+        AdjBatch* A = new (std::nothrow) AdjBatch();
+        if (!A) return fail(h, PRONY_ENOMEM, "prony_build_S_adjoint_batched: out of host memory");
+        const prony_status_t st = B->prec == PRONY_FP32 ? adj_batch_build<float>(h, B, A)
+                                                        : adj_batch_build<double>(h, B, A);
+        if (st != PRONY_OK) {
+            (void)adj_batch_free(A);
+            return st;
+        }
+        B->adj = A;
+    }
+    return B->prec == PRONY_FP32 ? adj_batch_launch<float>(h, B->adj, gS, gf)
+                                 : adj_batch_launch<double>(h, B->adj, gS, gf);
 }

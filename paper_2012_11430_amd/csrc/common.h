@@ -75,6 +75,10 @@ size_t pencil_workspace_bytes(prony_handle_t h, int d, int n, int m);
 size_t coeffs_workspace_bytes(int d, int n, int m);
 size_t adjoint_workspace_bytes(prony_handle_t h, int d, int n, int m);
 
+// Adjoint state of a batch (planned on the first batched adjoint call; adjoint.hip).
+struct AdjBatch;
+prony_status_t adj_batch_free(AdjBatch* a);
+
 // Common argument validation for (d, n): 1 <= d <= 3, n >= 1, sizes within int32.
 prony_status_t check_dn(prony_handle_t h, int d, int n);
 
@@ -113,3 +117,22 @@ __host__ __device__ inline int grid_shift(int d, int n, int ell) {
 }
 
 }  // namespace prony
+
+// A planned batch of S-builds (pencil.hip) and, once used, its adjoint state.
+struct prony_batch_s {
+    prony_handle_t owner = nullptr;
+    int count = 0;
+    prony_prec_t prec = PRONY_FP64;
+    std::vector<prony_instance_t> inst;   // descriptors in the caller's order
+    void* ws = nullptr;           // entries + per-instance operands and scratch
+    size_t ws_bytes = 0;
+    void* entries = nullptr;      // device BatchEntry<T>[count], grouped by class
+    int pack_x = 1;               // pack blocks per (instance, section)
+    int finish_x = 1;             // finishing workgroups per instance (largest instance)
+    struct ClassLaunch {
+        int nb, first, count, tiles;
+        size_t lds;
+    };
+    std::vector<ClassLaunch> launches;
+    prony::AdjBatch* adj = nullptr;
+};

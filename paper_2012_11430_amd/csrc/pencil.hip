@@ -697,22 +697,6 @@ extern "C" prony_status_t prony_reserve(prony_handle_t h, int d_max, int n_max, 
 // Batches
 // ---------------------------------------------------------------------------
 
-struct prony_batch_s {
-    prony_handle_t owner = nullptr;
-    int count = 0;
-    prony_prec_t prec = PRONY_FP64;
-    void* ws = nullptr;           // entries + per-instance operands and scratch
-    size_t ws_bytes = 0;
-    void* entries = nullptr;      // device BatchEntry<T>[count], grouped by class
-    int pack_x = 1;               // pack blocks per (instance, section)
-    int finish_x = 1;             // finishing workgroups per instance (largest instance)
-    struct ClassLaunch {
-        int nb, first, count, tiles;
-        size_t lds;
-    };
-    std::vector<ClassLaunch> launches;
-};
-
 namespace prony {
 namespace {
 
@@ -864,6 +848,7 @@ extern "C" prony_status_t prony_batch_create(prony_handle_t h, int count, const 
     B->owner = h;
     B->count = count;
     B->prec = prec;
+    B->inst.assign(instances, instances + count);
     const prony_status_t st = prec == PRONY_FP32 ? batch_build<float>(h, count, instances, B)
                                                  : batch_build<double>(h, count, instances, B);
     if (st != PRONY_OK) {
@@ -878,10 +863,11 @@ extern "C" prony_status_t prony_batch_create(prony_handle_t h, int count, const 
 extern "C" prony_status_t prony_batch_destroy(prony_batch_t B) {
     if (!B) return PRONY_EINVAL;
     prony_status_t st = PRONY_OK;
-    if (B->ws) {
+    if (B->ws || B->adj) {
         DeviceGuard g(B->owner->device);
         if (hipStreamSynchronize(B->owner->stream) != hipSuccess) st = PRONY_EHIP;
-        if (hipFree(B->ws) != hipSuccess) st = PRONY_EHIP;
+        if (B->ws && hipFree(B->ws) != hipSuccess) st = PRONY_EHIP;
+        if (B->adj && adj_batch_free(B->adj) != PRONY_OK) st = PRONY_EHIP;
     }
     delete B;
     return st;

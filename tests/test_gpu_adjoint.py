@@ -126,3 +126,56 @@ def test_adjoint_batch_of_c4_instances():
         inst, clean, noisy, U, s, V, ref, gS, grad = _c4_case(idx)
         got = api.build_S_adjoint(_dev(gS), inst.d, inst.n, _dev(U), _dev(s), _dev(V), prec="fp32")
         assert _rel(got.cpu().numpy(), grad) <= TOL["fp32"]
+
+
+def _mixed_instances(seed=900):
+    """Instances of mixed shapes (several d*m classes, one and two row fragments)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = [(2, 47, 16), (1, 70, 9), (2, 3, 5), (2, 12, 32), (3, 2, 4), (3, 6, 20), (1, 1, 1), (2, 47, 16),
+              (2, 9, 6), (1, 300, 32)]
+    out = []
+    for d, n, m in shapes:
+        N = (n + 1) ** d
+        U = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+        V = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+        s = rng.uniform(0.5, 2.0, m)
+        f = rng.standard_normal((2 * n + 2) ** d) + 1j * rng.standard_normal((2 * n + 2) ** d)
+        gS = rng.standard_normal((d, m, m)) + 1j * rng.standard_normal((d, m, m))
+        out.append((d, n, m, f, U, s, V, gS))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_adjoint_matches_oracle_and_single_calls(prec):
+    cases = _mixed_instances()
+    print(f"batched adjoint {prec}: {len(cases)} instances", flush=True)
+    dev_inst = [(d, n, _dev(f), _dev(U), _dev(s), _dev(V)) for d, n, m, f, U, s, V, gS in cases]
+    batch = api.Batch(dev_inst, prec=prec)
+    gS_all = torch.cat([_dev(gS).reshape(-1) for *_, gS in cases])
+    for rep in range(2):   # the second call reuses the planned adjoint
+        gf_all = batch.adjoint(gS_all)
+        torch.cuda.synchronize()
+        parts = torch.split(gf_all, batch.gf_sizes)
+        for (d, n, m, f, U, s, V, gS), got, (_, _, fd, Ud, sd, Vd) in zip(cases, parts, dev_inst):
+            ref = O.pencil_adjoint(gS, d, n, U, s, V)
+            assert _rel(got.cpu().numpy(), ref) <= TOL[prec], (d, n, m, rep)
+            single = api.build_S_adjoint(_dev(gS), d, n, Ud, sd, Vd, prec=prec)
+            assert _rel(got.cpu().numpy(), single.cpu().numpy()) <= TOL[prec]
+    batch.close()
+
+
+def test_batched_autograd_matches_per_instance_autograd():
+    from paper_2012_11430_amd.autograd import BatchedPencil
+    cases = [_c4_case(i) for i in range(4)]
+    fac = [(inst.d, inst.n, _dev(U), _dev(s), _dev(V)) for inst, clean, noisy, U, s, V, ref, gS, grad in cases]
+    bp = BatchedPencil(fac, prec="fp32")
+    f_all = torch.cat([_dev(noisy - clean) for inst, clean, noisy, *_r in cases]).requires_grad_(True)
+    S_all = bp(f_all)
+    torch.sum(torch.abs(S_all) ** 2).backward()
+    grads = torch.split(f_all.grad, bp.gf_sizes)
+    for (inst, clean, noisy, U, s, V, ref, gS, grad), g, S in zip(cases, grads, bp.split(S_all.detach())):
+        # forward against the oracle, gradient against the oracle's adjoint of 2 S(f - f0)
+        S_ref = O.pencil_matrices(noisy - clean, inst.d, inst.n, U, s, V)
+        assert _rel(S.cpu().numpy(), S_ref) <= TOL["fp32"]
+        assert _rel(g.cpu().numpy(), grad) <= TOL["fp32"]
+    bp.close()
