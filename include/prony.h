@@ -179,9 +179,9 @@ prony_status_t prony_coeffs(prony_handle_t handle, int d, int n, int m,
      gf(p) = sum_l sum_{k - h + e_l = p} [U gS_l Sigma^{-1} V^*]_{k,h}.
    U, V, sigma, strides: as for prony_build_S. gS: d x m x m complex128 (gradient
    of S_1..S_d). gf: (2n+2)^d complex128, overwritten. prec selects the MFMA and
-   tile-accumulation type (FP32 or FP64); the window sums are added to gf in
-   FP64. Summation order inside a window bin is not fixed (LDS atomics), so
-   repeated runs agree to rounding, not bitwise. Requires 1 <= m <= min(N, 32). */
+   tile-accumulation type (FP32 or FP64); the diagonal bins and the window sums
+   added to gf are FP64. Summation order inside a bin is not fixed (LDS atomics),
+   so repeated runs agree to rounding, not bitwise. Requires 1 <= m <= min(N, 32). */
 prony_status_t prony_build_S_adjoint(prony_handle_t handle, int d, int n, int m,
                                      const double* U, int64_t u_rs, int64_t u_cs,
                                      const double* sigma,

@@ -12,7 +12,7 @@
 //                writes the G(h') table and zeroes the gradient;
 // adjoint_tiles  one workgroup = 64 rows k x one chunk of h': for every block of
 //                16 h' the tile of Z W^T is formed on MFMA (K = d m), and each
-//                entry is added (LDS atomics, accumulation in T) to the bin of
+//                entry is added (LDS atomics, accumulation in FP64) to the bin of
 //                its diagonal in an LDS copy of the workgroup's grid window; the
 //                window is then added to the gradient in FP64 (device atomics).
 // The accumulation order inside a bin is not fixed: results agree to rounding,
@@ -118,9 +118,6 @@ __global__ __launch_bounds__(256) void adjoint_pack(AdjPlan P, const double2* __
     adj_pack_body<T>(P, U, u_rs, u_cs, sigma, V, v_rs, v_cs, gS, zp, wp, gt, gf, blockIdx.y);
 }
 
-__device__ __forceinline__ void lds_add(float* a, float v) { atomicAdd(a, v); }
-__device__ __forceinline__ void lds_add(double* a, double v) { atomicAdd(a, v); }
-
 // Two 16-row fragments per wave where the rows of Z kept in registers allow it.
 constexpr bool adj_rf2_supported(size_t tsize, int ks) { return ks <= (tsize == 4 ? 16 : 8); }
 
@@ -132,9 +129,11 @@ struct AdjPtrs {
     double2* gf;
 };
 
-// LDS: diagonal bins (2 win_cap T) | h' offsets (kc ints) | two staging
+// LDS: diagonal bins (2 win_cap doubles: LDS FP64 atomics measured several
+// times faster than FP32 ones here, and the bins then add in FP64 for both
+// precisions) | h' offsets (kc ints) | two staging
 // buffers of one W block (cp rows x 32 pairs each).
-__host__ __device__ inline size_t adj_bins_bytes(int win_cap, size_t tsize) { return align_up(2 * tsize * (size_t)win_cap, 16); }
+__host__ __device__ inline size_t adj_bins_bytes(int win_cap) { return align_up(2 * sizeof(double) * (size_t)win_cap, 16); }
 __host__ __device__ inline size_t adj_gt_bytes(int kc) { return align_up(4 * (size_t)kc, 16); }
 
 template <typename T, int KS, int RF>
@@ -146,9 +145,9 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
     constexpr int cp = 4 * KS;              // padded complex K
     constexpr int kStg = cp * 32 / kThreads;   // staged pairs per thread and block
     extern __shared__ __align__(16) unsigned char smem[];
-    T* bins = reinterpret_cast<T*>(smem);
-    int* gt = reinterpret_cast<int*>(smem + adj_bins_bytes(P.win_cap, sizeof(T)));
-    T2* wst = reinterpret_cast<T2*>(smem + adj_bins_bytes(P.win_cap, sizeof(T)) + adj_gt_bytes(P.kc));
+    double* bins = reinterpret_cast<double*>(smem);
+    int* gt = reinterpret_cast<int*>(smem + adj_bins_bytes(P.win_cap));
+    T2* wst = reinterpret_cast<T2*>(smem + adj_bins_bytes(P.win_cap) + adj_gt_bytes(P.kc));
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -171,7 +170,7 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
     T2 stg[kStg];
 #pragma unroll
     for (int u = 0; u < kStg; ++u) stg[u] = wsrc[(size_t)u * kRowStep * rowlen];
-    for (int i = tid; i < 2 * W; i += kThreads) bins[i] = T(0);
+    for (int i = tid; i < 2 * W; i += kThreads) bins[i] = 0.0;
     for (int i = tid; i < P.kc; i += kThreads) gt[i] = ptr.gtab[min(h_first + i, h_last)];
 
     // A operand (rows of Z) for all K steps, kept in registers
@@ -226,7 +225,7 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
 #pragma unroll
             for (int f = 0; f < RF; ++f)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) lds_add(&bins[2 * (gk[f][r] - gh) + (j & 1)], acc[f][cb][r]);
+                for (int r = 0; r < 4; ++r) atomicAdd(&bins[2 * (gk[f][r] - gh) + (j & 1)], (double)acc[f][cb][r]);
         }
         // the other buffer was last read before the previous barrier
 #pragma unroll
@@ -235,8 +234,8 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
     }
     double* out = reinterpret_cast<double*>(ptr.gf + lo);
     for (int i = tid; i < 2 * W; i += kThreads) {
-        const T v = bins[i];
-        if (v != T(0)) unsafeAtomicAdd(&out[i], (double)v);
+        const double v = bins[i];
+        if (v != 0.0) unsafeAtomicAdd(&out[i], v);
     }
 }
 
@@ -325,7 +324,7 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
     const int rowspan = span(P.N, P.rows, false);
     for (;;) {
         const int win = rowspan + span(P.kb, kc, true) + 1;
-        const size_t lds = adj_bins_bytes(win, tsize) + adj_gt_bytes(kc) + staging;
+        const size_t lds = adj_bins_bytes(win) + adj_gt_bytes(kc) + staging;
         if (lds <= budget) {
             P.kc = kc;
             P.sk = (P.kb + kc - 1) / kc;
