@@ -25,6 +25,13 @@ struct prony_handle_s {
     std::string prof_kernel;
     std::vector<hipEvent_t> prof_events;   // pool, pairs (start, stop)
     size_t prof_used = 0;                  // events in use (2 per launch)
+    // auxiliary streams (default priority) and fork/join events for launches
+    // that are independent of each other (the class launches of a batch)
+    static constexpr int kAux = 3;
+    hipStream_t aux[kAux] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kAux] = {};
+    bool aux_ready = false;
 };
 
 namespace prony {
@@ -52,12 +59,16 @@ prony_status_t ensure_workspace(prony_handle_t h, size_t bytes);
 // Brackets one kernel launch with profiling events when the handle profiles `name`.
 class ProfileScope {
   public:
-    ProfileScope(prony_handle_t h, const char* name);
+    ProfileScope(prony_handle_t h, const char* name, hipStream_t stream = nullptr);
     ~ProfileScope();
   private:
     prony_handle_t h_;
+    hipStream_t stream_ = nullptr;
     hipEvent_t stop_ = nullptr;
 };
+
+// Create the auxiliary streams and events (outside stream capture).
+prony_status_t ensure_aux(prony_handle_t h);
 
 // Launch-error check after a kernel launch.
 prony_status_t check_launch(prony_handle_t h, const char* what);
@@ -130,8 +141,9 @@ struct prony_batch_s {
     int pack_x = 1;               // pack blocks per (instance, section)
     int finish_x = 1;             // finishing workgroups per instance (largest instance)
     struct ClassLaunch {
-        int nb, first, count, tiles;
+        int nb, rf, first, count, tiles;
         size_t lds;
+        double work;   // sum of nwg * kc over the class (MFMA work, up to a factor)
     };
     std::vector<ClassLaunch> launches;
     prony::AdjBatch* adj = nullptr;

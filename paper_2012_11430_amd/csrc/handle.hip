@@ -65,17 +65,30 @@ static hipEvent_t next_event(prony_handle_t h) {
     return h->prof_events[h->prof_used++];
 }
 
-ProfileScope::ProfileScope(prony_handle_t h, const char* name) : h_(h) {
+ProfileScope::ProfileScope(prony_handle_t h, const char* name, hipStream_t stream)
+    : h_(h), stream_(stream ? stream : h->stream) {
     if (h->prof_kernel.empty() || h->prof_kernel != name) return;
     hipEvent_t start = next_event(h);
     hipEvent_t stop = next_event(h);
     if (!start || !stop) return;
-    if (hipEventRecord(start, h->stream) != hipSuccess) return;
+    if (hipEventRecord(start, stream_) != hipSuccess) return;
     stop_ = stop;
 }
 
 ProfileScope::~ProfileScope() {
-    if (stop_) (void)hipEventRecord(stop_, h_->stream);
+    if (stop_) (void)hipEventRecord(stop_, stream_);
+}
+
+prony_status_t ensure_aux(prony_handle_t h) {
+    if (h->aux_ready) return PRONY_OK;
+    hipError_t e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
+    for (int a = 0; a < prony_handle_s::kAux && e == hipSuccess; ++a) {
+        e = hipStreamCreateWithFlags(&h->aux[a], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join[a], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "auxiliary stream setup");
+    h->aux_ready = true;
+    return PRONY_OK;
 }
 
 }  // namespace prony
@@ -146,6 +159,14 @@ extern "C" prony_status_t prony_destroy(prony_handle_t h) {
         if (hipFree(h->ws) != hipSuccess) st = PRONY_EHIP;
     }
     for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
+    for (int a = 0; a < prony_handle_s::kAux; ++a) {
+        if (h->aux[a]) {
+            if (hipStreamSynchronize(h->aux[a]) != hipSuccess) st = PRONY_EHIP;
+            (void)hipStreamDestroy(h->aux[a]);
+        }
+        if (h->join[a]) (void)hipEventDestroy(h->join[a]);
+    }
+    if (h->fork) (void)hipEventDestroy(h->fork);
     delete h;
     return st;
 }

@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void pencil_pack_batched(const BatchEntry<T>* 
 // decreasing work: workgroup `id` finds its instance by binary search over the
 // tile offsets (the hardware dispatches workgroups in id order, so the longest
 // tiles start first).
-template <typename T, int NB>
+template <typename T, int NB, int RF>
 __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntry<T>* __restrict__ entries,
                                                                  int count) {
     const int id = blockIdx.x;
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntr
             hi = mid - 1;
     }
     const BatchEntry<T>& e = entries[lo];
-    tile_body<T, NB, 1>(e.P, e.ptr, id - e.tile_begin);
+    tile_body<T, NB, RF>(e.P, e.ptr, id - e.tile_begin);
 }
 
 size_t lds_bytes_for(int win, int kc, int nbp, size_t tsize) {
@@ -545,15 +545,16 @@ prony_status_t launch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtr
     return PRONY_OK;
 }
 
-template <typename T, int NB>
-prony_status_t launch_batched(prony_handle_t h, const BatchEntry<T>* entries, int count, int tiles, size_t lds) {
+template <typename T, int NB, int RF>
+prony_status_t launch_batched(prony_handle_t h, const BatchEntry<T>* entries, int count, int tiles, size_t lds,
+                              hipStream_t stream) {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles_batched<T, NB>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles_batched<T, NB, RF>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
     }
-    ProfileScope prof(h, "pencil_tiles_batched");
-    pencil_tiles_batched<T, NB><<<tiles, kThreads, lds, h->stream>>>(entries, count);
+    ProfileScope prof(h, "pencil_tiles_batched", stream);
+    pencil_tiles_batched<T, NB, RF><<<tiles, kThreads, lds, stream>>>(entries, count);
     return PRONY_OK;
 }
 
@@ -575,12 +576,14 @@ prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TileP
 }
 
 template <typename T>
-prony_status_t dispatch_batched(prony_handle_t h, int nb, const BatchEntry<T>* entries, int count, int tiles,
-                                size_t lds) {
+prony_status_t dispatch_batched(prony_handle_t h, int nb, int rf, const BatchEntry<T>* entries, int count, int tiles,
+                                size_t lds, hipStream_t stream) {
     switch (nb) {
-#define PRONY_CASE(NBV) \
-    case NBV:           \
-        return launch_batched<T, NBV>(h, entries, count, tiles, lds);
+#define PRONY_CASE(NBV)                                                                        \
+    case NBV:                                                                                  \
+        if constexpr (rf2_supported(sizeof(T), NBV))                                           \
+            if (rf == 2) return launch_batched<T, NBV, 2>(h, entries, count, tiles, lds, stream); \
+        return launch_batched<T, NBV, 1>(h, entries, count, tiles, lds, stream);
         PRONY_NB_CASES(PRONY_CASE)
 #undef PRONY_CASE
         default:
@@ -716,16 +719,18 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         if (!x.f || !x.U || !x.sigma || !x.V || !x.S) return fail(h, PRONY_EINVAL, who + "null pointer");
         // batch members: split into the tuned number of chunks (default 1)
         const int chunks = tuned_target(h, x.d, x.n, x.m, sizeof(T) == 4 ? PRONY_FP32 : PRONY_FP64, 1);
-        const int rt = (int)((N + kRowsPerTile - 1) / kRowsPerTile);   // batch members use one fragment
-        prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], std::max(1, chunks) * rt);
+        const int rf = rf2_supported(sizeof(T), (2 * x.d * x.m + 15) / 16) && N > kRowsPerTile ? 2 : 1;
+        const int rt = (int)((N + kRowsPerTile * rf - 1) / (kRowsPerTile * rf));
+        prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], std::max(1, chunks) * rt, true);
         if (st != PRONY_OK) return fail(h, st, who + h->err);
     }
-    // classes by column-block count; inside a class, longest tiles first
+    // classes by (column-block count, row fragments); inside a class, longest tiles first
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         if (plans[a].nb != plans[b].nb) return plans[a].nb < plans[b].nb;
-        return (int64_t)plans[a].kc > (int64_t)plans[b].kc;
+        if (plans[a].rf != plans[b].rf) return plans[a].rf < plans[b].rf;
+        return (int64_t)plans[a].kc * plans[a].rf > (int64_t)plans[b].kc * plans[b].rf;
     });
     // workspace layout: entries, then per instance vp | up | gt | part
     const size_t t2 = 2 * sizeof(T);
@@ -772,9 +777,9 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         E.ptr.S = reinterpret_cast<double2*>(x.S);
         E.U = reinterpret_cast<const double2*>(x.U);
         E.V = reinterpret_cast<const double2*>(x.V);
-        const bool new_class = pos == 0 || plans[order[pos - 1]].nb != P.nb;
+        const bool new_class = pos == 0 || plans[order[pos - 1]].nb != P.nb || plans[order[pos - 1]].rf != P.rf;
         if (new_class) {
-            B->launches.push_back({P.nb, pos, 0, 0, 0});
+            B->launches.push_back({P.nb, P.rf, pos, 0, 0, 0, 0.0});
             first = 0;
         }
         auto& cl = B->launches.back();
@@ -783,6 +788,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         cl.count += 1;
         cl.tiles = first;
         cl.lds = std::max(cl.lds, P.lds_bytes);
+        cl.work += (double)P.nwg * P.kc * P.rf * P.nb;
         const int64_t big = std::max<int64_t>(((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp,
                                               (int64_t)P.rt * P.rows * P.mbi * 16);
         largest = (int)std::max<int64_t>(largest, (big + 255) / 256);
@@ -806,10 +812,39 @@ prony_status_t batch_launch(prony_handle_t h, prony_batch_s* B) {
     }
     prony_status_t st = check_launch(h, "pencil_pack_batched");
     if (st != PRONY_OK) return st;
-    for (const auto& cl : B->launches) {
-        st = dispatch_batched<T>(h, cl.nb, entries + cl.first, cl.count, cl.tiles, cl.lds);
+    // The class launches are independent: they run on the handle's stream and up
+    // to kAux auxiliary streams (forked after the packing launch, joined before
+    // the finishing launch), each class on the lane with the least work so far
+    // (largest classes first), so that the tails of the classes overlap.
+    const int nl = h->aux_ready ? std::min<int>(1 + prony_handle_s::kAux, (int)B->launches.size()) : 1;
+    hipError_t e = hipSuccess;
+    if (nl > 1) {
+        e = hipEventRecord(h->fork, h->stream);
+        for (int a = 0; a + 1 < nl && e == hipSuccess; ++a) e = hipStreamWaitEvent(h->aux[a], h->fork, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "batch fork");
+    }
+    std::vector<int> by_work(B->launches.size());
+    for (size_t c = 0; c < by_work.size(); ++c) by_work[c] = (int)c;
+    std::stable_sort(by_work.begin(), by_work.end(),
+                     [&](int a, int b) { return B->launches[a].work > B->launches[b].work; });
+    double load[1 + prony_handle_s::kAux] = {};
+    for (int c : by_work) {
+        const auto& cl = B->launches[c];
+        int lane = 0;
+        for (int l = 1; l < nl; ++l)
+            if (load[l] < load[lane]) lane = l;
+        load[lane] += cl.work;
+        hipStream_t s = lane == 0 ? h->stream : h->aux[lane - 1];
+        st = dispatch_batched<T>(h, cl.nb, cl.rf, entries + cl.first, cl.count, cl.tiles, cl.lds, s);
         if (st != PRONY_OK) return st;
         if ((st = check_launch(h, "pencil_tiles_batched")) != PRONY_OK) return st;
+    }
+    if (nl > 1) {
+        for (int a = 0; a + 1 < nl && e == hipSuccess; ++a) {
+            e = hipEventRecord(h->join[a], h->aux[a]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->join[a], 0);
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "batch join");
     }
     {
         ProfileScope prof(h, "pencil_finish");
@@ -843,6 +878,8 @@ extern "C" prony_status_t prony_batch_create(prony_handle_t h, int count, const 
     }
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    prony_status_t ast = ensure_aux(h);
+    if (ast != PRONY_OK) return ast;
     prony_batch_s* B = new (std::nothrow) prony_batch_s();
     if (!B) return fail(h, PRONY_ENOMEM, "prony_batch_create: out of host memory");
     B->owner = h;
