@@ -150,25 +150,39 @@ def main():
     api.profile_enable(dev, None)
     tiles_avg_ms = tiles_ms / max(1, launches)
 
-    # ---------------- the S-build alone, both precisions (same inputs)
+    # ---------------- the S-build alone, both precisions (same inputs): per-call
+    # HIP events, median (and mean) over `steps` calls after the warm-up
+    def per_call_ms(fn, reps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in evs:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in evs]
+
     sbuild = {}
     S_out = {}
     for prec in ("fp32", "fp64"):
         for _ in range(args.warmup):
             api.build_S(f, d, n, Ud, sd, Vd, prec=prec, out=Sbuf)
         api.profile_enable(dev, DOMINANT)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.steps):
-            api.build_S(f, d, n, Ud, sd, Vd, prec=prec, out=Sbuf)
-        e1.record()
-        torch.cuda.synchronize()
+        times = per_call_ms(lambda: api.build_S(f, d, n, Ud, sd, Vd, prec=prec, out=Sbuf), max(20, args.steps))
         nl, tot = api.profile_read(dev)
         api.profile_enable(dev, None)
-        ms = e0.elapsed_time(e1) / args.steps
-        sbuild[prec] = {"ms": round(ms, 5), "tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 3),
-                        "tiles_ms": round(tot / max(1, nl), 5)}
+        med = float(np.median(times))
+        sbuild[prec] = {"ms_median": round(med, 5), "ms_mean": round(float(np.mean(times)), 5),
+                        "tflops": round(s_flops(d, N, m) / (med * 1e-3) / 1e12, 3),
+                        "tiles_ms": round(tot / max(1, nl), 5), "calls": len(times)}
         S_out[prec] = Sbuf.cpu().numpy().copy()
+
+    # ---------------- T alone (HBM-write-bound): GB/s against the 8 TB/s peak
+    for _ in range(args.warmup):
+        api.build_T(f, d, n, 0, out=Tbuf)
+    t_times = per_call_ms(lambda: api.build_T(f, d, n, 0, out=Tbuf), max(20, args.steps))
+    t_med = float(np.median(t_times))
+    build_T = {"ms_median": round(t_med, 5), "bytes": 16 * N * N,
+               "GB_per_s": round(16 * N * N / (t_med * 1e-3) / 1e9, 1), "peak_GB_per_s": 8000.0}
 
     F = s_flops(d, N, m)
     value = F / (ms_step * 1e-3) / 1e12
@@ -214,6 +228,7 @@ def main():
             "flops_per_launch": tile_flops(d, N, m),
         },
         "s_build": sbuild,
+        "build_T": build_T,
         "tuned_split_targets": tuned,
         "wall_s_timed": round(wall, 4),
     }
@@ -377,10 +392,11 @@ def adjoint_c4(dev, args):
 
 
 def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, grid_gpu):
-    """The CPU oracle timed on `steps` whole steps of the same workload; also the
-    relative error of the GPU S-build against the oracle on the same inputs."""
+    """The CPU oracle timed on `steps` whole steps of the same workload, and its
+    S-build alone (median of 3, all host threads and one thread); also the relative
+    error of the GPU S-build against the oracle on the same inputs."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import prony_oracle as O
 
@@ -395,9 +411,23 @@ def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, grid_gpu):
         S = O.pencil_matrices(grid, d, n, U, sig, V)
         O.coefficient_products(z, grid, d, n)
     el = (time.perf_counter() - t0) / steps
+
+    def s_only():
+        t = time.perf_counter()
+        O.pencil_matrices(grid, d, n, U, sig, V)
+        return time.perf_counter() - t
+    s_all = float(np.median([s_only() for _ in range(3)]))
+    with threadpool_limits(limits=1):
+        s_one = s_only()
     F = s_flops(d, inst.N, inst.m)
     rel = {p: max(float(np.linalg.norm(S_gpu[p][l] - S[l]) / np.linalg.norm(S[l])) for l in range(d))
            for p in S_gpu}
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": round(F / el / 1e12, 6),
         "unit": "TFLOP/s",
@@ -405,6 +435,9 @@ def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, grid_gpu):
         "kind": "oracle",
         "sample": f"{steps} whole oracle steps (samples, T, S_1..S_d, Gram/rhs) of the same workload, "
                   f"{el:.3f} s per step",
+        "cpu_model": model,
+        "s_build_only": {"s_median_all_threads": round(s_all, 4), "tflops_all_threads": round(F / s_all / 1e12, 6),
+                         "s_one_thread": round(s_one, 4), "tflops_one_thread": round(F / s_one / 1e12, 6)},
         "s_rel_err_vs_oracle": {p: float(f"{v:.3e}") for p, v in rel.items()},
         "samples_max_abs_err": float(f"{np.max(np.abs(grid_gpu - grid)):.3e}"),
     }
