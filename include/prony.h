@@ -188,6 +188,23 @@ prony_status_t prony_build_S_adjoint(prony_handle_t handle, int d, int n, int m,
                                      const double* V, int64_t v_rs, int64_t v_cs,
                                      const double* gS, prony_prec_t prec, double* gf);
 
+/* Product of the multilevel Toeplitz matrix T = [f(k - h)]_{k,h in I_n} (Sec. 1), or of
+   its conjugate transpose, with a block of r columns: the two products of every sweep
+   of the block power method for the SVD of T (Sec. 2.2, Algorithm 3):
+     Y = T X      (adjoint = 0),     Y = T^* X    (adjoint = 1),
+   computed from the sample grid without forming T (T^* is the Toeplitz matrix of
+   g(p) = conj(f(-p))).
+   f:    sample grid ((2n+2)^d complex128; only {-n..n}^d is read).
+   X:    N x r complex128, row-major with leading dimension ldx >= r (device).
+   Y:    N x r complex128 output, row-major with leading dimension ldy >= r; must not
+         overlap X.
+   prec: MFMA and tile-accumulation type (FP32 or FP64); the chunk partials are added
+         in FP64 in a fixed order (bitwise reproducible). Requires 1 <= r <= 64.
+   Uses the handle's workspace (grown as needed; PRONY_ECAPTURE if it must grow
+   under stream capture). */
+prony_status_t prony_toeplitz_mm(prony_handle_t handle, int d, int n, int adjoint, const double* f, int r,
+                                 const double* X, int64_t ldx, prony_prec_t prec, double* Y, int64_t ldy);
+
 /* ---- many instances: one planned launch sequence, graph capture ------------- */
 
 typedef struct prony_batch_s* prony_batch_t;

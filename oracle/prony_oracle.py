@@ -103,6 +103,13 @@ def toeplitz(grid: np.ndarray, d: int, n: int, ell: int) -> np.ndarray:
     return out
 
 
+def toeplitz_product(grid: np.ndarray, d: int, n: int, X: np.ndarray, adjoint: bool = False) -> np.ndarray:
+    """T X or T^* X with T the multilevel Toeplitz matrix of the grid (the two block
+    products of every sweep of Algorithm 3, Sec. 2.2)."""
+    T = toeplitz(grid, d, n, 0)
+    return (T.conj().T if adjoint else T) @ X
+
+
 # ---------------------------------------------------------------------------
 # Reduced SVD of T (Sec. 1 eq. T_svd; Sec. 2.2 Algorithm 3)
 # ---------------------------------------------------------------------------

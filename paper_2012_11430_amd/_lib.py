@@ -58,6 +58,7 @@ SIGNATURES = {
     "prony_batch_destroy": ([_ptr], _c_int),
     "prony_build_S_batched": ([_ptr, _ptr], _c_int),
     "prony_build_S_adjoint_batched": ([_ptr, _ptr, _ptr, _ptr], _c_int),
+    "prony_toeplitz_mm": ([_ptr, _c_int, _c_int, _c_int, _ptr, _c_int, _ptr, _c_i64, _c_int, _ptr, _c_i64], _c_int),
     "prony_graph_capture": ([_ptr, _ptr, ctypes.POINTER(_ptr)], _c_int),
     "prony_graph_launch": ([_ptr, _ptr], _c_int),
     "prony_graph_destroy": ([_ptr], _c_int),

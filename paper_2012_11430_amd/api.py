@@ -170,6 +170,32 @@ def build_S_adjoint(gS: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: to
     return out
 
 
+def toeplitz_mm(f: torch.Tensor, d: int, n: int, X: torch.Tensor, adjoint: bool = False, prec: str = "fp64",
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """Y = T X or T^* X for the multilevel Toeplitz matrix T of the grid f, without
+    forming T (prony_toeplitz_mm). X: N x r complex128 with unit column stride."""
+    _require(f, "f", torch.complex128)
+    dev = f.device
+    _require(X, "X", torch.complex128, dev, contiguous=False)
+    N = (n + 1) ** d
+    if f.numel() != grid_size(d, n):
+        raise ValueError("f must hold the (2n+2)^d sample grid")
+    if X.dim() != 2 or X.shape[0] != N or X.stride(1) != 1:
+        raise ValueError("X must be N x r with unit column stride")
+    if prec not in ("fp64", "fp32"):
+        raise ValueError("prec must be 'fp64' or 'fp32'")
+    r = X.shape[1]
+    if out is None:
+        out = torch.empty((N, r), dtype=torch.complex128, device=dev)
+    else:
+        _require(out, "out", torch.complex128, dev, contiguous=False)
+        if out.shape != (N, r) or out.stride(1) != 1:
+            raise ValueError("out must be N x r with unit column stride")
+    _call("prony_toeplitz_mm", dev, d, n, 1 if adjoint else 0, _ptr(f), r, _ptr(X), X.stride(0),
+          _lib.PRONY_FP32 if prec == "fp32" else _lib.PRONY_FP64, _ptr(out), out.stride(0))
+    return out
+
+
 def coeffs(z: torch.Tensor, f: torch.Tensor, d: int, n: int, want_AT: bool = False):
     """Gram (A^T)^* A^T and rhs (A^T)^* f_I (prony_coeffs); optionally A^T (N x m)."""
     _require(z, "z", torch.complex128)

@@ -52,13 +52,15 @@ constexpr bool rf2_supported(size_t tsize, int nb) { return nb <= (tsize == 4 ? 
 
 struct PencilPlan {
     int d, n, N, m;
+    int mode;       // 0: S-build (extended h', U^* epilogue); 1: product Y = T X (h in I_n)
+    int conj_grid;  // product mode: stage conj(f(-p)), i.e. multiply by T^* instead of T
     int ells;       // stacked matrices: d, or d + 1 with S_0
     int first_ell;  // 0 with S_0, else 1
     int C;          // complex columns ells * m
     int nb;         // 16-wide blocks of the 2C real columns
     int nrp;        // 16 * nb
     int mbi;        // 16-row blocks of the m output rows
-    int kb;         // (n+2)^d extended indices h'
+    int kb;         // (n+2)^d extended indices h' (N plain indices h in product mode)
     int kc;         // h' per chunk (multiple of 16)
     int sk;         // chunks
     int rf;         // 16-row fragments per wave (1 or 2)
@@ -73,6 +75,12 @@ struct PencilPlan {
     size_t off_v, off_u, off_g, off_p, ws_bytes;
 };
 
+
+// Grid offset of the K index hx: extended h' for the S-build, plain h of I_n
+// for the product.
+__host__ __device__ inline int h_offset(const PencilPlan& P, int hx) {
+    return P.mode ? grid_offset_of_index(hx, P.d, P.n) : ext_offset(hx, P.d, P.n);
+}
 
 // Packs, per call: (y = 0) the stacked shifted factors V_l in the pair layout,
 // rows h' of the extended index set padded with zeros to sk*kc + kPrefetchRows;
@@ -95,7 +103,11 @@ __device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __
             const int j = i - hx * P.nrp;
             const int c = j >> 1;
             double vr = 0.0, vi = 0.0;
-            if (hx < P.kb && c < P.C) {
+            if (P.mode && hx < P.N && c < P.C) {
+                const double2 v = V[hx * v_rs + c * v_cs];
+                vr = v.x;
+                vi = v.y;
+            } else if (!P.mode && hx < P.kb && c < P.C) {
                 const int li = c / P.m, q = c - li * P.m;
                 const int ell = li + P.first_ell;   // 0 = T itself, l = shift along axis l
                 int rem = hx, idx = 0, scale = 1;
@@ -118,6 +130,7 @@ __device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __
             vp[i] = (j & 1) ? T2{(T)vi, (T)vr} : T2{(T)vr, (T)(-vi)};
         }
     } else if (section == 1) {
+        if (P.mode) return;   // the product has no U^* epilogue
         const int mup = P.mbi * 16;
         const int nu = P.rt * P.rows * mup;
         for (int r = first; r < nu; r += stride) {
@@ -132,7 +145,7 @@ __device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __
             up[r] = T2{(T)ur, (T)ui};
         }
     } else {
-        for (int hx = first; hx < kbp; hx += stride) gt[hx] = ext_offset(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
+        for (int hx = first; hx < kbp; hx += stride) gt[hx] = h_offset(P, hx < P.kb ? hx : P.kb - 1);
     }
 }
 
@@ -169,7 +182,7 @@ struct TilePtrs {
 // One workgroup tile of the S-build: rows 64 rt_i .. +63 of I_n against chunk
 // sk_i of the extended indices h', where L = sk_i * rt + rt_i. See the file
 // comment for the formulation.
-template <typename T, int NB, int RF>
+template <typename T, int NB, int RF, int MODE>
 __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>& ptr, const int L) {
     using T2 = pair_t<T>;
     using M = Mfma<T>;
@@ -198,9 +211,12 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     const int k_last = min(k_first + kRows - 1, P.N - 1);
     const int h_first = sk_i * P.kc;
     const int h_last = min(h_first + P.kc, P.kb) - 1;
-    const int lo = grid_offset_of_index(k_first, P.d, P.n) - ext_offset(h_last, P.d, P.n) + P.c0;
-    const int hi = grid_offset_of_index(k_last, P.d, P.n) - ext_offset(h_first, P.d, P.n) + P.c0;
+    const int lo = grid_offset_of_index(k_first, P.d, P.n) - h_offset(P, h_last) + P.c0;
+    const int hi = grid_offset_of_index(k_last, P.d, P.n) - h_offset(P, h_first) + P.c0;
     const int W = hi - lo + 1;
+    // T^* X multiplies by the Toeplitz matrix of g(p) = conj(f(-p)): grid offsets
+    // are affine in p, so g at offset o is conj(f at 2 c0 - o).
+    const bool reflect = MODE == 1 && P.conj_grid;
 
     // Stage the window (converted to T) and the h' offsets, kStage loads per
     // thread in flight. The offsets are stored transposed per lane group:
@@ -215,13 +231,13 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 #pragma unroll
         for (int j = 0; j < kStage; ++j) {
             const int w = base + j * kThreads + tid;
-            if (w < W) v[j] = grid[lo + w];
+            if (w < W) v[j] = grid[reflect ? 2 * P.c0 - (lo + w) : lo + w];
             if (w < ngt) o[j] = gtab[min(h_first + w, h_last)];
         }
 #pragma unroll
         for (int j = 0; j < kStage; ++j) {
             const int w = base + j * kThreads + tid;
-            if (w < W) win[w] = T2{(T)v[j].x, (T)v[j].y};
+            if (w < W) win[w] = T2{(T)v[j].x, reflect ? -(T)v[j].y : (T)v[j].y};
             if (w < ngt) gt[(w & 3) * gstride + (w >> 2)] = o[j];
         }
     }
@@ -300,6 +316,21 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         mma(a[3], b[3]);
         __builtin_amdgcn_sched_barrier(0);
         gc = gn;
+    }
+
+    if constexpr (MODE == 1) {
+        // Product: this chunk's part of Y = T X for the wave's rows, real column
+        // 16 cb + col of row 16 (RF wave + f) + row(g, r), summed over chunks by
+        // the finishing launch. No barrier: the window is not reused.
+        T* yp = reinterpret_cast<T*>(part) + ((size_t)sk_i * P.rt * P.rows + k_first + kRowsPerWave * RF * wave) * P.nrp + col;
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    yp[(size_t)(kRowsPerWave * f + M::row(g, r)) * P.nrp + 16 * cb] = acc[f][cb][r];
+        return;
     }
 
     // U^* reduction over this wave's rows. The accumulators are the second
@@ -385,7 +416,33 @@ template <typename T, int NB, int RF>
 __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, TilePtrs<T> ptr) {
     const int id = blockIdx.x;
     const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
-    tile_body<T, NB, RF>(P, ptr, L);
+    tile_body<T, NB, RF, 0>(P, ptr, L);
+}
+
+// Y = T X (or T^* X) for a block of columns: tiles of the product, partial
+// over the K chunks (summed by toeplitz_mm_finish).
+template <typename T, int NB, int RF>
+__global__ __launch_bounds__(kThreads) void toeplitz_mm_tiles(PencilPlan P, TilePtrs<T> ptr) {
+    const int id = blockIdx.x;
+    const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
+    tile_body<T, NB, RF, 1>(P, ptr, L);
+}
+
+// Y[k, c] = sum over chunks s (in order) of the partial real columns 2c, 2c+1, FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void toeplitz_mm_finish(PencilPlan P, const T* __restrict__ part,
+                                                         double2* __restrict__ Y, int64_t ldy) {
+    const int o = blockIdx.x * 256 + threadIdx.x;
+    if (o >= P.N * P.C) return;
+    const int k = o / P.C, c = o - (o / P.C) * P.C;
+    const size_t slab = (size_t)P.rt * P.rows * P.nrp;
+    const T* src = part + (size_t)k * P.nrp + 2 * c;
+    double re = 0.0, im = 0.0;
+    for (int s2 = 0; s2 < P.sk; ++s2) {
+        re += (double)src[s2 * slab];
+        im += (double)src[s2 * slab + 1];
+    }
+    Y[(size_t)k * ldy + c] = make_double2(re, im);
 }
 
 // One instance of a batch: its plan, its pointers and the first global tile
@@ -424,7 +481,7 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntr
             hi = mid - 1;
     }
     const BatchEntry<T>& e = entries[lo];
-    tile_body<T, NB, RF>(e.P, e.ptr, id - e.tile_begin);
+    tile_body<T, NB, RF, 0>(e.P, e.ptr, id - e.tile_begin);
 }
 
 size_t lds_bytes_for(int win, int kc, int nbp, size_t tsize) {
@@ -455,20 +512,23 @@ int tuned_target(prony_handle_t h, int d, int n, int m, int prec, int batched) {
 // target_wgs: workgroups the split of the h' range aims at (single instances
 // fill the GPU with one launch; batch members use target 1, i.e. no split
 // beyond what the LDS window imposes).
+// mode 1 plans the product Y = T X of a block of m columns (h over I_n, no
+// shifted copies, no U^* epilogue).
 prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P,
-                         int target_wgs = 0, bool allow_rf2 = false) {
+                         int target_wgs = 0, bool allow_rf2 = false, int mode = 0) {
     P = PencilPlan{};
     P.d = d;
     P.n = n;
     P.N = (int)ipow(n + 1, d);
     P.m = m;
-    P.ells = d + (with_s0 ? 1 : 0);
-    P.first_ell = with_s0 ? 0 : 1;
+    P.mode = mode;
+    P.ells = mode ? 1 : d + (with_s0 ? 1 : 0);
+    P.first_ell = mode || with_s0 ? 0 : 1;
     P.C = P.ells * m;
     P.nb = (2 * P.C + 15) / 16;
     P.nrp = 16 * P.nb;
-    P.mbi = (m + 15) / 16;
-    P.kb = (int)ipow(n + 2, d);
+    P.mbi = mode ? 0 : (m + 15) / 16;
+    P.kb = mode ? P.N : (int)ipow(n + 2, d);
     P.rf = allow_rf2 && rf2_supported(tsize, P.nb) && P.N > kRowsPerTile ? 2 : 1;
     P.rows = kRowsPerTile * P.rf;
     P.rt = (P.N + P.rows - 1) / P.rows;
@@ -482,9 +542,9 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, 16)));
     const int rowspan = max_span(P.N, P.rows, d, n, false);
     for (;;) {
-        const int colspan = max_span(P.kb, kc, d, n, true);
+        const int colspan = max_span(P.kb, kc, d, n, !mode);
         const int win = rowspan + colspan + 1;
-        const size_t lds = lds_bytes_for(win, kc, P.nbp, tsize);
+        const size_t lds = lds_bytes_for(win, kc, mode ? 0 : P.nbp, tsize);
         if (lds <= budget) {
             P.kc = kc;
             P.sk = (P.kb + kc - 1) / kc;
@@ -497,7 +557,8 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     }
     P.nwg = P.rt * P.sk;
     if (((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp >= (int64_t(1) << 31) ||
-        (int64_t)P.nwg * P.m * P.C >= (int64_t(1) << 31))
+        (int64_t)P.nwg * P.m * P.C >= (int64_t(1) << 31) ||
+        (int64_t)P.sk * P.rt * P.rows * P.nrp >= (int64_t(1) << 31))
         return fail(h, PRONY_ENOTSUP, "prony_build_S: problem too large for 32-bit tile indexing");
     const size_t t2 = 2 * tsize;
     const size_t tot = (size_t)P.m * P.C;
@@ -509,7 +570,10 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.off_g = off;
     off = align_up(off + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
     P.off_p = off;
-    off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
+    if (mode)   // partial Y rows of every chunk, real columns
+        off = align_up(off + tsize * (size_t)P.sk * P.rt * P.rows * P.nrp, 256);
+    else
+        off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
     P.ws_bytes = off;
     return PRONY_OK;
 }
@@ -626,6 +690,65 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, const double
             P, part, sigma, reinterpret_cast<double2*>(S));
     }
     return check_launch(h, "pencil_finish");
+}
+
+template <typename T, int NB, int RF>
+prony_status_t launch_mm_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
+    if (P.lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&toeplitz_mm_tiles<T, NB, RF>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+        if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+    }
+    ProfileScope prof(h, "toeplitz_mm_tiles");
+    toeplitz_mm_tiles<T, NB, RF><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
+    return PRONY_OK;
+}
+
+#define PRONY_MM_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+
+template <typename T>
+prony_status_t dispatch_mm(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
+    switch (P.nb) {
+#define PRONY_CASE(NBV)                                               \
+    case NBV:                                                         \
+        if constexpr (rf2_supported(sizeof(T), NBV))                  \
+            if (P.rf == 2) return launch_mm_tiles<T, NBV, 2>(h, P, ptr); \
+        return launch_mm_tiles<T, NBV, 1>(h, P, ptr);
+        PRONY_MM_NB_CASES(PRONY_CASE)
+#undef PRONY_CASE
+        default:
+            return fail(h, PRONY_ENOTSUP, "prony_toeplitz_mm: too many columns");
+    }
+}
+
+template <typename T>
+prony_status_t launch_toeplitz_mm(prony_handle_t h, const PencilPlan& P, const double* f, const double* X,
+                                  int64_t ldx, double* Y, int64_t ldy) {
+    using T2 = pair_t<T>;
+    prony_status_t st = ensure_workspace(h, P.ws_bytes);
+    if (st != PRONY_OK) return st;
+    unsigned char* ws = static_cast<unsigned char*>(h->ws);
+    T2* vp = reinterpret_cast<T2*>(ws + P.off_v);
+    int* gt = reinterpret_cast<int*>(ws + P.off_g);
+    T2* part = reinterpret_cast<T2*>(ws + P.off_p);
+    const int64_t kbp = (int64_t)P.sk * P.kc + kPrefetchRows;
+    const int pack_blocks = (int)std::min<int64_t>((kbp * P.nrp + 255) / 256, 2 * (int64_t)h->num_cus);
+    {
+        ProfileScope prof(h, "pencil_pack");
+        pencil_pack<T><<<dim3(pack_blocks, 3), 256, 0, h->stream>>>(
+            P, nullptr, 0, 0, reinterpret_cast<const double2*>(X), ldx, 1, vp, nullptr, gt);
+    }
+    if ((st = check_launch(h, "pencil_pack")) != PRONY_OK) return st;
+    const TilePtrs<T> ptr{reinterpret_cast<const double2*>(f), vp, nullptr, gt, part, nullptr, nullptr};
+    if ((st = dispatch_mm<T>(h, P, ptr)) != PRONY_OK) return st;
+    if ((st = check_launch(h, "toeplitz_mm_tiles")) != PRONY_OK) return st;
+    {
+        ProfileScope prof(h, "toeplitz_mm_finish");
+        const int outs = P.N * P.C;
+        toeplitz_mm_finish<T><<<(outs + 255) / 256, 256, 0, h->stream>>>(
+            P, reinterpret_cast<const T*>(part), reinterpret_cast<double2*>(Y), ldy);
+    }
+    return check_launch(h, "toeplitz_mm_finish");
 }
 
 }  // namespace
@@ -991,4 +1114,29 @@ extern "C" prony_status_t prony_tune_set(prony_handle_t h, int d, int n, int m, 
     else
         h->split_targets[key] = target_wgs;
     return PRONY_OK;
+}
+
+extern "C" prony_status_t prony_toeplitz_mm(prony_handle_t h, int d, int n, int adjoint, const double* f, int r,
+                                            const double* X, int64_t ldx, prony_prec_t prec, double* Y,
+                                            int64_t ldy) {
+    if (!h) return PRONY_EINVAL;
+    prony_status_t st = check_dn(h, d, n);
+    if (st != PRONY_OK) return st;
+    if (adjoint != 0 && adjoint != 1) return fail(h, PRONY_EINVAL, "prony_toeplitz_mm: adjoint must be 0 or 1");
+    if (r < 1 || r > 64) return fail(h, PRONY_EINVAL, "prony_toeplitz_mm: r must be in 1..64");
+    if (ldx < r || ldy < r) return fail(h, PRONY_EINVAL, "prony_toeplitz_mm: leading dimensions must be >= r");
+    if (!f || !X || !Y) return fail(h, PRONY_EINVAL, "prony_toeplitz_mm: null pointer");
+    if (prec != PRONY_FP64 && prec != PRONY_FP32) return fail(h, PRONY_EINVAL, "prony_toeplitz_mm: bad precision");
+    const int64_t N = ipow(n + 1, d);
+    if ((N - 1) * ldx + r >= (int64_t(1) << 40) || (N - 1) * ldy + r >= (int64_t(1) << 40))
+        return fail(h, PRONY_EINVAL, "prony_toeplitz_mm: leading dimensions out of range");
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    PencilPlan P;
+    const size_t ts = prec == PRONY_FP32 ? sizeof(float) : sizeof(double);
+    if ((st = make_plan(h, d, n, r, false, ts, P, 0, true, 1)) != PRONY_OK) return st;
+    P.conj_grid = adjoint;
+    return prec == PRONY_FP32 ? launch_toeplitz_mm<float>(h, P, f, X, ldx, Y, ldy)
+                              : launch_toeplitz_mm<double>(h, P, f, X, ldx, Y, ldy);
 }

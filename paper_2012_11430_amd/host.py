@@ -1,7 +1,9 @@
 """FP64 host steps of Algorithm 1 that the paper assigns to the CPU (Sec. 3).
 
 * reduced SVD of T: LAPACK for small N, the block power method with rank
-  determination (Sec. 2.2, Algorithm 3) for large N;
+  determination (Sec. 2.2, Algorithm 3) for large N, whose block products
+  T X and T^* Y run on the GPU from the sample grid (prony_toeplitz_mm) while
+  the QR factorisations and the small SVD stay on the host;
 * eigendecomposition of the random combination C_mu and extraction of the
   nodes z_j, t_j (Algorithm 1, eigenvalue step);
 * the m x m solve of the normal equations gram c = rhs formed on the GPU
@@ -25,19 +27,66 @@ def _orth(X: np.ndarray) -> np.ndarray:
     return q
 
 
-def power_svd(T: np.ndarray, start_u: np.ndarray, start_v: np.ndarray, tol: float, rank: int | None = None,
+class DenseToeplitz:
+    """The operator interface of power_svd for an explicit matrix."""
+
+    def __init__(self, T: np.ndarray):
+        self.T = T
+
+    def matmul(self, X: np.ndarray) -> np.ndarray:
+        return self.T @ X
+
+    def rmatmul(self, Y: np.ndarray) -> np.ndarray:
+        return self.T.conj().T @ Y
+
+    def fro_norm(self) -> float:
+        return float(np.linalg.norm(self.T))
+
+
+class GpuToeplitz:
+    """T of the sample grid f (device tensor) as an operator: T X and T^* Y on the
+    GPU without forming T (prony_toeplitz_mm); numpy blocks in and out."""
+
+    def __init__(self, f: torch.Tensor, d: int, n: int, prec: str = "fp64"):
+        self.f, self.d, self.n, self.prec = f, d, n, prec
+
+    def _mm(self, X: np.ndarray, adjoint: bool) -> np.ndarray:
+        Xd = torch.from_numpy(np.ascontiguousarray(X)).to(self.f.device)
+        return api.toeplitz_mm(self.f, self.d, self.n, Xd, adjoint=adjoint, prec=self.prec).cpu().numpy()
+
+    def matmul(self, X: np.ndarray) -> np.ndarray:
+        return self._mm(X, False)
+
+    def rmatmul(self, Y: np.ndarray) -> np.ndarray:
+        return self._mm(Y, True)
+
+    def fro_norm(self) -> float:
+        """||T||_F^2 = sum_p |f(p)|^2 prod_l (n + 1 - |p_l|) over p in {-n..n}^d: every
+        difference p = k - h occurs that many times in T."""
+        n, d = self.n, self.d
+        g = self.f.cpu().numpy().reshape((2 * n + 2,) * d)[(slice(0, 2 * n + 1),) * d]
+        w1 = n + 1 - np.abs(np.arange(-n, n + 1))
+        w = w1
+        for _ in range(d - 1):
+            w = np.multiply.outer(w, w1)
+        return float(np.sqrt(np.sum(np.abs(g) ** 2 * w)))
+
+
+def power_svd(T, start_u: np.ndarray, start_v: np.ndarray, tol: float, rank: int | None = None,
               max_sweeps: int = 60):
     """Block power SVD with pivoted-QR rank determination in the first sweep
-    (Sec. 2.2, Algorithm 3). Returns (U, sigma, V, detected_rank, sweeps)."""
+    (Sec. 2.2, Algorithm 3). T is a matrix or an operator with matmul, rmatmul and
+    fro_norm (GpuToeplitz). Returns (U, sigma, V, detected_rank, sweeps)."""
+    op = DenseToeplitz(T) if isinstance(T, np.ndarray) else T
     Uk, Vk = _orth(start_u), _orth(start_v)
-    norm_t = np.linalg.norm(T)
-    TV = T @ Vk
+    norm_t = op.fro_norm()
+    TV = op.matmul(Vk)
     Qk = Uk.conj().T @ TV
     sweeps, detected = 0, Vk.shape[1]
     while np.linalg.norm(TV - Uk @ Qk) > tol * norm_t and sweeps < max_sweeps:
         sweeps += 1
-        Uk = _orth(T @ Vk)
-        W = T.conj().T @ Uk
+        Uk = _orth(op.matmul(Vk))
+        W = op.rmatmul(Uk)
         if sweeps == 1:
             Qv, Rv, perm = scipy.linalg.qr(W, mode="economic", pivoting=True)
             tail = np.sqrt(np.cumsum((np.abs(Rv) ** 2).sum(axis=1)[::-1])[::-1])
@@ -51,7 +100,7 @@ def power_svd(T: np.ndarray, start_u: np.ndarray, start_v: np.ndarray, tol: floa
         else:
             Vk, Rv = np.linalg.qr(W)
             Qk = Rv.conj().T
-        TV = T @ Vk
+        TV = op.matmul(Vk)
     Uq, s, Vqh = np.linalg.svd(Qk, full_matrices=False)
     r = Vk.shape[1] if rank is None else rank
     return (Uk @ Uq)[:, :r], s[:r], (Vk @ Vqh.conj().T)[:, :r], detected, sweeps
@@ -99,13 +148,26 @@ class Solution:
 
 
 def solve(f: torch.Tensor, d: int, n: int, m: int, mu: np.ndarray, prec: str = "fp64",
-          start_blocks=None) -> Solution:
-    """Algorithm 1 on one GPU plus the host: T (GPU) -> reduced SVD (host) -> S_l (GPU)
-    -> nodes (host) -> Vandermonde products (GPU) -> coefficients (host)."""
+          start_blocks=None, svd: str = "dense") -> Solution:
+    """Algorithm 1 on one GPU plus the host: reduced SVD of T -> S_l (GPU) -> nodes
+    (host) -> Vandermonde products (GPU) -> coefficients (host).
+
+    svd="dense": T formed on the GPU and decomposed on the host (LAPACK for
+    N <= 1024, else Algorithm 3 on the dense T); svd="gpu": Algorithm 3 with the
+    block products on the GPU (start_blocks required), T never formed."""
     dev = f.device
-    T = api.build_T(f, d, n, 0).cpu().numpy()
-    U, s, V, _ = reduced_svd(T, m, start_blocks)
-    del T
+    if svd == "gpu":
+        if start_blocks is None:
+            raise ValueError("svd='gpu' needs start_blocks (two N x r blocks)")
+        N = (n + 1) ** d
+        U, s, V, _, _ = power_svd(GpuToeplitz(f, d, n), start_blocks[0], start_blocks[1],
+                                  N * np.finfo(float).eps, rank=m)
+    elif svd == "dense":
+        T = api.build_T(f, d, n, 0).cpu().numpy()
+        U, s, V, _ = reduced_svd(T, m, start_blocks)
+        del T
+    else:
+        raise ValueError("svd must be 'dense' or 'gpu'")
     Ud = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
     Vd = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
     sd = torch.from_numpy(np.ascontiguousarray(s)).to(dev)

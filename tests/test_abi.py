@@ -135,3 +135,14 @@ def test_adjoint_validation(vhandle):
     assert lib.prony_build_S_adjoint(h, 2, 47, 16, P, 16, 1, P, P, 16, 1, NULL, 0, P) == _lib.PRONY_EINVAL
     assert lib.prony_build_S_adjoint(h, 2, 47, 16, P, 0, 1, P, P, 16, 1, P, 0, P) == _lib.PRONY_EINVAL
     assert lib.prony_build_S_adjoint(h, 2, 47, 16, P, 16, 1, P, P, 16, 1, P, 5, P) == _lib.PRONY_EINVAL
+
+
+def test_toeplitz_mm_validation(vhandle):
+    lib, h = vhandle
+    assert lib.prony_toeplitz_mm(h, 2, 15, 0, P, 10, P, 10, _lib.PRONY_FP64, P, 10) == _lib.PRONY_ENODEV
+    assert lib.prony_toeplitz_mm(h, 2, 15, 2, P, 10, P, 10, _lib.PRONY_FP64, P, 10) == _lib.PRONY_EINVAL
+    assert lib.prony_toeplitz_mm(h, 2, 15, 0, P, 65, P, 65, _lib.PRONY_FP64, P, 65) == _lib.PRONY_EINVAL
+    assert lib.prony_toeplitz_mm(h, 2, 15, 0, P, 10, P, 9, _lib.PRONY_FP64, P, 10) == _lib.PRONY_EINVAL
+    assert lib.prony_toeplitz_mm(h, 2, 15, 0, NULL, 10, P, 10, _lib.PRONY_FP64, P, 10) == _lib.PRONY_EINVAL
+    assert lib.prony_toeplitz_mm(h, 2, 15, 1, P, 10, P, 10, 7, P, 10) == _lib.PRONY_EINVAL
+    assert lib.prony_toeplitz_mm(h, 4, 15, 0, P, 10, P, 10, _lib.PRONY_FP64, P, 10) == _lib.PRONY_EINVAL
