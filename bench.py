@@ -184,6 +184,17 @@ def main():
     build_T = {"ms_median": round(t_med, 5), "bytes": 16 * N * N,
                "GB_per_s": round(16 * N * N / (t_med * 1e-3) / 1e9, 1), "peak_GB_per_s": 8000.0}
 
+    # recovered nodes and coefficients from each precision's S (host FP64 steps:
+    # eig of C_mu and the LS solve; the SVD inputs are shared)
+    recovered = {}
+    for prec, S_p in S_out.items():
+        z_p, t_p = host.nodes(S_p, inst.mu)
+        gram, rhs = api.coeffs(to_dev(z_p), f, d, n)
+        recovered[prec] = (t_p, host.solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy()))
+    for prec in sbuild:
+        sbuild[prec]["frac_of_mfma_peak"] = round(sbuild[prec]["tflops"] / PEAK_TFLOPS[prec], 4)
+    sbuild["speedup_fp32_over_fp64"] = round(sbuild["fp64"]["ms_median"] / sbuild["fp32"]["ms_median"], 3)
+
     F = s_flops(d, N, m)
     value = F / (ms_step * 1e-3) / 1e12
     achieved = tile_flops(d, N, m) / (tiles_avg_ms * 1e-3) / 1e12
@@ -234,11 +245,12 @@ def main():
     }
     if not args.no_extra:
         result["svd_products"] = svd_products(dev, args, f, d, n, m, sig, blocks, per_call_ms)
+        result["noise_sweep_c2"] = noise_sweep_c2(dev, args)
         result["batched"] = batched_c3(dev, args)
         result["adjoint"] = adjoint_c4(dev, args)
 
     if args.cpu_sample_steps > 0:
-        result["cpu_baseline"] = cpu_baseline(inst, U, sig, V, z, S_out, args.cpu_sample_steps,
+        result["cpu_baseline"] = cpu_baseline(inst, U, sig, V, z, S_out, args.cpu_sample_steps, recovered,
                                               f.cpu().numpy())
     print(json.dumps(result), flush=True)
 
@@ -271,6 +283,64 @@ def svd_products(dev, args, f, d, n, m, sig_ref, blocks, per_call_ms):
     out["power_svd_gpu_products"] = {"s": round(time.perf_counter() - t0, 4), "sweeps": sweeps,
                                      "sigma_rel_diff_vs_dense_T": float(f"{np.max(np.abs(s - sig_ref) / sig_ref):.3e}")}
     return out
+
+
+def _match_errors(t_est, c_est, t_true, c_true):
+    """max torus |dt| and ||dc|| / ||c|| after an optimal assignment of the nodes."""
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+
+    diff = np.abs(t_est[None, :, :] - t_true[:, None, :]) % 1.0
+    dist = np.minimum(diff, 1.0 - diff).max(axis=2)
+    rows, cols = linear_sum_assignment(dist)
+    dt = float(dist[rows, cols].max())
+    dc = float(np.linalg.norm(c_est[cols] - c_true[rows]) / np.linalg.norm(c_true))
+    return dt, dc
+
+
+def noise_sweep_c2(dev, args):
+    """c2 (d=3, n=19, N=8000, m=30) over its noise levels: the SVD by Algorithm 3
+    with GPU block products (T is never formed), S in FP32-MFMA and FP64, and the
+    recovered t_j, c_j of both against the truth, with the S-build times."""
+    import numpy as np
+    import torch
+
+    from paper_2012_11430_amd import api, host
+    from workload import config_instances, random_orthonormal
+
+    inst = config_instances("c2", count=1)[0]
+    d, n, m, N = inst.d, inst.n, inst.m, inst.N
+    rng = np.random.Generator(np.random.PCG64(2020))
+    blocks = (random_orthonormal(rng, N, 2 * m), random_orthonormal(rng, N, 2 * m))
+    t_d = torch.from_numpy(inst.t).to(dev)
+    c_d = torch.from_numpy(inst.c).to(dev)
+    rows = []
+    for level in inst.noise_levels:
+        noise = torch.from_numpy(inst.noise(level)).to(dev) if level > 0 else None
+        f = api.samples(t_d, c_d, n, noise=noise)
+        tol = max(N * np.finfo(float).eps, level)
+        U, s, V, _, sweeps = host.power_svd(host.GpuToeplitz(f, d, n), blocks[0], blocks[1], tol, rank=m)
+        Ud, sd, Vd = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (U, s, V))
+        row = {"noise": level, "svd_sweeps": sweeps}
+        S = {}
+        for prec in ("fp64", "fp32"):
+            api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            S[prec] = api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            z_p, t_p = host.nodes(S[prec].cpu().numpy(), inst.mu)
+            gram, rhs = api.coeffs(torch.from_numpy(z_p).to(dev), f, d, n)
+            c_p = host.solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy())
+            dt, dc = _match_errors(t_p, c_p, inst.t, inst.c)
+            ms = e0.elapsed_time(e1)
+            row[prec] = {"s_build_ms": round(ms, 4), "tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 2),
+                         "max_dt_vs_truth": float(f"{dt:.3e}"), "rel_dc_vs_truth": float(f"{dc:.3e}")}
+        row["s_rel_diff_fp32_vs_fp64"] = float(f"{float(torch.linalg.norm(S['fp32'] - S['fp64']) / torch.linalg.norm(S['fp64'])):.3e}")
+        rows.append(row)
+    return {"workload": "c2: d=3, n=19, N=8000, m=30, separation 0.08, |c| log-uniform [1e-2, 1]", "levels": rows}
 
 
 def _closed_form_factors(t, c, d, n):
@@ -422,7 +492,7 @@ def adjoint_c4(dev, args):
     }
 
 
-def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, grid_gpu):
+def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, recovered, grid_gpu):
     """The CPU oracle timed on `steps` whole steps of the same workload, and its
     S-build alone (median of 3, all host threads and one thread); also the relative
     error of the GPU S-build against the oracle on the same inputs."""
@@ -453,6 +523,18 @@ def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, grid_gpu):
     F = s_flops(d, inst.N, inst.m)
     rel = {p: max(float(np.linalg.norm(S_gpu[p][l] - S[l]) / np.linalg.norm(S[l])) for l in range(d))
            for p in S_gpu}
+    # t_j, c_j of each precision against the FP64 oracle pipeline (same SVD inputs)
+    # and against the truth; host FP64 steps: SVD, eig, LS
+    z_or, t_or, _ = O.nodes_from_pencil(S, inst.mu)
+    c_or, _ = O.least_squares_coefficients(z_or, grid, d, n)
+    recovery = {"fp64_host_steps": "SVD (Algorithm 3 on T), eig of C_mu, LS (normal equations)"}
+    dt, dc = O.recovery_errors(dict(t=t_or, c=c_or), inst.t, inst.c)
+    recovery["oracle_vs_truth"] = {"max_dt": float(f"{dt:.3e}"), "rel_dc": float(f"{dc:.3e}")}
+    for p, (t_p, c_p) in recovered.items():
+        dt_o, dc_o = O.recovery_errors(dict(t=t_p, c=c_p), t_or, c_or)
+        dt_t, dc_t = O.recovery_errors(dict(t=t_p, c=c_p), inst.t, inst.c)
+        recovery[p] = {"max_dt_vs_oracle": float(f"{dt_o:.3e}"), "rel_dc_vs_oracle": float(f"{dc_o:.3e}"),
+                       "max_dt_vs_truth": float(f"{dt_t:.3e}"), "rel_dc_vs_truth": float(f"{dc_t:.3e}")}
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -470,6 +552,7 @@ def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, grid_gpu):
         "s_build_only": {"s_median_all_threads": round(s_all, 4), "tflops_all_threads": round(F / s_all / 1e12, 6),
                          "s_one_thread": round(s_one, 4), "tflops_one_thread": round(F / s_one / 1e12, 6)},
         "s_rel_err_vs_oracle": {p: float(f"{v:.3e}") for p, v in rel.items()},
+        "recovery_vs_oracle": recovery,
         "samples_max_abs_err": float(f"{np.max(np.abs(grid_gpu - grid)):.3e}"),
     }
 
