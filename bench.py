@@ -246,6 +246,7 @@ def main():
     if not args.no_extra:
         result["svd_products"] = svd_products(dev, args, f, d, n, m, sig, blocks, per_call_ms)
         result["noise_sweep_c2"] = noise_sweep_c2(dev, args)
+        result["paper_workload"] = paper_workload(dev, args, per_call_ms)
         result["batched"] = batched_c3(dev, args)
         result["adjoint"] = adjoint_c4(dev, args)
 
@@ -282,6 +283,57 @@ def svd_products(dev, args, f, d, n, m, sig_ref, blocks, per_call_ms):
     torch.cuda.synchronize()
     out["power_svd_gpu_products"] = {"s": round(time.perf_counter() - t0, 4), "sweeps": sweeps,
                                      "sigma_rel_diff_vs_dense_T": float(f"{np.max(np.abs(s - sig_ref) / sig_ref):.3e}")}
+    return out
+
+
+# The paper's S-build times on its own efficiency workload (d=3, n=20, N=9261,
+# deterministic inputs, noise-free; Sec. 2 timing table, complex FP64, machine of Sec. 5:
+# 2x Xeon E5-2690 v3 + Tesla K40c): t_S in seconds for m = 5, 10, 15, 20.
+PAPER_T_S = {5: 0.1100, 10: 0.1199, 15: 0.1290, 20: 0.1495}
+
+
+def paper_workload(dev, args, per_call_ms):
+    """The paper's efficiency workload on this GPU: the S-build (FP64, the paper's
+    arithmetic, and FP32-MFMA) for m = 5..20 against the paper's t_S, and the whole
+    GPU path of Algorithm 1 (samples, power SVD with GPU block products, S, nodes,
+    Gram/rhs, LS) for m = 5."""
+    import numpy as np
+    import torch
+
+    from paper_2012_11430_amd import api, host
+    from workload import paper_efficiency_inputs, random_orthonormal
+
+    d, n = 3, 20
+    N = (n + 1) ** d
+    out = {"workload": "d=3, n=20, N=9261, noise-free, t_j(i) = ((i-1)m+j-1) 10^-ceil(log10 dm), c_j = j + ij",
+           "paper_hardware": "2x Xeon E5-2690 v3 + Tesla K40c (FP64)", "m": {}}
+    mu = np.array([1.0, 1j, -0.5]) / np.linalg.norm([1.0, 1j, -0.5])
+    for m in sorted(PAPER_T_S):
+        t, c = paper_efficiency_inputs(d, m)
+        f = api.samples(torch.from_numpy(t).to(dev), torch.from_numpy(c).to(dev), n)
+        rng = np.random.Generator(np.random.PCG64(140 + m))
+        blocks = (random_orthonormal(rng, N, 2 * m), random_orthonormal(rng, N, 2 * m))
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        U, s, V, rank, sweeps = host.power_svd(host.GpuToeplitz(f, d, n), blocks[0], blocks[1],
+                                               N * np.finfo(float).eps, rank=m)
+        Ud, sd, Vd = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (U, s, V))
+        S = api.build_S(f, d, n, Ud, sd, Vd, prec="fp64").cpu().numpy()
+        z, t_est = host.nodes(S, mu)
+        gram, rhs = api.coeffs(torch.from_numpy(z).to(dev), f, d, n)
+        host.solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        row = {"paper_t_S_s": PAPER_T_S[m],
+               "paper_gflops": round(s_flops(d, N, m) / PAPER_T_S[m] / 1e9, 1),
+               "algorithm1_gpu_path_s": round(wall, 4), "svd_sweeps": sweeps}
+        for prec in ("fp64", "fp32"):
+            for _ in range(args.warmup):
+                api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
+            ms = float(np.median(per_call_ms(lambda: api.build_S(f, d, n, Ud, sd, Vd, prec=prec), 10)))
+            row[prec] = {"s_build_ms": round(ms, 4), "tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 2),
+                         "speedup_vs_paper_t_S": round(PAPER_T_S[m] / (ms * 1e-3), 1)}
+        out["m"][str(m)] = row
     return out
 
 
