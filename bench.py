@@ -294,9 +294,9 @@ PAPER_T_S = {5: 0.1100, 10: 0.1199, 15: 0.1290, 20: 0.1495}
 
 def paper_workload(dev, args, per_call_ms):
     """The paper's efficiency workload on this GPU: the S-build (FP64, the paper's
-    arithmetic, and FP32-MFMA) for m = 5..20 against the paper's t_S, and the whole
-    GPU path of Algorithm 1 (samples, power SVD with GPU block products, S, nodes,
-    Gram/rhs, LS) for m = 5."""
+    arithmetic, and FP32-MFMA) for m = 5..20 against the paper's t_S, the whole GPU
+    path of Algorithm 1 (samples, power SVD with GPU block products, S, nodes,
+    Gram/rhs, LS), and the Lanczos SVD (Algorithm 2) with GPU products."""
     import numpy as np
     import torch
 
@@ -324,7 +324,16 @@ def paper_workload(dev, args, per_call_ms):
         host.solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy())
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        row = {"paper_t_S_s": PAPER_T_S[m],
+        lrng = np.random.Generator(np.random.PCG64(240 + m))
+        p1 = lrng.standard_normal(N) + 1j * lrng.standard_normal(N)
+        restarts = [lrng.standard_normal(N) + 1j * lrng.standard_normal(N) for _ in range(4)]
+        torch.cuda.synchronize()
+        l0 = time.perf_counter()
+        _, s_l, _, rank_l = host.lanczos_svd(host.GpuToeplitz(f, d, n), p1, N * np.finfo(float).eps, restarts)
+        torch.cuda.synchronize()
+        lanczos = {"s": round(time.perf_counter() - l0, 4), "rank": rank_l,
+                   "sigma_rel_diff_vs_power": float(f"{np.max(np.abs(s_l[:m] - s) / s):.3e}")}
+        row = {"paper_t_S_s": PAPER_T_S[m], "lanczos_svd_gpu_products": lanczos,
                "paper_gflops": round(s_flops(d, N, m) / PAPER_T_S[m] / 1e9, 1),
                "algorithm1_gpu_path_s": round(wall, 4), "svd_sweeps": sweeps}
         for prec in ("fp64", "fp32"):

@@ -133,6 +133,81 @@ def _orthonormal_columns(X: np.ndarray) -> np.ndarray:
     return Q
 
 
+def _reorthogonalize(x: np.ndarray, Q: np.ndarray) -> np.ndarray:
+    """x minus its projection on the orthonormal columns of Q, done twice (full
+    reorthogonalisation, Sec. 2.1)."""
+    for _ in range(2):
+        if Q.shape[1]:
+            x = x - Q @ (Q.conj().T @ x)
+    return x
+
+
+def lanczos_bidiagonalization(A: np.ndarray, p1: np.ndarray, tol: float, restart_vectors=(),
+                              max_steps: int | None = None):
+    """Lanczos bidiagonalization with full reorthogonalisation, the early-stop check
+    and restart (Sec. 2.1, Algorithm 2 and the text after it); rank from the size of
+    the bidiagonal factor.
+
+    A v_i - beta_i u_{i-1} and A^* u_i - alpha_i v_i give alpha_i u_i and
+    beta_{i+1} v_{i+1}; a coefficient <= tol ||A||_F counts as zero. Then a random
+    vector (taken in order from `restart_vectors`, drawn by the caller) is
+    orthogonalised against the current basis: if the operator maps it below the
+    tolerance the process has finished, otherwise it becomes the next basis vector
+    with a zero coefficient in B.
+    Returns (U, sigma, V, rank): the singular triplets of A from the SVD of B
+    (left vectors U_i U_B, right V V_B), sorted decreasingly, and the rank.
+    """
+    rows, cols = A.shape
+    thr = tol * np.linalg.norm(A)
+    restarts = iter(restart_vectors)
+    steps = max_steps if max_steps is not None else min(rows, cols)
+    U = np.zeros((rows, 0), dtype=complex)
+    beta1 = np.linalg.norm(p1)
+    V = (p1 / beta1).astype(complex)[:, None]
+    alphas, betas = [], []          # B: alpha_i on the diagonal, beta_{i+1} above it
+    beta_i = beta1
+    stop = None
+    for _ in range(steps):
+        r = A @ V[:, -1]
+        if U.shape[1]:
+            r = r - beta_i * U[:, -1]
+        r = _reorthogonalize(r, U)
+        alpha = np.linalg.norm(r)
+        if alpha <= thr:
+            y = _reorthogonalize(np.asarray(next(restarts), dtype=complex), U)
+            if np.linalg.norm(A.conj().T @ y) <= thr * np.linalg.norm(y):
+                stop = "alpha"      # span{u_1..u_i} = R(A): B is i x (i+1)
+                break
+            r, alpha = y, 0.0
+        u = r / np.linalg.norm(r)
+        alphas.append(alpha)
+        U = np.hstack([U, u[:, None]])
+        p = _reorthogonalize(A.conj().T @ u - alpha * V[:, -1], V)
+        beta = np.linalg.norm(p)
+        if beta <= thr:
+            w = _reorthogonalize(np.asarray(next(restarts), dtype=complex), V)
+            if np.linalg.norm(A @ w) <= thr * np.linalg.norm(w):
+                stop = "beta"       # span{v_1..v_i} = R(A^*): B is i x i
+                break
+            p, beta = w, 0.0
+        betas.append(beta)
+        V = np.hstack([V, (p / np.linalg.norm(p))[:, None]])
+        beta_i = beta
+    i = U.shape[1]
+    ncol = i + 1 if stop == "alpha" or stop is None else i
+    B = np.zeros((i, ncol))
+    B[np.arange(i), np.arange(i)] = alphas
+    sup = betas[:ncol - 1]
+    B[np.arange(len(sup)), np.arange(1, len(sup) + 1)] = sup
+    UB, s, VBh = np.linalg.svd(B, full_matrices=False)
+    # Reading: rounding can let the process take a step past the rank (a v_i with a
+    # component just above the threshold); such a step adds a singular value of B
+    # at rounding level, so the rank counts the singular values of B above the same
+    # threshold instead of the raw size of B.
+    rank = int(np.count_nonzero(s > thr))
+    return U @ UB, s, V[:, :ncol] @ VBh.conj().T, rank
+
+
 def block_power_svd(A: np.ndarray, U0: np.ndarray, V0: np.ndarray, tol: float,
                     rank: int | None = None, max_sweeps: int = 60):
     """Block power method for the SVD with rank determination (Sec. 2.2, Algorithm 3).

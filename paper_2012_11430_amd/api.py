@@ -180,7 +180,7 @@ def toeplitz_mm(f: torch.Tensor, d: int, n: int, X: torch.Tensor, adjoint: bool 
     N = (n + 1) ** d
     if f.numel() != grid_size(d, n):
         raise ValueError("f must hold the (2n+2)^d sample grid")
-    if X.dim() != 2 or X.shape[0] != N or X.stride(1) != 1:
+    if X.dim() != 2 or X.shape[0] != N or (X.shape[1] > 1 and X.stride(1) != 1):
         raise ValueError("X must be N x r with unit column stride")
     if prec not in ("fp64", "fp32"):
         raise ValueError("prec must be 'fp64' or 'fp32'")
@@ -189,7 +189,7 @@ def toeplitz_mm(f: torch.Tensor, d: int, n: int, X: torch.Tensor, adjoint: bool 
         out = torch.empty((N, r), dtype=torch.complex128, device=dev)
     else:
         _require(out, "out", torch.complex128, dev, contiguous=False)
-        if out.shape != (N, r) or out.stride(1) != 1:
+        if out.shape != (N, r) or (r > 1 and out.stride(1) != 1):
             raise ValueError("out must be N x r with unit column stride")
     _call("prony_toeplitz_mm", dev, d, n, 1 if adjoint else 0, _ptr(f), r, _ptr(X), X.stride(0),
           _lib.PRONY_FP32 if prec == "fp32" else _lib.PRONY_FP64, _ptr(out), out.stride(0))

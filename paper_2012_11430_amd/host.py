@@ -106,6 +106,75 @@ def power_svd(T, start_u: np.ndarray, start_v: np.ndarray, tol: float, rank: int
     return (Uk @ Uq)[:, :r], s[:r], (Vk @ Vqh.conj().T)[:, :r], detected, sweeps
 
 
+def _project_out(x: np.ndarray, Q: list) -> np.ndarray:
+    """Remove the components along the orthonormal vectors Q, twice."""
+    if Q:
+        M = np.stack(Q, axis=1)
+        for _ in range(2):
+            x = x - M @ (M.conj().T @ x)
+    return x
+
+
+def lanczos_svd(T, p1: np.ndarray, tol: float, restart_vectors=(), max_steps: int | None = None):
+    """Lanczos bidiagonalization (Sec. 2.1, Algorithm 2) with full
+    reorthogonalisation and the early-stop check and restart described with it.
+    T is a matrix or an operator with matmul, rmatmul and fro_norm (GpuToeplitz:
+    every step is one GPU product with T and one with T^*). Coefficients below
+    tol ||T||_F count as zero; a zero triggers the check with the next caller-drawn
+    vector of `restart_vectors`. Returns (U, sigma, V, rank) from the SVD of the
+    bidiagonal factor; the rank counts its singular values above the threshold."""
+    op = DenseToeplitz(T) if isinstance(T, np.ndarray) else T
+    thr = tol * op.fro_norm()
+    vecs = iter(restart_vectors)
+    n = p1.shape[0]
+    steps = max_steps if max_steps is not None else n
+
+    def mv(x):
+        return op.matmul(x[:, None])[:, 0]
+
+    def rmv(x):
+        return op.rmatmul(x[:, None])[:, 0]
+
+    us, vs = [], [p1 / np.linalg.norm(p1)]
+    diag, sup = [], []
+    beta = 0.0
+    done = None
+    for _ in range(steps):
+        r = mv(vs[-1]) - (beta * us[-1] if us else 0.0)
+        r = _project_out(r, us)
+        alpha = float(np.linalg.norm(r))
+        if alpha <= thr:
+            y = _project_out(np.asarray(next(vecs), dtype=complex), us)
+            if np.linalg.norm(rmv(y)) <= thr * np.linalg.norm(y):
+                done = "alpha"
+                break
+            r, alpha = y, 0.0
+        us.append(r / np.linalg.norm(r))
+        diag.append(alpha)
+        p = _project_out(rmv(us[-1]) - alpha * vs[-1], vs)
+        beta = float(np.linalg.norm(p))
+        if beta <= thr:
+            w = _project_out(np.asarray(next(vecs), dtype=complex), vs)
+            if np.linalg.norm(mv(w)) <= thr * np.linalg.norm(w):
+                done = "beta"
+                break
+            p, beta = w, 0.0
+        sup.append(beta)
+        vs.append(p / np.linalg.norm(p))
+    k = len(us)
+    cols = k if done == "beta" else k + 1
+    B = np.zeros((k, cols))
+    B[range(k), range(k)] = diag
+    for j, b in enumerate(sup[:cols - 1]):
+        B[j, j + 1] = b
+    Ub, s, Vbh = np.linalg.svd(B, full_matrices=False)
+    U = np.stack(us, axis=1) @ Ub
+    V = np.stack(vs[:cols], axis=1) @ Vbh.conj().T
+    # a step taken past the rank by rounding leaves a singular value of B at rounding
+    # level: the rank counts the singular values above the stopping threshold
+    return U, s, V, int(np.count_nonzero(s > thr))
+
+
 def reduced_svd(T: np.ndarray, m: int, start_blocks=None, tol: float | None = None):
     """Rank-m reduced SVD of T: LAPACK for N <= 1024, Algorithm 3 above."""
     N = T.shape[0]
@@ -154,7 +223,9 @@ def solve(f: torch.Tensor, d: int, n: int, m: int, mu: np.ndarray, prec: str = "
 
     svd="dense": T formed on the GPU and decomposed on the host (LAPACK for
     N <= 1024, else Algorithm 3 on the dense T); svd="gpu": Algorithm 3 with the
-    block products on the GPU (start_blocks required), T never formed."""
+    block products on the GPU (start_blocks required), T never formed;
+    svd="lanczos": Algorithm 2 with GPU products (start_blocks = (p1, restart
+    vectors)), T never formed."""
     dev = f.device
     if svd == "gpu":
         if start_blocks is None:
@@ -162,12 +233,18 @@ def solve(f: torch.Tensor, d: int, n: int, m: int, mu: np.ndarray, prec: str = "
         N = (n + 1) ** d
         U, s, V, _, _ = power_svd(GpuToeplitz(f, d, n), start_blocks[0], start_blocks[1],
                                   N * np.finfo(float).eps, rank=m)
+    elif svd == "lanczos":
+        if start_blocks is None:
+            raise ValueError("svd='lanczos' needs start_blocks = (p1, restart vectors)")
+        N = (n + 1) ** d
+        U, s, V, _ = lanczos_svd(GpuToeplitz(f, d, n), start_blocks[0], N * np.finfo(float).eps, start_blocks[1])
+        U, s, V = U[:, :m], s[:m], V[:, :m]
     elif svd == "dense":
         T = api.build_T(f, d, n, 0).cpu().numpy()
         U, s, V, _ = reduced_svd(T, m, start_blocks)
         del T
     else:
-        raise ValueError("svd must be 'dense' or 'gpu'")
+        raise ValueError("svd must be 'dense', 'gpu' or 'lanczos'")
     Ud = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
     Vd = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
     sd = torch.from_numpy(np.ascontiguousarray(s)).to(dev)

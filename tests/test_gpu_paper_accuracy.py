@@ -81,3 +81,18 @@ def test_rank_detection_on_gpu_path(golden_dir):
         _, _, _, rank, _ = host.power_svd(host.GpuToeplitz(f, d, n), blocks[0], blocks[1], N * O.EPS64)
         print(f"rank d={d} n={n} m={m}: detected {rank} ({rel})", flush=True)
         assert (rank == m) if rel == "eq" else (rank < m)
+
+
+def test_rank_detection_with_gpu_lanczos(golden_dir):
+    # Sec. 5: the Lanczos method found the same ranks as the other SVD algorithms
+    for d_s, n_s, m_s, rel in _rows(golden_dir, "rank_detection.txt"):
+        d, n, m = int(d_s), int(n_s), int(m_s)
+        N = (n + 1) ** d
+        t_true, c_true = paper_efficiency_inputs(d, m)
+        f = _dev(O.samples(t_true, c_true, n))
+        rng = np.random.Generator(np.random.PCG64(42))
+        p1 = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        restarts = [rng.standard_normal(N) + 1j * rng.standard_normal(N) for _ in range(8)]
+        _, _, _, rank = host.lanczos_svd(host.GpuToeplitz(f, d, n), p1, N * O.EPS64, restarts)
+        print(f"lanczos rank d={d} n={n} m={m}: detected {rank} ({rel})", flush=True)
+        assert (rank == m) if rel == "eq" else (rank < m)

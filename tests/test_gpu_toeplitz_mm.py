@@ -90,3 +90,33 @@ def test_solve_without_forming_T_recovers_c1():
     err_t, err_c = O.recovery_errors(dict(t=sol.t, c=sol.c), inst.t, inst.c)
     print(f"c1 without T: max node error {err_t:.3e}, max coefficient error {err_c:.3e}", flush=True)
     assert err_t <= 1e-6 and err_c <= 1e-4
+
+
+def test_gpu_lanczos_matches_lapack():
+    inst = config_instances("c1", count=1)[0]
+    d, n, m = inst.d, 35, inst.m
+    grid = O.samples(inst.t, inst.c, n)
+    N = (n + 1) ** d
+    rng = np.random.Generator(np.random.PCG64(8))
+    p1 = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    restarts = [rng.standard_normal(N) + 1j * rng.standard_normal(N) for _ in range(8)]
+    U, s, V, rank = host.lanczos_svd(host.GpuToeplitz(_dev(grid), d, n), p1, N * O.EPS64, restarts)
+    T = O.toeplitz(grid, d, n, 0)
+    s_ref = np.linalg.svd(T, compute_uv=False)[:m]
+    print(f"gpu lanczos: rank {rank}, sigma rel err {np.max(np.abs(s[:m] - s_ref) / s_ref):.3e}", flush=True)
+    assert rank == m
+    assert np.max(np.abs(s[:m] - s_ref) / s_ref) <= 1e-10
+    assert _rel(T @ V[:, :m], U[:, :m] * s[None, :m]) <= 1e-9
+
+
+def test_solve_with_gpu_lanczos_recovers_c0():
+    inst = config_instances("c0")[0]
+    d, n, m = inst.d, inst.n, inst.m
+    f = api.samples(_dev(inst.t), _dev(inst.c), n)
+    N = (n + 1) ** d
+    rng = np.random.Generator(np.random.PCG64(9))
+    p1 = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    restarts = [rng.standard_normal(N) + 1j * rng.standard_normal(N) for _ in range(8)]
+    sol = host.solve(f, d, n, m, inst.mu, prec="fp64", start_blocks=(p1, restarts), svd="lanczos")
+    dt, dc = O.recovery_errors(dict(t=sol.t, c=sol.c), inst.t, inst.c)
+    assert dt < 1e-12 and dc < 1e-10, (dt, dc)

@@ -467,3 +467,63 @@ def test_adjoint_matches_torch_autograd():
     grad = O.pencil_adjoint(2 * (S - ref), d, n, U, s, V)
     g = f.grad.numpy()
     assert np.linalg.norm(g - grad) < 1e-10 * np.linalg.norm(grad)
+
+
+# ---------------------------------------------------------------- Lanczos bidiagonalization (Alg. 2)
+
+
+def _low_rank(rng, rows, cols, sv):
+    X = np.linalg.qr(rng.standard_normal((rows, len(sv))) + 1j * rng.standard_normal((rows, len(sv))))[0]
+    Y = np.linalg.qr(rng.standard_normal((cols, len(sv))) + 1j * rng.standard_normal((cols, len(sv))))[0]
+    return X @ np.diag(sv) @ Y.conj().T, X, Y
+
+
+def _vectors(rng, n, count):
+    return [rng.standard_normal(n) + 1j * rng.standard_normal(n) for _ in range(count)]
+
+
+def test_lanczos_recovers_prescribed_singular_values_and_rank():
+    rng = _rng(900)
+    sv = np.array([7.0, 3.0, 2.5, 1.0, 0.25, 0.01])
+    A, X, Y = _low_rank(rng, 80, 70, sv)
+    U, s, V, rank = O.lanczos_bidiagonalization(A, _vectors(rng, 70, 1)[0], 80 * O.EPS64, _vectors(rng, 80, 8))
+    assert rank == len(sv)
+    assert np.max(np.abs(s[:rank] - sv) / sv) < 1e-12
+    # A V = U Sigma and A^* U = V Sigma on the detected triplets; orthonormal bases
+    assert np.linalg.norm(A @ V[:, :rank] - U[:, :rank] * s[:rank]) < 1e-12 * sv[0]
+    assert np.linalg.norm(A.conj().T @ U[:, :rank] - V[:, :rank] * s[:rank]) < 1e-12 * sv[0]
+    assert np.linalg.norm(U[:, :rank].conj().T @ U[:, :rank] - np.eye(rank)) < 1e-12
+
+
+def test_lanczos_restarts_after_an_early_stop():
+    # p1 in the span of two right singular vectors: the plain recurrence stops after
+    # two steps; the early-stop check must detect it and restart to the full rank
+    rng = _rng(901)
+    sv = np.array([5.0, 3.0, 2.0, 1.0, 0.5])
+    A, X, Y = _low_rank(rng, 60, 60, sv)
+    U, s, V, rank = O.lanczos_bidiagonalization(A, Y[:, 0] + 2 * Y[:, 2], 60 * O.EPS64, _vectors(rng, 60, 8))
+    assert rank == len(sv)
+    assert np.max(np.abs(s[:rank] - sv) / sv) < 1e-12
+
+
+def test_lanczos_matches_lapack_on_toeplitz_and_paper_ranks(golden_dir):
+    inst = config_instances("c0")[0]
+    grid = O.samples(inst.t, inst.c, inst.n)
+    T = O.toeplitz(grid, inst.d, inst.n, 0)
+    N = T.shape[0]
+    rng = _rng(902)
+    U, s, V, rank = O.lanczos_bidiagonalization(T, _vectors(rng, N, 1)[0], N * O.EPS64, _vectors(rng, N, 8))
+    s_ref = np.linalg.svd(T, compute_uv=False)
+    assert rank == inst.m
+    assert np.max(np.abs(s[:inst.m] - s_ref[:inst.m]) / s_ref[:inst.m]) < 1e-11
+    # Sec. 5: all SVD methods found the same (sometimes deficient) rank at d = 2, n = 20
+    rows = [line.split() for line in open(f"{golden_dir}/rank_detection.txt")
+            if line.strip() and not line.startswith("#")]
+    for d, n, m, rel in rows:
+        d, n, m = int(d), int(n), int(m)
+        t, c = paper_efficiency_inputs(d, m)
+        T = O.toeplitz(O.samples(t, c, n), d, n, 0)
+        N = T.shape[0]
+        rng = _rng(903 + m)
+        _, _, _, rank = O.lanczos_bidiagonalization(T, _vectors(rng, N, 1)[0], N * O.EPS64, _vectors(rng, N, 8))
+        assert (rank == m) if rel == "eq" else (rank < m), (d, n, m, rank)
