@@ -56,8 +56,12 @@ typedef enum {
 
 typedef enum {
     PRONY_FP64 = 0,      /* complex128 operands, FP64 MFMA, FP64 accumulation            */
-    PRONY_FP32 = 1       /* complex64 operands, FP32 MFMA with FP32 accumulation per tile,
+    PRONY_FP32 = 1,      /* complex64 operands, FP32 MFMA with FP32 accumulation per tile,
                             FP64 reduction of the tile partials and FP64 Sigma^{-1}       */
+    PRONY_BF16X3 = 2     /* prony_build_S only: both operands split into three bfloat16
+                            terms (x = h + m + l, 24 significant bits), the six products
+                            above 2^-24 on the bf16 MFMA with FP32 accumulation; then as
+                            PRONY_FP32. Same error scale as PRONY_FP32.                   */
 } prony_prec_t;
 
 /* Flag of prony_build_S: also form S_0 = U^* T V Sigma^{-1} (equal to I for an
@@ -107,7 +111,8 @@ prony_status_t prony_profile_read(prony_handle_t handle, int* launches, double* 
    workgroups run (default 4 per compute unit). With flag PRONY_TUNE_BATCHED the
    entry applies to instances of that shape inside batches and gives the number
    of chunks per instance (default 1: split only as far as the LDS window
-   requires). target_wgs = 0 removes the entry.
+   requires). target_wgs = 0 removes the entry. PRONY_BF16X3 entries exist for
+   single instances only (batches run PRONY_FP32 or PRONY_FP64).
    Entries live in the handle. */
 #define PRONY_TUNE_BATCHED 1u
 prony_status_t prony_tune_set(prony_handle_t handle, int d, int n, int m, prony_prec_t prec, unsigned flags,
@@ -145,7 +150,7 @@ prony_status_t prony_build_T(prony_handle_t handle, int d, int n, int which,
    U, V:   N x m complex128; entry (k, j) at U + 2*(k*u_rs + j*u_cs) (strides in
            complex elements, both >= 1). V is the right factor itself, not V^*.
    sigma:  m doubles > 0 (device memory).
-   prec:   PRONY_FP64 or PRONY_FP32 (see prony_prec_t).
+   prec:   PRONY_FP64, PRONY_FP32 or PRONY_BF16X3 (see prony_prec_t).
    flags:  0 or PRONY_WITH_S0.
    S:      output, (d or d+1) x m x m complex128, row-major per matrix: S_l(i,j)
            at S + 2*((l*m + i)*m + j), l counted from the first stored matrix.

@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "PRONY_OK", 1: "PRONY_EINVAL", 2: "PRONY_ENOTSUP", 3: "PRONY_
 
 PRONY_FP64 = 0
 PRONY_FP32 = 1
+PRONY_BF16X3 = 2
 PRONY_WITH_S0 = 1
 PRONY_TUNE_BATCHED = 1
 

@@ -107,12 +107,16 @@ def build_T(f: torch.Tensor, d: int, n: int, which: int = 0, out: torch.Tensor |
     return out
 
 
+_S_PRECS = {"fp64": _lib.PRONY_FP64, "fp32": _lib.PRONY_FP32, "bf16x3": _lib.PRONY_BF16X3}
+
+
 def build_S(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,
             prec: str = "fp64", with_s0: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
     """S_l = U^* T_l V Sigma^{-1}, l = 1..d (prony_build_S); shape (d[+1], m, m).
 
     V is the right factor itself (torch.linalg.svd returns V^* as Vh: pass Vh.mH).
-    prec: 'fp64' or 'fp32'.
+    prec: 'fp64', 'fp32' or 'bf16x3' (three-term bfloat16 splits on the bf16 MFMA,
+    same error scale as 'fp32').
     """
     _require(f, "f", torch.complex128)
     dev = f.device
@@ -127,8 +131,8 @@ def build_S(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tenso
     m = U.shape[1]
     if sigma.shape != (m,):
         raise ValueError("sigma must have shape (m,)")
-    if prec not in ("fp64", "fp32"):
-        raise ValueError("prec must be 'fp64' or 'fp32'")
+    if prec not in _S_PRECS:
+        raise ValueError("prec must be 'fp64', 'fp32' or 'bf16x3'")
     ells = d + (1 if with_s0 else 0)
     if out is None:
         out = torch.empty((ells, m, m), dtype=torch.complex128, device=dev)
@@ -137,8 +141,7 @@ def build_S(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tenso
         if out.shape != (ells, m, m):
             raise ValueError("out has the wrong shape")
     _call("prony_build_S", dev, d, n, m, _ptr(f), _ptr(U), U.stride(0), U.stride(1), _ptr(sigma),
-          _ptr(V), V.stride(0), V.stride(1), _lib.PRONY_FP32 if prec == "fp32" else _lib.PRONY_FP64,
-          _lib.PRONY_WITH_S0 if with_s0 else 0, _ptr(out))
+          _ptr(V), V.stride(0), V.stride(1), _S_PRECS[prec], _lib.PRONY_WITH_S0 if with_s0 else 0, _ptr(out))
     return out
 
 

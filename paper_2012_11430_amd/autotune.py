@@ -57,9 +57,12 @@ def _write(path, data):
     os.replace(tmp, path)
 
 
+_PRECS = {"fp64": _lib.PRONY_FP64, "fp32": _lib.PRONY_FP32, "bf16x3": _lib.PRONY_BF16X3}
+
+
 def register(device: torch.device, d: int, n: int, m: int, prec: str, batched: bool, target: int) -> None:
-    api._call("prony_tune_set", device, d, n, m, _lib.PRONY_FP32 if prec == "fp32" else _lib.PRONY_FP64,
-              _lib.PRONY_TUNE_BATCHED if batched else 0, int(target))
+    api._call("prony_tune_set", device, d, n, m, _PRECS[prec], _lib.PRONY_TUNE_BATCHED if batched else 0,
+              int(target))
 
 
 def load_cache(device: torch.device, path: str | None = None) -> int:

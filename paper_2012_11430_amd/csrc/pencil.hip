@@ -54,6 +54,8 @@ struct PencilPlan {
     int d, n, N, m;
     int mode;       // 0: S-build (extended h', U^* epilogue); 1: product Y = T X (h in I_n)
     int conj_grid;  // product mode: stage conj(f(-p)), i.e. multiply by T^* instead of T
+    int split;      // 1: operands as three bfloat16 terms on the bf16 MFMA (T = float)
+    int bbufs;      // split: LDS buffers of the staged B planes (2, or 1 when two do not fit)
     int ells;       // stacked matrices: d, or d + 1 with S_0
     int first_ell;  // 0 with S_0, else 1
     int C;          // complex columns ells * m
@@ -82,6 +84,85 @@ __host__ __device__ inline int h_offset(const PencilPlan& P, int hx) {
     return P.mode ? grid_offset_of_index(hx, P.d, P.n) : ext_offset(hx, P.d, P.n);
 }
 
+// Three-term bfloat16 split x = h + m + l (each term rounded to nearest; the
+// subtractions are exact in FP32, so x - (h + m + l) is below 2^-24 |x|).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// 16-byte unit of the split operands (a native vector: copies stay in registers)
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kSplitK = 32;     // h' per K block of the bf16 MFMA (16x16x32)
+constexpr int kSplitPlanes = 3; // stored B planes per K block: the Re-multiplier's h, m, l
+__device__ __forceinline__ void split3(float x, unsigned short& h, unsigned short& m, unsigned short& l) {
+    const __bf16 bh = (__bf16)x;
+    float r = x - (float)bh;
+    const __bf16 bm = (__bf16)r;
+    r -= (float)bm;
+    const __bf16 bl = (__bf16)r;
+    h = __builtin_bit_cast(unsigned short, bh);
+    m = __builtin_bit_cast(unsigned short, bm);
+    l = __builtin_bit_cast(unsigned short, bl);
+}
+
+// Pair values of the second operand at (row hx, real column j): .x multiplies
+// Re(a), .y multiplies Im(a) (see pack_body).
+__device__ __forceinline__ double2 pair_of(const PencilPlan& P, const double2* __restrict__ V, int64_t v_rs,
+                                           int64_t v_cs, int hx, int j) {
+    const int c = j >> 1;
+    double vr = 0.0, vi = 0.0;
+    if (hx < P.kb && c < P.C) {
+        const int E = P.n + 2, Pn = P.n + 1;
+        const int li = c / P.m, q = c - li * P.m;
+        const int ell = li + P.first_ell;
+        int rem = hx, idx = 0, scale = 1;
+        bool inside = true;
+        for (int l = P.d - 1; l >= 0; --l) {
+            const int qq = rem / E;
+            const int coord = rem - qq * E - 1 + (l == ell - 1 ? 1 : 0);
+            rem = qq;
+            inside = inside && coord >= 0 && coord <= P.n;
+            idx += coord * scale;
+            scale *= Pn;
+        }
+        if (inside) {
+            const double2 v = V[idx * v_rs + q * v_cs];
+            vr = v.x;
+            vi = v.y;
+        }
+    }
+    return (j & 1) ? make_double2(vi, vr) : make_double2(vr, -vi);
+}
+
+// Split packing of the second operand: per K block of 32 h', per plane p (the
+// h, m, l terms of the Re-multiplier .x of the pair layout) and real column j, the 32
+// bfloat16 values of rows h' = 32 kblk .. 32 kblk + 31, ordered so that element t
+// of MFMA lane group g is h' = 32 kblk + 4 t + g (interleaved: the four lane groups
+// then read neighbouring window entries, which keeps the LDS reads free of bank
+// conflicts); a thread makes the eight rows of one lane group (16 bytes per plane).
+// The Im-multiplier is not stored: .y of column j is -.x of column j + 1 (j even)
+// or .x of column j - 1 (j odd), which the tile kernel forms in registers.
+__device__ __forceinline__ void pack_split(const PencilPlan& P, const double2* __restrict__ V, int64_t v_rs,
+                                           int64_t v_cs, u32x4* __restrict__ vp16, int first, int stride) {
+    const int nunits = (P.sk * P.kc / kSplitK) * P.nrp * 4;
+    for (int i = first; i < nunits; i += stride) {
+        const int t8 = i & 3, rest = i >> 2;
+        const int kblk = rest / P.nrp, j = rest - (rest / P.nrp) * P.nrp;
+        unsigned short w[kSplitPlanes][8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const double2 pr = pair_of(P, V, v_rs, v_cs, kblk * kSplitK + 4 * t + t8, j);
+            split3((float)pr.x, w[0][t], w[1][t], w[2][t]);
+        }
+#pragma unroll
+        for (int p = 0; p < kSplitPlanes; ++p) {
+            u32x4 u;
+            u.x = w[p][0] | ((unsigned)w[p][1] << 16);
+            u.y = w[p][2] | ((unsigned)w[p][3] << 16);
+            u.z = w[p][4] | ((unsigned)w[p][5] << 16);
+            u.w = w[p][6] | ((unsigned)w[p][7] << 16);
+            vp16[((size_t)(kblk * kSplitPlanes + p) * P.nrp + j) * 4 + t8] = u;
+        }
+    }
+}
+
 // Packs, per call: (y = 0) the stacked shifted factors V_l in the pair layout,
 // rows h' of the extended index set padded with zeros to sk*kc + kPrefetchRows;
 // (y = 1) the (Re U, Im U) pairs, rows padded to whole 64-row tiles and
@@ -95,7 +176,9 @@ __device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __
     const int kbp = P.sk * P.kc + kPrefetchRows;
     const int stride = gridDim.x * blockDim.x;
     const int first = blockIdx.x * blockDim.x + threadIdx.x;
-    if (section == 0) {
+    if (section == 0 && P.split) {
+        pack_split(P, V, v_rs, v_cs, reinterpret_cast<u32x4*>(vp), first, stride);
+    } else if (section == 0) {
         const int E = P.n + 2, Pn = P.n + 1;
         const int nv = kbp * P.nrp;
         for (int i = first; i < nv; i += stride) {
@@ -182,8 +265,9 @@ struct TilePtrs {
 // One workgroup tile of the S-build: rows 64 rt_i .. +63 of I_n against chunk
 // sk_i of the extended indices h', where L = sk_i * rt + rt_i. See the file
 // comment for the formulation.
-template <typename T, int NB, int RF, int MODE>
+template <typename T, int NB, int RF, int MODE, bool SPLIT = false>
 __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>& ptr, const int L) {
+    static_assert(!SPLIT || sizeof(T) == 4, "the split operands accumulate in FP32");
     using T2 = pair_t<T>;
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
@@ -197,8 +281,12 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     extern __shared__ __align__(16) unsigned char smem[];
     // Phase 1 (K loop): grid window + h' offsets. Phase 2 (U^* reduction): the
     // same bytes hold one slab of results per wave.
+    // window entries: complex<T>, or for split operands 16 bytes
+    // (Re h | Im h, Re m | Im m, Re l | Im l, 0) as bfloat16 pairs
+    constexpr size_t kEntry = SPLIT ? 16 : sizeof(T2);
     T2* win = reinterpret_cast<T2*>(smem);
-    int* gt = reinterpret_cast<int*>(smem + align_up(sizeof(T2) * (size_t)P.win_cap, 16));
+    u32x4* win16 = reinterpret_cast<u32x4*>(smem);
+    int* gt = reinterpret_cast<int*>(smem + align_up(kEntry * (size_t)P.win_cap, 16));
     T* slab = reinterpret_cast<T*>(smem);
 
     const int tid = threadIdx.x;
@@ -223,7 +311,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // gt[g * stride + s] = G(h' = h_first + 4 s + g), so one 16-byte LDS read
     // gives a lane the offsets of four consecutive K steps.
     constexpr int kStage = 8;
-    const int ngt = P.kc + kPrefetchRows;
+    const int ngt = SPLIT ? P.kc : P.kc + kPrefetchRows;
     const int gstride = ngt >> 2;
     for (int base = 0; base < max(W, ngt); base += kStage * kThreads) {
         double2 v[kStage];
@@ -237,10 +325,35 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 #pragma unroll
         for (int j = 0; j < kStage; ++j) {
             const int w = base + j * kThreads + tid;
-            if (w < W) win[w] = T2{(T)v[j].x, reflect ? -(T)v[j].y : (T)v[j].y};
-            if (w < ngt) gt[(w & 3) * gstride + (w >> 2)] = o[j];
+            if constexpr (SPLIT) {
+                if (w < W) {
+                    unsigned short rh, rm, rl, ih, im, il;
+                    split3((float)v[j].x, rh, rm, rl);
+                    split3((float)v[j].y, ih, im, il);
+                    win16[w] = u32x4{rh | ((unsigned)ih << 16), rm | ((unsigned)im << 16), rl | ((unsigned)il << 16), 0u};
+                }
+                // per K block, h' = 4 t + g at 8 g + t: a lane reads its 8 offsets as two int4
+                if (w < ngt) gt[(w & ~31) | ((w & 3) << 3) | ((w & 31) >> 2)] = o[j];
+            } else {
+                if (w < W) win[w] = T2{(T)v[j].x, reflect ? -(T)v[j].y : (T)v[j].y};
+                if (w < ngt) gt[(w & 3) * gstride + (w >> 2)] = o[j];
+            }
         }
     }
+    // Split operands: the six B planes of one K block (32 h') are staged in LDS
+    // (two buffers, or one); the four 16-byte units of a column are XOR-swizzled by
+    // bits 1..2 of the column, the pattern under which a ds_read_b128 of 16 columns
+    // x 4 lane groups runs without bank conflicts on gfx950 (measured).
+    u32x4* bst = reinterpret_cast<u32x4*>(smem + align_up(kEntry * (size_t)P.win_cap, 16) +
+                                          align_up(4 * ((size_t)P.kc + kPrefetchRows + 16), 16));
+    const int bunits = kSplitPlanes * P.nrp * 4;  // 16-byte units of one K block
+    const u32x4* bsrc = reinterpret_cast<const u32x4*>(vp) + (size_t)(h_first / kSplitK) * bunits;
+    auto bslot = [&](int e) {
+        const int row = e >> 2;                   // plane * nrp + column j
+        return (row << 2) | ((e & 3) ^ (((row - (row / P.nrp) * P.nrp) >> 1) & 3));
+    };
+    if constexpr (SPLIT)
+        for (int e = tid; e < bunits; e += kThreads) bst[bslot(e)] = bsrc[e];
     __syncthreads();
 
     // Rows of this wave: k_first + 16 (RF wave + f) + col for fragment f.
@@ -285,6 +398,104 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 #pragma unroll
             for (int cb = 0; cb < NB; ++cb) acc[f][cb] = M::fma(av[f].y, bv[cb].y, acc[f][cb]);
     };
+    if constexpr (SPLIT) {
+        constexpr int kVecB = (kSplitPlanes * 16 * NB * 4 + kThreads - 1) / kThreads;
+        // Im-multiplier from the Re-multiplier of the neighbouring column (lane col ^ 1):
+        // negated (sign bits of both bfloat16 halves) on even columns
+        const unsigned neg = (col & 1) ? 0u : 0x80008000u;
+        auto im_of = [neg](const u32x4& x) {
+            u32x4 y;
+            y.x = (unsigned)__builtin_amdgcn_mov_dpp((int)x.x, 0xB1, 0xF, 0xF, false) ^ neg;
+            y.y = (unsigned)__builtin_amdgcn_mov_dpp((int)x.y, 0xB1, 0xF, 0xF, false) ^ neg;
+            y.z = (unsigned)__builtin_amdgcn_mov_dpp((int)x.z, 0xB1, 0xF, 0xF, false) ^ neg;
+            y.w = (unsigned)__builtin_amdgcn_mov_dpp((int)x.w, 0xB1, 0xF, 0xF, false) ^ neg;
+            return y;
+        };
+        const int nkb = P.kc / kSplitK;
+        const int swz = (col >> 1) & 3;
+        auto mfma = [](const bf16x8& x, const bf16x8& y, acc_t c) {
+            return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+        };
+        // the buffer count is a compile-time constant of each loop copy: a
+        // barrier under a run-time condition sends the staging registers to scratch
+        auto kloop = [&](auto two_buffers) {
+        constexpr bool kTwo = decltype(two_buffers)::value;
+        for (int kb = 0; kb < nkb; ++kb) {
+            const int nxt = min(kb + 1, nkb - 1);
+            u32x4 stg[kVecB];
+#pragma unroll
+            for (int u = 0; u < kVecB; ++u) stg[u] = bsrc[(size_t)nxt * bunits + min(tid + u * kThreads, bunits - 1)];
+            __builtin_amdgcn_sched_barrier(0);   // issue the next block's loads before this block's MFMAs
+            const int4 o0 = *reinterpret_cast<const int4*>(gt + kSplitK * kb + 8 * g);
+            const int4 o1 = *reinterpret_cast<const int4*>(gt + kSplitK * kb + 8 * g + 4);
+            const int offs[8] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
+            // A terms of each fragment: element t of lane group g is h' = 32 kb + 4 t + g
+            bf16x8 ar[RF][3], ai[RF][3];
+#pragma unroll
+            for (int f = 0; f < RF; ++f) {
+                u32x4 e[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) e[t] = win16[gk[f] - offs[t]];
+                unsigned re[3][4], im[3][4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const u32x4 lo = e[2 * k], hi = e[2 * k + 1];
+                    re[0][k] = (lo.x & 0xffffu) | (hi.x << 16);
+                    im[0][k] = (lo.x >> 16) | (hi.x & 0xffff0000u);
+                    re[1][k] = (lo.y & 0xffffu) | (hi.y << 16);
+                    im[1][k] = (lo.y >> 16) | (hi.y & 0xffff0000u);
+                    re[2][k] = (lo.z & 0xffffu) | (hi.z << 16);
+                    im[2][k] = (lo.z >> 16) | (hi.z & 0xffff0000u);
+                }
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    ar[f][q] = __builtin_bit_cast(bf16x8, u32x4{re[q][0], re[q][1], re[q][2], re[q][3]});
+                    ai[f][q] = __builtin_bit_cast(bf16x8, u32x4{im[q][0], im[q][1], im[q][2], im[q][3]});
+                }
+            }
+            const u32x4* bb = bst + (kTwo ? (kb & 1) * bunits : 0);
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                bf16x8 b[2 * kSplitPlanes];
+#pragma unroll
+                for (int pl = 0; pl < kSplitPlanes; ++pl) {
+                    const u32x4 x = bb[((pl * P.nrp + 16 * cb + col) << 2) | (g ^ swz)];
+                    b[pl] = __builtin_bit_cast(bf16x8, x);
+                    b[kSplitPlanes + pl] = __builtin_bit_cast(bf16x8, im_of(x));
+                }
+                // the six products of the three-term splits above 2^-24 (h h, h m, m h, h l, l h, m m)
+#pragma unroll
+                for (int f = 0; f < RF; ++f) {
+                    acc_t c = acc[f][cb];
+                    c = mfma(ar[f][2], b[0], c);
+                    c = mfma(ar[f][0], b[2], c);
+                    c = mfma(ar[f][1], b[1], c);
+                    c = mfma(ar[f][1], b[0], c);
+                    c = mfma(ar[f][0], b[1], c);
+                    c = mfma(ar[f][0], b[0], c);
+                    c = mfma(ai[f][2], b[3], c);
+                    c = mfma(ai[f][0], b[5], c);
+                    c = mfma(ai[f][1], b[4], c);
+                    c = mfma(ai[f][1], b[3], c);
+                    c = mfma(ai[f][0], b[4], c);
+                    c = mfma(ai[f][0], b[3], c);
+                    acc[f][cb] = c;
+                }
+            }
+            // with two buffers the other one was last read before the previous barrier;
+            // with one, every wave must be done with it first
+            if constexpr (!kTwo) __syncthreads();
+            u32x4* wb = bst + (kTwo ? ((kb + 1) & 1) * bunits : 0);
+#pragma unroll
+            for (int u = 0; u < kVecB; ++u) wb[bslot(min(tid + u * kThreads, bunits - 1))] = stg[u];
+            __syncthreads();
+        }
+        };
+        if (P.bbufs == 2)
+            kloop(std::integral_constant<bool, true>{});
+        else
+            kloop(std::integral_constant<bool, false>{});
+    } else {
     int4 gc = gq[0];
     load_a(a[0], gc.x);
     load_a(a[1], gc.y);
@@ -316,6 +527,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         mma(a[3], b[3]);
         __builtin_amdgcn_sched_barrier(0);
         gc = gn;
+    }
     }
 
     if constexpr (MODE == 1) {
@@ -419,6 +631,14 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, TilePtrs<
     tile_body<T, NB, RF, 0>(P, ptr, L);
 }
 
+// S-build tiles with split operands (FP32-accurate products on the bf16 MFMA).
+template <int NB, int RF>
+__global__ __launch_bounds__(kThreads) void pencil_tiles_split(PencilPlan P, TilePtrs<float> ptr) {
+    const int id = blockIdx.x;
+    const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
+    tile_body<float, NB, RF, 0, true>(P, ptr, L);
+}
+
 // Y = T X (or T^* X) for a block of columns: tiles of the product, partial
 // over the K chunks (summed by toeplitz_mm_finish).
 template <typename T, int NB, int RF>
@@ -484,8 +704,10 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntr
     tile_body<T, NB, RF, 0>(e.P, e.ptr, id - e.tile_begin);
 }
 
-size_t lds_bytes_for(int win, int kc, int nbp, size_t tsize) {
-    const size_t loop = align_up(2 * tsize * (size_t)win, 16) + 4 * ((size_t)kc + kPrefetchRows + 16);
+size_t lds_bytes_for(int win, int kc, int nbp, size_t tsize, int split_nrp = 0, int bbufs = 2) {
+    const size_t entry = split_nrp ? 16 : 2 * tsize;
+    const size_t loop = align_up(entry * (size_t)win, 16) + align_up(4 * ((size_t)kc + kPrefetchRows + 16), 16) +
+                        (split_nrp ? (size_t)bbufs * kSplitPlanes * split_nrp * 64 : 0);
     const size_t epi = tsize * (size_t)kWaves * 16 * 16 * nbp;   // one 16 x 16nbp slab per wave
     return align_up(std::max(loop, epi), 16);
 }
@@ -515,13 +737,14 @@ int tuned_target(prony_handle_t h, int d, int n, int m, int prec, int batched) {
 // mode 1 plans the product Y = T X of a block of m columns (h over I_n, no
 // shifted copies, no U^* epilogue).
 prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P,
-                         int target_wgs = 0, bool allow_rf2 = false, int mode = 0) {
+                         int target_wgs = 0, bool allow_rf2 = false, int mode = 0, bool split = false) {
     P = PencilPlan{};
     P.d = d;
     P.n = n;
     P.N = (int)ipow(n + 1, d);
     P.m = m;
     P.mode = mode;
+    P.split = split ? 1 : 0;
     P.ells = mode ? 1 : d + (with_s0 ? 1 : 0);
     P.first_ell = mode || with_s0 ? 0 : 1;
     P.C = P.ells * m;
@@ -534,17 +757,26 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.rt = (P.N + P.rows - 1) / P.rows;
     P.c0 = grid_center(d, n);
 
-    const size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
+    // two workgroups per CU; the split kernel, which also stages B planes, may
+    // take the whole LDS when its window does not fit otherwise
+    size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
     P.nbp = std::max(1, std::min(P.nb, (int)(budget / (tsize * kWaves * 16 * 16))));
+    P.bbufs = 2;
     const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
-    int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), 16);
-    kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, 16)));
+    const size_t kal = split ? kSplitK : 16;   // chunk granularity: K blocks of the MFMA loop
+    int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), kal);
+    kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, kal)));
+    const int kc0 = kc;
     const int rowspan = max_span(P.N, P.rows, d, n, false);
     for (;;) {
         const int colspan = max_span(P.kb, kc, d, n, !mode);
         const int win = rowspan + colspan + 1;
-        const size_t lds = lds_bytes_for(win, kc, mode ? 0 : P.nbp, tsize);
+        size_t lds = lds_bytes_for(win, kc, mode ? 0 : P.nbp, tsize, split ? P.nrp : 0, 2);
+        if (split && lds > budget) {   // one B buffer (two barriers per K block) before smaller chunks
+            P.bbufs = 1;
+            lds = lds_bytes_for(win, kc, mode ? 0 : P.nbp, tsize, P.nrp, 1);
+        }
         if (lds <= budget) {
             P.kc = kc;
             P.sk = (P.kb + kc - 1) / kc;
@@ -552,8 +784,17 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
             P.lds_bytes = lds;
             break;
         }
-        if (kc <= 16) return fail(h, PRONY_ENOTSUP, "prony_build_S: sample window does not fit in LDS");
-        kc = (int)align_up((size_t)(kc / 2), 16);
+        if (kc <= (int)kal) {
+            if (split && budget < h->lds_per_block) {   // retry from the first chunk size
+                budget = h->lds_per_block;
+                kc = kc0;
+                P.bbufs = 2;
+                continue;
+            }
+            return fail(h, PRONY_ENOTSUP, "prony_build_S: sample window does not fit in LDS");
+        }
+        kc = (int)align_up((size_t)(kc / 2), kal);
+        P.bbufs = 2;
     }
     P.nwg = P.rt * P.sk;
     if (((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp >= (int64_t(1) << 31) ||
@@ -564,7 +805,10 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     const size_t tot = (size_t)P.m * P.C;
     size_t off = 0;
     P.off_v = off;
-    off = align_up(off + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
+    if (split)   // three bfloat16 planes per K block, 32 values per (plane, column)
+        off = align_up(off + ((size_t)P.sk * P.kc / kSplitK) * kSplitPlanes * P.nrp * 64, 256);
+    else
+        off = align_up(off + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
     P.off_u = off;
     off = align_up(off + t2 * (size_t)P.rt * P.rows * P.mbi * 16, 256);
     P.off_g = off;
@@ -622,15 +866,33 @@ prony_status_t launch_batched(prony_handle_t h, const BatchEntry<T>* entries, in
     return PRONY_OK;
 }
 
+template <int NB, int RF>
+prony_status_t launch_tiles_split(prony_handle_t h, const PencilPlan& P, const TilePtrs<float>& ptr) {
+    if (P.lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles_split<NB, RF>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+        if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+    }
+    ProfileScope prof(h, "pencil_tiles");
+    pencil_tiles_split<NB, RF><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
+    return PRONY_OK;
+}
+
 #define PRONY_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
 template <typename T>
 prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
     switch (P.nb) {
-#define PRONY_CASE(NBV)                                         \
-    case NBV:                                                   \
-        if constexpr (rf2_supported(sizeof(T), NBV))            \
-            if (P.rf == 2) return launch_tiles<T, NBV, 2>(h, P, ptr); \
+#define PRONY_CASE(NBV)                                                    \
+    case NBV:                                                              \
+        if constexpr (sizeof(T) == 4)                                      \
+            if (P.split) {                                                 \
+                if constexpr (rf2_supported(4, NBV))                       \
+                    if (P.rf == 2) return launch_tiles_split<NBV, 2>(h, P, ptr); \
+                return launch_tiles_split<NBV, 1>(h, P, ptr);              \
+            }                                                              \
+        if constexpr (rf2_supported(sizeof(T), NBV))                       \
+            if (P.rf == 2) return launch_tiles<T, NBV, 2>(h, P, ptr);      \
         return launch_tiles<T, NBV, 1>(h, P, ptr);
         PRONY_NB_CASES(PRONY_CASE)
 #undef PRONY_CASE
@@ -782,15 +1044,17 @@ extern "C" prony_status_t prony_build_S(prony_handle_t h, int d, int n, int m, c
         return fail(h, PRONY_EINVAL, "prony_build_S: strides must be >= 1");
     if ((N - 1) * u_rs + (m - 1) * u_cs >= (int64_t(1) << 40) || (N - 1) * v_rs + (m - 1) * v_cs >= (int64_t(1) << 40))
         return fail(h, PRONY_EINVAL, "prony_build_S: strides out of range");
-    if (prec != PRONY_FP64 && prec != PRONY_FP32) return fail(h, PRONY_EINVAL, "prony_build_S: bad precision");
+    if (prec != PRONY_FP64 && prec != PRONY_FP32 && prec != PRONY_BF16X3)
+        return fail(h, PRONY_EINVAL, "prony_build_S: bad precision");
     if (flags & ~PRONY_WITH_S0) return fail(h, PRONY_EINVAL, "prony_build_S: unknown flag");
     if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     const bool s0 = (flags & PRONY_WITH_S0) != 0;
     PencilPlan P;
-    if (prec == PRONY_FP32) {
-        if ((st = make_plan(h, d, n, m, s0, sizeof(float), P, tuned_target(h, d, n, m, prec, 0), true)) != PRONY_OK)
+    if (prec == PRONY_FP32 || prec == PRONY_BF16X3) {
+        if ((st = make_plan(h, d, n, m, s0, sizeof(float), P, tuned_target(h, d, n, m, prec, 0), true, 0,
+                            prec == PRONY_BF16X3)) != PRONY_OK)
             return st;
         return launch_pencil<float>(h, P, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
     }
@@ -1105,7 +1369,8 @@ extern "C" prony_status_t prony_tune_set(prony_handle_t h, int d, int n, int m, 
                                          int target_wgs) {
     if (!h) return PRONY_EINVAL;
     if (d < 1 || d > 3 || n < 1 || m < 1 || m > 32) return fail(h, PRONY_EINVAL, "prony_tune_set: bad shape");
-    if (prec != PRONY_FP64 && prec != PRONY_FP32) return fail(h, PRONY_EINVAL, "prony_tune_set: bad precision");
+    if (prec != PRONY_FP64 && prec != PRONY_FP32 && !(prec == PRONY_BF16X3 && flags == 0))
+        return fail(h, PRONY_EINVAL, "prony_tune_set: bad precision");
     if (flags & ~PRONY_TUNE_BATCHED) return fail(h, PRONY_EINVAL, "prony_tune_set: unknown flag");
     if (target_wgs < 0 || target_wgs > (1 << 20)) return fail(h, PRONY_EINVAL, "prony_tune_set: bad target");
     const auto key = std::make_tuple(d, n, m, (int)prec, (flags & PRONY_TUNE_BATCHED) ? 1 : 0);

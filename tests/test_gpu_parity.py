@@ -3,7 +3,7 @@
 Tolerances: T and the index maps are exact copies (bitwise); samples within
 1e-13 * sum|c_j|; Gram/rhs within 1e-12 relative; S_l normwise relative error
 max_l ||S_l - S_l^oracle||_F / ||S_l^oracle||_F <= 1e-12 on the FP64 path and
-<= 1e-5 on the FP32 path.
+<= 1e-5 on the FP32 path and on the split-bfloat16 (bf16x3) path.
 """
 import functools
 import sys
@@ -19,7 +19,7 @@ from workload import config_instances, random_orthonormal
 pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda:0")
-TOL = {"fp64": 1e-12, "fp32": 1e-5}
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-5}
 
 
 def _say(msg):
@@ -125,7 +125,7 @@ def _check_S(inst, grid, U, s, V, prec, with_s0):
     return got, errs
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("with_s0", [False, True])
 def test_build_S_c0(prec, with_s0):
     inst, grid, U, s, V = _problem("c0")
@@ -134,14 +134,14 @@ def test_build_S_c0(prec, with_s0):
         assert np.max(np.abs(got[0] - np.eye(inst.m))) < 10 * TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_build_S_c1_full_size(prec):
     _say(f"build_S c1 {prec}")
     inst, grid, U, s, V = _problem("c1")
     _check_S(inst, grid, U, s, V, prec, with_s0=True)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_build_S_c2_full_size(prec):
     _say(f"build_S c2 {prec}")
     inst, grid, U, s, V = _problem("c2", level_index=4)
@@ -153,7 +153,7 @@ CASES = [(1, 1, 1), (1, 63, 5), (1, 200, 32), (2, 1, 2), (2, 4, 16), (2, 9, 17),
 
 
 @pytest.mark.parametrize("d,n,m", CASES)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_build_S_ragged_random(d, n, m, prec):
     # arbitrary grids and factors: several row tiles and h' chunks with ragged tails
     rng = np.random.Generator(np.random.PCG64(1000 * d + 10 * n + m))
@@ -181,12 +181,27 @@ def test_build_S_strided_factors():
     assert max(_rel(got[l], ref[l]) for l in range(inst.d)) <= 1e-12
 
 
-def test_build_S_is_deterministic():
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_build_S_is_deterministic(prec):
     inst, grid, U, s, V = _problem("c1")
     args = (_dev(grid), inst.d, inst.n, _dev(U), _dev(s), _dev(V))
-    a = api.build_S(*args, prec="fp32")
-    b = api.build_S(*args, prec="fp32")
+    a = api.build_S(*args, prec=prec)
+    b = api.build_S(*args, prec=prec)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("d,n,m", [(1, 200, 32), (3, 6, 31), (2, 63, 20)])
+def test_build_S_bf16x3_single_buffer_plans(d, n, m):
+    # wide factors: the staged B planes fit LDS only once, or only in smaller chunks
+    rng = np.random.Generator(np.random.PCG64(77 + d + n + m))
+    N, G = (n + 1) ** d, (2 * n + 2) ** d
+    grid = rng.standard_normal(G) + 1j * rng.standard_normal(G)
+    U = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+    V = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+    s = rng.uniform(0.5, 2.0, m)
+    ref = O.pencil_matrices(grid, d, n, U, s, V, with_s0=True)
+    got = api.build_S(_dev(grid), d, n, _dev(U), _dev(s), _dev(V), prec="bf16x3", with_s0=True).cpu().numpy()
+    assert max(_rel(got[l], ref[l]) for l in range(d + 1)) <= TOL["bf16x3"]
 
 
 def test_build_S_eigenvalues_are_the_nodes_c0():
