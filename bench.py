@@ -445,18 +445,25 @@ def batched_c3(dev, args):
     else:
         autotune.load_cache(dev)
     batch = api.Batch(dev_inst, prec="fp32")
-    batch.capture()
     reps = max(3, args.steps // 4)
-    for _ in range(2):
-        batch.replay()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        batch.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_graph = e0.elapsed_time(e1) / reps
+
+    def time_graph():
+        batch.capture()
+        for _ in range(2):
+            batch.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            batch.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    batch.set_schedule("classes")
+    ms_classes = time_graph()
+    batch.set_schedule("queue")        # the FP32 default: one persistent launch over all tiles
+    ms_graph = time_graph()
 
     outs = [torch.empty_like(S) for S in batch.S]
 
@@ -480,6 +487,8 @@ def batched_c3(dev, args):
         "instances_per_s_fp64_per_instance_loop": round(n_inst / (ms_loop * 1e-3), 1),
         "speedup": round(ms_loop / ms_graph, 2),
         "ms_fp32_graph": round(ms_graph, 4),
+        "schedule": "queue (one persistent launch, LPT work items)",
+        "ms_fp32_graph_class_launches": round(ms_classes, 4),
         "ms_fp64_loop": round(ms_loop, 4),
         "tflops_fp32_graph": round(flops / (ms_graph * 1e-3) / 1e12, 3),
         "rel_err_fp32_vs_fp64": float(f"{rel:.3e}"),

@@ -228,20 +228,40 @@ typedef struct {
 
 /* Plan the S-build of `count` (1..65535) instances (host array of descriptors, copied):
    validates every descriptor, chooses tiles per instance, groups the instances
-   by column-block count, orders them by decreasing work, allocates the batch's
-   own device workspace and uploads its work table (synchronously on the
-   handle's stream). Errors name the offending instance. */
+   by column-block count, orders them by decreasing work, builds the queue of all
+   tiles (longest first), allocates the batch's own device workspace and uploads
+   its work tables (synchronously on the handle's stream). Errors name the
+   offending instance. */
 prony_status_t prony_batch_create(prony_handle_t handle, int count, const prony_instance_t* instances,
                                   prony_prec_t prec, prony_batch_t* batch);
 
 /* Free a batch (waits for the stream of the handle that created it). */
 prony_status_t prony_batch_destroy(prony_batch_t batch);
 
+/* How prony_build_S_batched runs the tiles of a batch (a system pattern, not in
+   the paper):
+   PRONY_SCHEDULE_QUEUE   — one persistent launch (as many workgroups as fit the
+                            device at once) that takes (instance, tile) work items,
+                            longest first, from a counter the packing launch resets.
+                            FP32 batches only; their default.
+   PRONY_SCHEDULE_CLASSES — one launch per class of instances with the same
+                            column-block count and row fragments, spread over the
+                            handle's stream and three auxiliary streams (forked after
+                            the packing launch, joined before the finishing launch).
+                            The FP64 batches' only schedule.
+   Both compute the same tiles and the same fixed-order sums: their results are
+   bitwise equal. */
+#define PRONY_SCHEDULE_QUEUE 0
+#define PRONY_SCHEDULE_CLASSES 1
+/* Select the schedule of a batch (EINVAL for an unknown value, ENOTSUP for the
+   queue on an FP64 batch). Takes effect at the next prony_build_S_batched. */
+prony_status_t prony_batch_set_schedule(prony_batch_t batch, int schedule);
+
 /* Enqueue the S-build of every instance of the batch on the handle's stream:
-   one packing launch for all instances, one launch per column-block class and
-   one finishing launch (fixed-order sums, Sigma^{-1}) for all instances.
-   Allocates nothing and records no memset, so it can be captured. The handle
-   must be the one that created the batch. */
+   one packing launch for all instances, the tile launch(es) of the batch's
+   schedule and one finishing launch (fixed-order sums, Sigma^{-1}) for all
+   instances. Allocates nothing and records no memset, so it can be captured.
+   The handle must be the one that created the batch. */
 prony_status_t prony_build_S_batched(prony_handle_t handle, prony_batch_t batch);
 
 /* Adjoint of prony_build_S_batched: prony_build_S_adjoint for every instance of

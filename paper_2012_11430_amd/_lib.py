@@ -26,6 +26,8 @@ PRONY_FP32 = 1
 PRONY_BF16X3 = 2
 PRONY_WITH_S0 = 1
 PRONY_TUNE_BATCHED = 1
+PRONY_SCHEDULE_QUEUE = 0
+PRONY_SCHEDULE_CLASSES = 1
 
 class InstanceDesc(ctypes.Structure):
     """prony_instance_t."""
@@ -57,6 +59,7 @@ SIGNATURES = {
                                _ptr, _c_int, _ptr], _c_int),
     "prony_batch_create": ([_ptr, _c_int, ctypes.POINTER(InstanceDesc), _c_int, ctypes.POINTER(_ptr)], _c_int),
     "prony_batch_destroy": ([_ptr], _c_int),
+    "prony_batch_set_schedule": ([_ptr, _c_int], _c_int),
     "prony_build_S_batched": ([_ptr, _ptr], _c_int),
     "prony_build_S_adjoint_batched": ([_ptr, _ptr, _ptr, _ptr], _c_int),
     "prony_toeplitz_mm": ([_ptr, _c_int, _c_int, _c_int, _ptr, _c_int, _ptr, _c_i64, _c_int, _ptr, _c_i64], _c_int),

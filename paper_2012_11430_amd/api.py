@@ -287,6 +287,22 @@ class Batch:
               _lib.PRONY_FP32 if prec == "fp32" else _lib.PRONY_FP64, ctypes.byref(out))
         self.handle = out
 
+    def set_schedule(self, schedule: str) -> None:
+        """'queue' (one persistent launch over all tiles, FP32 only; the FP32
+        default) or 'classes' (one launch per column-block class; the FP64 one)
+        — prony_batch_set_schedule. Results are bitwise equal."""
+        codes = {"queue": _lib.PRONY_SCHEDULE_QUEUE, "classes": _lib.PRONY_SCHEDULE_CLASSES}
+        if schedule not in codes:
+            raise ValueError("schedule must be 'queue' or 'classes'")
+        lib = _lib.load()
+        if self.graph is not None:     # a captured graph holds the old schedule's launches
+            lib.prony_graph_destroy(self.graph)
+            self.graph = None
+        st = lib.prony_batch_set_schedule(self.handle, codes[schedule])
+        if st != _lib.PRONY_OK:
+            msg = lib.prony_last_error(_handle(self.device))
+            raise _lib.PronyError(st, f"prony_batch_set_schedule: {msg.decode() if msg else ''}")
+
     def run(self) -> None:
         """Enqueue the S-build of every instance (prony_build_S_batched)."""
         _call("prony_build_S_batched", self.device, self.handle)

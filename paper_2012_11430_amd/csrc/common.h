@@ -146,5 +146,12 @@ struct prony_batch_s {
         double work;   // sum of nwg * kc over the class (MFMA work, up to a factor)
     };
     std::vector<ClassLaunch> launches;
+    // queue schedule (FP32): one persistent launch over all tiles, longest first
+    int schedule = PRONY_SCHEDULE_CLASSES;
+    void* queue_counter = nullptr;   // device int, reset by the packing launch
+    void* queue_items = nullptr;     // device WorkItem[queue_n]
+    int queue_n = 0;
+    int queue_grid = 0;
+    size_t queue_lds = 0;
     prony::AdjBatch* adj = nullptr;
 };

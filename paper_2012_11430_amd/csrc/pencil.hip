@@ -676,9 +676,13 @@ struct BatchEntry {
     int tile_begin;
 };
 
-// Packing for every instance of a batch: grid (x, 3, instances).
+// Packing for every instance of a batch: grid (x, 3, instances). The first
+// thread also resets the work counter of the queue schedule (the tile launch
+// follows on the same stream).
 template <typename T>
-__global__ __launch_bounds__(256) void pencil_pack_batched(const BatchEntry<T>* __restrict__ entries) {
+__global__ __launch_bounds__(256) void pencil_pack_batched(const BatchEntry<T>* __restrict__ entries,
+                                                           int* __restrict__ queue_counter) {
+    if (queue_counter && (blockIdx.x | blockIdx.y | blockIdx.z | threadIdx.x) == 0) *queue_counter = 0;
     const BatchEntry<T>& e = entries[blockIdx.z];
     pack_body<T>(e.P, e.U, e.P.m, 1, e.V, e.P.m, 1, const_cast<pair_t<T>*>(e.ptr.vp),
                  const_cast<pair_t<T>*>(e.ptr.up), const_cast<int*>(e.ptr.gtab), blockIdx.y);
@@ -879,6 +883,51 @@ prony_status_t launch_tiles_split(prony_handle_t h, const PencilPlan& P, const T
 }
 
 #define PRONY_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+// Work item of the queue schedule: a tile L of the instance at position `entry`
+// of the batch's entry table.
+struct WorkItem {
+    int entry;
+    int tile;
+};
+
+// One tile of any class: the instantiation is chosen per item from the
+// instance's column blocks and row fragments.
+template <typename T>
+__device__ __forceinline__ void tile_of_class(const BatchEntry<T>& e, int L) {
+    switch (e.P.nb * 2 + e.P.rf - 1) {
+#define PRONY_QCASE(NBV)                                           \
+    case NBV * 2:                                                  \
+        tile_body<T, NBV, 1, 0>(e.P, e.ptr, L);                    \
+        break;                                                     \
+    case NBV * 2 + 1:                                              \
+        if constexpr (rf2_supported(sizeof(T), NBV)) tile_body<T, NBV, 2, 0>(e.P, e.ptr, L); \
+        break;
+        PRONY_NB_CASES(PRONY_QCASE)
+#undef PRONY_QCASE
+        default:
+            break;
+    }
+}
+
+// Queue schedule of a batch: one persistent launch of as many workgroups as fit
+// the device at once; each takes the next work item (all tiles of all
+// instances, longest first) from a counter until the queue is empty.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void pencil_tiles_queue(const BatchEntry<T>* __restrict__ entries,
+                                                               const WorkItem* __restrict__ items, int nitems,
+                                                               int* __restrict__ counter) {
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();   // every thread has read `next` (and left the previous tile's LDS)
+        if (it >= nitems) break;
+        const WorkItem w = items[it];
+        tile_of_class<T>(entries[w.entry], w.tile);
+    }
+}
 
 template <typename T>
 prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
@@ -1119,9 +1168,16 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         if (plans[a].rf != plans[b].rf) return plans[a].rf < plans[b].rf;
         return (int64_t)plans[a].kc * plans[a].rf > (int64_t)plans[b].kc * plans[b].rf;
     });
-    // workspace layout: entries, then per instance vp | up | gt | part
+    // work items of the queue schedule (FP32): every tile of every instance,
+    // longest first; tiles of one instance stay in L order
+    size_t nitems = 0;
+    for (int i = 0; i < count; ++i) nitems += (size_t)plans[i].nwg;
+    if (nitems > (size_t)INT32_MAX) return fail(h, PRONY_ENOTSUP, "prony_batch_create: too many tiles");
+    // workspace layout: entries, queue counter, work items, then per instance vp | up | gt | part
     const size_t t2 = 2 * sizeof(T);
-    size_t off = align_up(sizeof(BatchEntry<T>) * (size_t)count, 256);
+    const size_t off_counter = align_up(sizeof(BatchEntry<T>) * (size_t)count, 256);
+    const size_t off_items = off_counter + 256;
+    size_t off = align_up(off_items + sizeof(WorkItem) * nitems, 256);
     std::vector<BatchEntry<T>> host(count);
     std::vector<size_t> base(count);
     for (int pos = 0; pos < count; ++pos) {
@@ -1184,7 +1240,27 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     for (int i = 0; i < count; ++i)
         B->finish_x = std::max(B->finish_x, (plans[i].m * plans[i].C + kFinishOuts - 1) / kFinishOuts);
     B->entries = ws;
+    std::vector<WorkItem> items;
+    items.reserve(nitems);
+    std::vector<int> by_cost(count);
+    for (int pos = 0; pos < count; ++pos) by_cost[pos] = pos;
+    auto cost = [&](int pos) { return (int64_t)host[pos].P.kc * host[pos].P.rf * host[pos].P.nb; };
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    for (int pos : by_cost)
+        for (int L = 0; L < host[pos].P.nwg; ++L) items.push_back({pos, L});
+    B->queue_counter = w + off_counter;
+    B->queue_items = w + off_items;
+    B->queue_n = (int)nitems;
+    B->queue_lds = 0;
+    for (int pos = 0; pos < count; ++pos) B->queue_lds = std::max(B->queue_lds, host[pos].P.lds_bytes);
+    // resident workgroups per CU: LDS (dynamic + the kernel's 16 static bytes), and
+    // at most 2 (the kernel's registers allow 2 waves per SIMD)
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, h->lds_per_block / (B->queue_lds + 16)));
+    B->queue_grid = (int)std::min<size_t>(nitems, (size_t)per_cu * h->num_cus);
+    B->schedule = sizeof(T) == 4 ? PRONY_SCHEDULE_QUEUE : PRONY_SCHEDULE_CLASSES;
     e = hipMemcpyAsync(ws, host.data(), sizeof(BatchEntry<T>) * (size_t)count, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w + off_items, items.data(), sizeof(WorkItem) * nitems, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "batch work table upload");
     return PRONY_OK;
@@ -1193,12 +1269,34 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
 template <typename T>
 prony_status_t batch_launch(prony_handle_t h, prony_batch_s* B) {
     const BatchEntry<T>* entries = static_cast<const BatchEntry<T>*>(B->entries);
+    const bool queue = B->schedule == PRONY_SCHEDULE_QUEUE;
+    int* counter = queue ? static_cast<int*>(B->queue_counter) : nullptr;
     {
         ProfileScope prof(h, "pencil_pack");
-        pencil_pack_batched<T><<<dim3(B->pack_x, 3, B->count), 256, 0, h->stream>>>(entries);
+        pencil_pack_batched<T><<<dim3(B->pack_x, 3, B->count), 256, 0, h->stream>>>(entries, counter);
     }
     prony_status_t st = check_launch(h, "pencil_pack_batched");
     if (st != PRONY_OK) return st;
+    if (queue) {
+        if constexpr (sizeof(T) == 4) {
+            if (B->queue_lds > 65536) {
+                hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles_queue<T>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)B->queue_lds);
+                if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+            }
+            {
+                ProfileScope prof(h, "pencil_tiles_batched");
+                pencil_tiles_queue<T><<<B->queue_grid, kThreads, B->queue_lds, h->stream>>>(
+                    entries, static_cast<const WorkItem*>(B->queue_items), B->queue_n, counter);
+            }
+            if ((st = check_launch(h, "pencil_tiles_queue")) != PRONY_OK) return st;
+            ProfileScope prof(h, "pencil_finish");
+            pencil_finish_batched<T><<<dim3(B->finish_x, B->count), kFinishThreads, 0, h->stream>>>(entries);
+            return check_launch(h, "pencil_finish_batched");
+        } else {
+            return fail(h, PRONY_ENOTSUP, "prony_build_S_batched: the queue schedule is FP32 only");
+        }
+    }
     // The class launches are independent: they run on the handle's stream and up
     // to kAux auxiliary streams (forked after the packing launch, joined before
     // the finishing launch), each class on the lane with the least work so far
@@ -1295,6 +1393,17 @@ extern "C" prony_status_t prony_batch_destroy(prony_batch_t B) {
     }
     delete B;
     return st;
+}
+
+extern "C" prony_status_t prony_batch_set_schedule(prony_batch_t B, int schedule) {
+    if (!B) return PRONY_EINVAL;
+    prony_handle_t h = B->owner;
+    if (schedule != PRONY_SCHEDULE_QUEUE && schedule != PRONY_SCHEDULE_CLASSES)
+        return fail(h, PRONY_EINVAL, "prony_batch_set_schedule: unknown schedule");
+    if (schedule == PRONY_SCHEDULE_QUEUE && B->prec != PRONY_FP32)
+        return fail(h, PRONY_ENOTSUP, "prony_batch_set_schedule: the queue schedule is FP32 only");
+    B->schedule = schedule;
+    return PRONY_OK;
 }
 
 extern "C" prony_status_t prony_build_S_batched(prony_handle_t h, prony_batch_t B) {

@@ -121,6 +121,7 @@ def test_batch_validation(vhandle):
     assert lib.prony_batch_create(h, 0, arr, _lib.PRONY_FP64, ctypes.byref(out)) == _lib.PRONY_EINVAL
     assert lib.prony_batch_create(h, 3, arr, 9, ctypes.byref(out)) == _lib.PRONY_EINVAL
     assert lib.prony_build_S_batched(h, NULL) == _lib.PRONY_EINVAL
+    assert lib.prony_batch_set_schedule(NULL, _lib.PRONY_SCHEDULE_QUEUE) == _lib.PRONY_EINVAL
     assert lib.prony_build_S_adjoint_batched(h, NULL, P, P) == _lib.PRONY_EINVAL
     assert lib.prony_build_S_adjoint_batched(NULL, NULL, P, P) == _lib.PRONY_EINVAL
     assert lib.prony_graph_launch(h, NULL) == _lib.PRONY_EINVAL

@@ -94,6 +94,38 @@ def test_full_c3_batch_matches_single_instance_calls():
         batch.close()
 
 
+def test_queue_schedule_is_bitwise_equal_to_class_launches():
+    # the same tiles and fixed-order sums under both schedules (FP32, full c3 batch)
+    dev_inst = _device_instances(_c3_inputs(512))
+    batch = api.Batch(dev_inst, prec="fp32")
+    _say("queue vs class schedules: 512 instances")
+    batch.run()                        # default schedule of an FP32 batch: queue
+    torch.cuda.synchronize()
+    queued = [S.clone() for S in batch.S]
+    for S in batch.S:
+        S.zero_()
+    batch.set_schedule("classes")
+    batch.run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(queued, batch.S))
+    batch.set_schedule("queue")        # and back: a second queue run resets its counter
+    for S in batch.S:
+        S.zero_()
+    batch.run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(queued, batch.S))
+    batch.close()
+
+
+def test_queue_schedule_rejected_for_fp64():
+    batch = api.Batch(_device_instances(_c3_inputs(512)[:4]), prec="fp64")
+    with pytest.raises(api._lib.PronyError):
+        batch.set_schedule("queue")
+    with pytest.raises(ValueError):
+        batch.set_schedule("fifo")
+    batch.close()
+
+
 def test_graph_replays_match_eager_run():
     inputs = _c3_inputs(512)[:96]
     dev_inst = _device_instances(inputs)
