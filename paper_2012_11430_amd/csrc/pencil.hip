@@ -1257,7 +1257,9 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     // at most 2 (the kernel's registers allow 2 waves per SIMD)
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, h->lds_per_block / (B->queue_lds + 16)));
     B->queue_grid = (int)std::min<size_t>(nitems, (size_t)per_cu * h->num_cus);
-    B->schedule = sizeof(T) == 4 ? PRONY_SCHEDULE_QUEUE : PRONY_SCHEDULE_CLASSES;
+    // several classes: one persistent launch over all of them; one class is one
+    // launch already, and its own kernel keeps more workgroups resident
+    B->schedule = sizeof(T) == 4 && B->launches.size() > 1 ? PRONY_SCHEDULE_QUEUE : PRONY_SCHEDULE_CLASSES;
     e = hipMemcpyAsync(ws, host.data(), sizeof(BatchEntry<T>) * (size_t)count, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(w + off_items, items.data(), sizeof(WorkItem) * nitems, hipMemcpyHostToDevice, h->stream);

@@ -99,7 +99,7 @@ def test_queue_schedule_is_bitwise_equal_to_class_launches():
     dev_inst = _device_instances(_c3_inputs(512))
     batch = api.Batch(dev_inst, prec="fp32")
     _say("queue vs class schedules: 512 instances")
-    batch.run()                        # default schedule of an FP32 batch: queue
+    batch.run()                        # default schedule of a several-class FP32 batch: queue
     torch.cuda.synchronize()
     queued = [S.clone() for S in batch.S]
     for S in batch.S:
