@@ -11,16 +11,24 @@
 // The second factor is packed once per call in that pair layout.
 //
 // Kernels:
-//   pencil_pack   packs V_l (pair layout), U (Re/Im pairs) and the grid
-//                 offsets G(h') of the extended index set into the workspace;
-//   pencil_tiles  one workgroup = 64 rows k x one chunk of h'; the T_ext tile
-//                 is generated from a flat window of the sample grid staged in
-//                 LDS, multiplied on MFMA against the packed V_l, then the
-//                 U^* reduction over the 64 rows runs on MFMA as well and the
-//                 m x (d m) partial is stored.
-//                 The last workgroups to finish reduce the partials of all
-//                 workgroups in FP64 in a fixed order and apply Sigma^{-1} in
-//                 FP64 (no separate reduction launch).
+//   pencil_pack         packs V_l (pair layout, or bfloat16 split planes), U
+//                       (Re/Im pairs) and the grid offsets G(h') of the extended
+//                       index set into the workspace;
+//   pencil_tiles        one workgroup = 64 rf rows k x one chunk of h'; the T_ext
+//                       tile is generated from a flat window of the sample grid
+//                       staged in LDS, multiplied on MFMA (FP32 or FP64) against
+//                       the packed V_l, then the U^* reduction over the tile's rows
+//                       runs on MFMA as well and the m x (d m) partial is stored;
+//   pencil_tiles_split  the same tile with both operands as three bfloat16 terms
+//                       on the bf16 MFMA (FP32-accurate products);
+//   pencil_finish       sums the partials of all workgroups in FP64 in a fixed
+//                       order and applies Sigma^{-1} in FP64;
+//   toeplitz_mm_tiles / toeplitz_mm_finish
+//                       the product mode Y = T X or T^* X (h over I_n, no U^*);
+//   pencil_pack_batched / pencil_tiles_batched / pencil_tiles_queue /
+//   pencil_finish_batched
+//                       many instances: one launch per tile class, or one
+//                       persistent launch over a queue of all tiles.
 #include <algorithm>
 #include <cmath>
 #include <new>

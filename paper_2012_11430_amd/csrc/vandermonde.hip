@@ -45,11 +45,11 @@ __device__ __forceinline__ void emit_gram(int m, double2* __restrict__ gram, dou
         rhs[e - m * m] = make_double2(re, im);
 }
 
-// One workgroup takes `chunks` consecutive 64-row chunks of I_n. Per chunk the
+// One workgroup takes `chunks` consecutive 16-row chunks of I_n. Per chunk the
 // rows of A^T are evaluated into LDS, then every thread accumulates its fixed
 // entries of (A^T)^* [A^T | f_I] over the chunk in FP64 registers. The
-// workgroup's sums are stored; the last workgroup to finish adds them up in
-// workgroup order (bitwise reproducible) and writes gram and rhs.
+// workgroup's sums are stored as one row of partials; coeffs_finish adds the
+// rows in workgroup order (bitwise reproducible) and writes gram and rhs.
 __global__ __launch_bounds__(kThreads) void coeffs_tiles(int d, int n, int N, int m, int chunks,
                                                          const double2* __restrict__ z,
                                                          const double2* __restrict__ f, double2* __restrict__ at_out,
