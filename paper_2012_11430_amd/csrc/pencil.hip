@@ -447,13 +447,14 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                 unsigned re[3][4], im[3][4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
+                    // byte permutes of {hi : lo}: low halves (Re) and high halves (Im)
                     const u32x4 lo = e[2 * k], hi = e[2 * k + 1];
-                    re[0][k] = (lo.x & 0xffffu) | (hi.x << 16);
-                    im[0][k] = (lo.x >> 16) | (hi.x & 0xffff0000u);
-                    re[1][k] = (lo.y & 0xffffu) | (hi.y << 16);
-                    im[1][k] = (lo.y >> 16) | (hi.y & 0xffff0000u);
-                    re[2][k] = (lo.z & 0xffffu) | (hi.z << 16);
-                    im[2][k] = (lo.z >> 16) | (hi.z & 0xffff0000u);
+                    re[0][k] = __builtin_amdgcn_perm(hi.x, lo.x, 0x05040100u);
+                    im[0][k] = __builtin_amdgcn_perm(hi.x, lo.x, 0x07060302u);
+                    re[1][k] = __builtin_amdgcn_perm(hi.y, lo.y, 0x05040100u);
+                    im[1][k] = __builtin_amdgcn_perm(hi.y, lo.y, 0x07060302u);
+                    re[2][k] = __builtin_amdgcn_perm(hi.z, lo.z, 0x05040100u);
+                    im[2][k] = __builtin_amdgcn_perm(hi.z, lo.z, 0x07060302u);
                 }
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
