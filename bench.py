@@ -303,7 +303,7 @@ PAPER_T_S = {5: 0.1100, 10: 0.1199, 15: 0.1290, 20: 0.1495}
 
 def paper_workload(dev, args, per_call_ms):
     """The paper's efficiency workload on this GPU: the S-build (FP64, the paper's
-    arithmetic, and FP32-MFMA) for m = 5..20 against the paper's t_S, the whole GPU
+    arithmetic, FP32-MFMA and split bfloat16) for m = 5..20 against the paper's t_S, the whole GPU
     path of Algorithm 1 (samples, power SVD with GPU block products, S, nodes,
     Gram/rhs, LS), and the Lanczos SVD (Algorithm 2) with GPU products."""
     import numpy as np
@@ -345,7 +345,7 @@ def paper_workload(dev, args, per_call_ms):
         row = {"paper_t_S_s": PAPER_T_S[m], "lanczos_svd_gpu_products": lanczos,
                "paper_gflops": round(s_flops(d, N, m) / PAPER_T_S[m] / 1e9, 1),
                "algorithm1_gpu_path_s": round(wall, 4), "svd_sweeps": sweeps}
-        for prec in ("fp64", "fp32"):
+        for prec in ("fp64", "fp32", "bf16x3"):
             for _ in range(args.warmup):
                 api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
             ms = float(np.median(per_call_ms(lambda: api.build_S(f, d, n, Ud, sd, Vd, prec=prec), 10)))
@@ -370,8 +370,9 @@ def _match_errors(t_est, c_est, t_true, c_true):
 
 def noise_sweep_c2(dev, args):
     """c2 (d=3, n=19, N=8000, m=30) over its noise levels: the SVD by Algorithm 3
-    with GPU block products (T is never formed), S in FP32-MFMA and FP64, and the
-    recovered t_j, c_j of both against the truth, with the S-build times."""
+    with GPU block products (T is never formed), S in FP64, FP32-MFMA and split
+    bfloat16, and the recovered t_j, c_j of each against the truth, with the
+    S-build times."""
     import numpy as np
     import torch
 
@@ -393,7 +394,7 @@ def noise_sweep_c2(dev, args):
         Ud, sd, Vd = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (U, s, V))
         row = {"noise": level, "svd_sweeps": sweeps}
         S = {}
-        for prec in ("fp64", "fp32"):
+        for prec in ("fp64", "fp32", "bf16x3"):
             api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -408,7 +409,8 @@ def noise_sweep_c2(dev, args):
             ms = e0.elapsed_time(e1)
             row[prec] = {"s_build_ms": round(ms, 4), "tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 2),
                          "max_dt_vs_truth": float(f"{dt:.3e}"), "rel_dc_vs_truth": float(f"{dc:.3e}")}
-        row["s_rel_diff_fp32_vs_fp64"] = float(f"{float(torch.linalg.norm(S['fp32'] - S['fp64']) / torch.linalg.norm(S['fp64'])):.3e}")
+        for p in ("fp32", "bf16x3"):
+            row[f"s_rel_diff_{p}_vs_fp64"] = float(f"{float(torch.linalg.norm(S[p] - S['fp64']) / torch.linalg.norm(S['fp64'])):.3e}")
         rows.append(row)
     return {"workload": "c2: d=3, n=19, N=8000, m=30, separation 0.08, |c| log-uniform [1e-2, 1]", "levels": rows}
 

@@ -248,7 +248,7 @@ def test_coeffs_ragged(d, n, m):
 def test_end_to_end_c0_exact_recovery():
     inst = config_instances("c0")[0]
     f = api.samples(_dev(inst.t), _dev(inst.c), inst.n)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         sol = host.solve(f, inst.d, inst.n, inst.m, inst.mu, prec=prec)
         dt, dc = O.recovery_errors(dict(t=sol.t, c=sol.c), inst.t, inst.c)
         if prec == "fp64":
@@ -265,7 +265,7 @@ def test_end_to_end_c1_against_oracle_pipeline():
     cr, _ = O.least_squares_coefficients(zr, grid, inst.d, inst.n)
     dt_ref, dc_ref = O.recovery_errors(dict(t=tr, c=cr), inst.t, inst.c)
     fd = _dev(grid)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         S = api.build_S(fd, inst.d, inst.n, _dev(U), _dev(s), _dev(V), prec=prec).cpu().numpy()
         z, t = host.nodes(S, inst.mu)
         gram, rhs = api.coeffs(_dev(z), fd, inst.d, inst.n)
