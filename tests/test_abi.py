@@ -76,6 +76,18 @@ def test_build_S_argument_checks(vhandle):
     assert lib.prony_build_S(h, 2, 15, 5, P, P, 5, 1, P, P, 5, 1, 0, 2, P) == _lib.PRONY_EINVAL
     # S_0 flag accepted
     assert lib.prony_build_S(h, 2, 15, 5, P, P, 5, 1, P, P, 5, 1, 0, _lib.PRONY_WITH_S0, P) == _lib.PRONY_ENODEV
+    # the split-bfloat16 precision is a valid request for the S-build only
+    assert lib.prony_build_S(h, 2, 15, 5, P, P, 5, 1, P, P, 5, 1, _lib.PRONY_BF16X3, 0, P) == _lib.PRONY_ENODEV
+    assert lib.prony_build_S(h, 2, 15, 5, P, P, 5, 1, P, P, 5, 1, 3, 0, P) == _lib.PRONY_EINVAL
+    assert lib.prony_build_S_adjoint(h, 2, 15, 5, P, 5, 1, P, P, 5, 1, P, _lib.PRONY_BF16X3, P) == _lib.PRONY_EINVAL
+    assert lib.prony_toeplitz_mm(h, 2, 15, 0, P, 4, P, 4, _lib.PRONY_BF16X3, P, 4) == _lib.PRONY_EINVAL
+    arr = (_lib.InstanceDesc * 1)(_desc(2, 15, 5))
+    out = ctypes.c_void_p()
+    assert lib.prony_batch_create(h, 1, arr, _lib.PRONY_BF16X3, ctypes.byref(out)) == _lib.PRONY_EINVAL
+    # tuning entries: single-instance entries for every precision, batch entries for FP32/FP64
+    assert lib.prony_tune_set(h, 2, 15, 5, _lib.PRONY_BF16X3, 0, 512) == _lib.PRONY_OK
+    assert lib.prony_tune_set(h, 2, 15, 5, _lib.PRONY_BF16X3, _lib.PRONY_TUNE_BATCHED, 2) == _lib.PRONY_EINVAL
+    assert lib.prony_tune_set(h, 2, 15, 5, _lib.PRONY_BF16X3, 0, 0) == _lib.PRONY_OK
 
 
 def test_build_T_and_coeffs_argument_checks(vhandle):
