@@ -171,14 +171,15 @@ def test_build_S_ragged_random(d, n, m, prec):
     _check_S(inst, grid, U, s, V, prec, with_s0=(m % 2 == 1))
 
 
-def test_build_S_strided_factors():
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_build_S_strided_factors(prec):
     inst, grid, U, s, V = _problem("c0")
     ref = O.pencil_matrices(grid, inst.d, inst.n, U, s, V)
     Ut = _dev(U.T.copy()).T          # column-major storage: row stride 1, column stride N
     Vt = _dev(V.T.copy()).T
     assert Ut.stride() == (1, inst.N)
-    got = api.build_S(_dev(grid), inst.d, inst.n, Ut, _dev(s), Vt, prec="fp64").cpu().numpy()
-    assert max(_rel(got[l], ref[l]) for l in range(inst.d)) <= 1e-12
+    got = api.build_S(_dev(grid), inst.d, inst.n, Ut, _dev(s), Vt, prec=prec).cpu().numpy()
+    assert max(_rel(got[l], ref[l]) for l in range(inst.d)) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
