@@ -8,7 +8,8 @@ from oracle import prony_oracle as O
 
 _orig = {name: getattr(O, name) for name in
          ("samples", "toeplitz", "pencil_matrices", "vandermonde_transpose", "pencil_adjoint",
-          "nodes_from_pencil", "coefficient_products")}
+          "nodes_from_pencil", "coefficient_products", "toeplitz_product", "lanczos_bidiagonalization",
+          "_reorthogonalize")}
 
 
 def _samples_wrong_sign(t, c, n, abs_noise=None, rel_noise=None):
@@ -51,6 +52,31 @@ def _nodes_wrong_sign(S, mu):
     return z, np.mod(-t, 1.0), W
 
 
+def _product_ignores_adjoint(grid, d, n, X, adjoint=False):
+    return _orig["toeplitz_product"](grid, d, n, X, adjoint=False)
+
+
+def _product_transpose_without_conjugate(grid, d, n, X, adjoint=False):
+    T = _orig["toeplitz"](grid, d, n, 0)
+    return (T.T if adjoint else T) @ X
+
+
+def _product_reversed_shift(grid, d, n, X, adjoint=False):
+    # f(h - k) instead of f(k - h)
+    T = _orig["toeplitz"](grid, d, n, 0)
+    return (T.conj() if adjoint else T.T) @ X
+
+
+def _no_reorthogonalization(x, Q):
+    return x
+
+
+def _lanczos_stops_at_first_small_coefficient(A, p1, tol, restart_vectors=(), max_steps=None):
+    # the early-stop check skipped: a zero test vector makes every small coefficient end the process
+    zeros = [np.zeros(max(A.shape), dtype=complex)[: A.shape[1]] for _ in range(8)]
+    return _orig["lanczos_bidiagonalization"](A, p1, tol, zeros, max_steps)
+
+
 MUTANTS = [
     ("samples", _samples_wrong_sign,
      [pins.test_samples_on_rational_nodes_are_an_fft, pins.test_toeplitz_vandermonde_factorisation]),
@@ -61,6 +87,14 @@ MUTANTS = [
     ("vandermonde_transpose", _vandermonde_conj, [pins.test_vandermonde_matches_direct_exponentials]),
     ("pencil_adjoint", _adjoint_missing_conj, [pins.test_adjoint_dot_product_identity]),
     ("nodes_from_pencil", _nodes_wrong_sign, [pins.test_c0_noise_free_exact_recovery]),
+    ("toeplitz_product", _product_ignores_adjoint, [pins.test_toeplitz_product_adjoint_dot_product_identity]),
+    ("toeplitz_product", _product_transpose_without_conjugate,
+     [pins.test_toeplitz_product_adjoint_dot_product_identity]),
+    ("toeplitz_product", _product_reversed_shift, [pins.test_toeplitz_product_is_an_fft_convolution]),
+    ("_reorthogonalize", _no_reorthogonalization,
+     [pins.test_lanczos_recovers_prescribed_singular_values_and_rank, pins.test_lanczos_restarts_after_an_early_stop]),
+    ("lanczos_bidiagonalization", _lanczos_stops_at_first_small_coefficient,
+     [pins.test_lanczos_restarts_after_an_early_stop]),
 ]
 
 

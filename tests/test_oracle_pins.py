@@ -482,6 +482,38 @@ def _vectors(rng, n, count):
     return [rng.standard_normal(n) + 1j * rng.standard_normal(n) for _ in range(count)]
 
 
+@pytest.mark.parametrize("d,n,r", [(1, 5, 3), (2, 3, 2), (3, 2, 2)])
+def test_toeplitz_product_is_an_fft_convolution(d, n, r):
+    # (T X)[k] = sum_h f(k - h) X[h]: with F[p + n] = f(p), p in {-n..n+1}^d, the linear
+    # convolution C = F * X (by zero-padded FFTs) has (T X)[k] = C[k + n]
+    rng = _rng(300 + 10 * d + n)
+    G = (2 * n + 2) ** d
+    grid = rng.standard_normal(G) + 1j * rng.standard_normal(G)
+    X = rng.standard_normal(((n + 1) ** d, r)) + 1j * rng.standard_normal(((n + 1) ** d, r))
+    L = (2 * n + 2) + (n + 1) - 1
+    axes = tuple(range(d))
+    F = np.fft.fftn(grid.reshape((2 * n + 2,) * d), s=(L,) * d, axes=axes)
+    Y = np.empty_like(X)
+    for q in range(r):
+        C = np.fft.ifftn(F * np.fft.fftn(X[:, q].reshape((n + 1,) * d), s=(L,) * d, axes=axes), axes=axes)
+        Y[:, q] = C[(slice(n, 2 * n + 1),) * d].reshape(-1)
+    got = O.toeplitz_product(grid, d, n, X)
+    assert np.max(np.abs(got - Y)) < 1e-12 * np.max(np.abs(Y))
+
+
+def test_toeplitz_product_adjoint_dot_product_identity():
+    # <T X, Y> = <X, T^* Y> for random complex X, Y
+    rng = _rng(310)
+    d, n, r = 2, 4, 3
+    G, N = (2 * n + 2) ** d, (n + 1) ** d
+    grid = rng.standard_normal(G) + 1j * rng.standard_normal(G)
+    X = rng.standard_normal((N, r)) + 1j * rng.standard_normal((N, r))
+    Y = rng.standard_normal((N, r)) + 1j * rng.standard_normal((N, r))
+    lhs = np.vdot(O.toeplitz_product(grid, d, n, X), Y)
+    rhs = np.vdot(X, O.toeplitz_product(grid, d, n, Y, adjoint=True))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
 def test_lanczos_recovers_prescribed_singular_values_and_rank():
     rng = _rng(900)
     sv = np.array([7.0, 3.0, 2.5, 1.0, 0.25, 0.01])
