@@ -63,9 +63,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--prec", choices=["fp32", "fp64", "bf16x3"], default="fp32",
+                    help="S-build precision of the timed step (bf16x3: split bfloat16 on the bf16 MFMA)")
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2"])
-    ap.add_argument("--cpu-sample-steps", type=int, default=3,
+    ap.add_argument("--cpu-sample-steps", type=int, default=16,
                     help="oracle steps timed for the CPU baseline (0 skips it)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched (c3) and adjoint (c4) measurements")
@@ -227,7 +228,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3"}[args.prec],
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: d={d}, n={n}, N={N}, m={m}, additive noise {level:g}*max|c|",
