@@ -141,6 +141,25 @@ def test_build_S_c1_full_size(prec):
     _check_S(inst, grid, U, s, V, prec, with_s0=True)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_build_S_c1_every_tuner_target(prec):
+    # the launch configurations bench.py may time: every split target the autotuner
+    # chooses from (1, 2, 4, 8 x CUs), registered explicitly, then removed
+    from paper_2012_11430_amd import autotune
+    inst, grid, U, s, V = _problem("c1")
+    ref = O.pencil_matrices(grid, inst.d, inst.n, U, s, V)
+    cus = torch.cuda.get_device_properties(DEV).multi_processor_count
+    args = (_dev(grid), inst.d, inst.n, _dev(U), _dev(s), _dev(V))
+    try:
+        for c in autotune.SINGLE_CANDIDATES:
+            autotune.register(DEV, inst.d, inst.n, inst.m, prec, False, c * cus)
+            got = api.build_S(*args, prec=prec).cpu().numpy()
+            err = max(_rel(got[l], ref[l]) for l in range(inst.d))
+            assert err <= TOL[prec], (c, err)
+    finally:
+        autotune.register(DEV, inst.d, inst.n, inst.m, prec, False, 0)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_build_S_c2_full_size(prec):
     _say(f"build_S c2 {prec}")
