@@ -18,14 +18,15 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
 
 
-def test_tune_single_registers_caches_and_stays_correct(tmp_path):
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_tune_single_registers_caches_and_stays_correct(tmp_path, prec):
     path = str(tmp_path / "tune.json")
     d, n, m = 2, 31, 12
-    times = autotune.tune_single(DEV, d, n, m, "fp32", reps=3, path=path)
+    times = autotune.tune_single(DEV, d, n, m, prec, reps=3, path=path)
     assert len(times) == len(autotune.SINGLE_CANDIDATES) and all(t > 0 for t in times.values())
     data = json.load(open(path))
     entries = next(iter(data["devices"].values()))
-    assert entries[f"{d},{n},{m},fp32,single"] in times
+    assert entries[f"{d},{n},{m},{prec},single"] in times
     assert autotune.load_cache(DEV, path) == 1
     rng = np.random.Generator(np.random.PCG64(5))
     N = (n + 1) ** d
@@ -35,10 +36,10 @@ def test_tune_single_registers_caches_and_stays_correct(tmp_path):
     s = rng.uniform(0.5, 2, m)
     ref = O.pencil_matrices(grid, d, n, U, s, V)
     for target in (256, 2048):      # plans at both ends of the candidate range
-        autotune.register(DEV, d, n, m, "fp32", False, target)
-        got = api.build_S(_dev(grid), d, n, _dev(U), _dev(s), _dev(V), prec="fp32").cpu().numpy()
+        autotune.register(DEV, d, n, m, prec, False, target)
+        got = api.build_S(_dev(grid), d, n, _dev(U), _dev(s), _dev(V), prec=prec).cpu().numpy()
         assert max(np.linalg.norm(got[l] - ref[l]) / np.linalg.norm(ref[l]) for l in range(d)) <= 1e-5
-    autotune.register(DEV, d, n, m, "fp32", False, 0)
+    autotune.register(DEV, d, n, m, prec, False, 0)
 
 
 def test_tune_batch(tmp_path):
