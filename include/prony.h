@@ -257,7 +257,8 @@ prony_status_t prony_batch_destroy(prony_batch_t batch);
 #define PRONY_SCHEDULE_QUEUE 0
 #define PRONY_SCHEDULE_CLASSES 1
 /* Select the schedule of a batch (EINVAL for an unknown value, ENOTSUP for the
-   queue on an FP64 batch). Takes effect at the next prony_build_S_batched. */
+   queue on an FP64 batch). Takes effect at the next prony_build_S_batched or
+   prony_graph_capture; a graph captured before keeps the launches it recorded. */
 prony_status_t prony_batch_set_schedule(prony_batch_t batch, int schedule);
 
 /* Enqueue the S-build of every instance of the batch on the handle's stream:
