@@ -265,7 +265,9 @@ prony_status_t prony_batch_set_schedule(prony_batch_t batch, int schedule);
    one packing launch for all instances, the tile launch(es) of the batch's
    schedule and one finishing launch (fixed-order sums, Sigma^{-1}) for all
    instances. Allocates nothing and records no memset, so it can be captured.
-   The handle must be the one that created the batch. */
+   The handle must be the one that created the batch. Launches of one batch
+   share its workspace and work counter: they must not overlap (stream order,
+   as on the handle's stream, keeps them apart). */
 prony_status_t prony_build_S_batched(prony_handle_t handle, prony_batch_t batch);
 
 /* Adjoint of prony_build_S_batched: prony_build_S_adjoint for every instance of
