@@ -167,8 +167,8 @@ def test_build_S_c2_full_size(prec):
     _check_S(inst, grid, U, s, V, prec, with_s0=False)
 
 
-CASES = [(1, 1, 1), (1, 63, 5), (1, 200, 32), (2, 1, 2), (2, 4, 16), (2, 9, 17), (2, 20, 32),
-         (3, 1, 3), (3, 3, 8), (3, 6, 31)]
+CASES = [(1, 1, 1), (1, 3, 4), (1, 63, 5), (1, 200, 32), (2, 1, 2), (2, 1, 4), (2, 4, 16), (2, 9, 17),
+         (2, 20, 32), (3, 1, 3), (3, 1, 8), (3, 3, 8), (3, 6, 31)]   # m = N in (1,3,4), (2,1,4), (3,1,8)
 
 
 @pytest.mark.parametrize("d,n,m", CASES)
