@@ -118,6 +118,19 @@ prony_status_t prony_profile_read(prony_handle_t handle, int* launches, double* 
 prony_status_t prony_tune_set(prony_handle_t handle, int d, int n, int m, prony_prec_t prec, unsigned flags,
                               int target_wgs);
 
+/* The registered entry of a shape (0 when none). */
+prony_status_t prony_tune_get(prony_handle_t handle, int d, int n, int m, prony_prec_t prec, unsigned flags,
+                              int* target_wgs);
+
+/* Register the autotuner's cached entries for this handle's device. The cache is
+   the JSON file the Python autotuner writes (paper_2012_11430_amd/autotune.py):
+   {"devices": {"<arch name>:<compute units>": {"d,n,m,prec,mode": target, ...}},
+   "version": 1}, prec fp64 / fp32 / bf16x3, mode single / batch. Entries are
+   registered through prony_tune_set (same validation); a device without entries
+   registers nothing. EINVAL for a missing path, an unreadable file or a malformed
+   entry (entries before it stay registered); ENODEV on a validation-only handle. */
+prony_status_t prony_autotune(prony_handle_t handle, const char* cache_json_path);
+
 /* ---- Algorithm 1, GPU steps -------------------------------------------------- */
 
 /* Samples of the exponential sum (Sec. 1, eq. exp_sum), with the additive noise

@@ -60,6 +60,8 @@ SIGNATURES = {
     "prony_batch_create": ([_ptr, _c_int, ctypes.POINTER(InstanceDesc), _c_int, ctypes.POINTER(_ptr)], _c_int),
     "prony_batch_destroy": ([_ptr], _c_int),
     "prony_batch_set_schedule": ([_ptr, _c_int], _c_int),
+    "prony_tune_get": ([_ptr, _c_int, _c_int, _c_int, _c_int, ctypes.c_uint, ctypes.POINTER(_c_int)], _c_int),
+    "prony_autotune": ([_ptr, ctypes.c_char_p], _c_int),
     "prony_build_S_batched": ([_ptr, _ptr], _c_int),
     "prony_build_S_adjoint_batched": ([_ptr, _ptr, _ptr, _ptr], _c_int),
     "prony_toeplitz_mm": ([_ptr, _c_int, _c_int, _c_int, _ptr, _c_int, _ptr, _c_i64, _c_int, _ptr, _c_i64], _c_int),

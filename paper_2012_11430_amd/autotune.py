@@ -13,6 +13,7 @@ Cache file: $PRONY_TUNE_CACHE, else ~/.cache/prony_mi355x_tune.json.
 """
 from __future__ import annotations
 
+import ctypes
 import json
 import os
 
@@ -63,6 +64,20 @@ _PRECS = {"fp64": _lib.PRONY_FP64, "fp32": _lib.PRONY_FP32, "bf16x3": _lib.PRONY
 def register(device: torch.device, d: int, n: int, m: int, prec: str, batched: bool, target: int) -> None:
     api._call("prony_tune_set", device, d, n, m, _PRECS[prec], _lib.PRONY_TUNE_BATCHED if batched else 0,
               int(target))
+
+
+def registered(device: torch.device, d: int, n: int, m: int, prec: str, batched: bool) -> int:
+    """The registered target of a shape (0 when none) — prony_tune_get."""
+    out = ctypes.c_int(0)
+    api._call("prony_tune_get", device, d, n, m, _PRECS[prec], _lib.PRONY_TUNE_BATCHED if batched else 0,
+              ctypes.byref(out))
+    return out.value
+
+
+def load_cache_native(device: torch.device, path: str | None = None) -> None:
+    """Register the cached entries of this device through the library's own
+    loader (prony_autotune), as a C caller would."""
+    api._call("prony_autotune", device, (path or cache_path()).encode())
 
 
 def load_cache(device: torch.device, path: str | None = None) -> int:

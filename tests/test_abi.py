@@ -90,6 +90,23 @@ def test_build_S_argument_checks(vhandle):
     assert lib.prony_tune_set(h, 2, 15, 5, _lib.PRONY_BF16X3, 0, 0) == _lib.PRONY_OK
 
 
+def test_tune_entries_and_cache_loader(vhandle, tmp_path):
+    lib, h = vhandle
+    got = ctypes.c_int(-1)
+    assert lib.prony_tune_set(h, 3, 19, 30, _lib.PRONY_FP32, 0, 768) == _lib.PRONY_OK
+    assert lib.prony_tune_get(h, 3, 19, 30, _lib.PRONY_FP32, 0, ctypes.byref(got)) == _lib.PRONY_OK
+    assert got.value == 768
+    assert lib.prony_tune_get(h, 3, 19, 30, _lib.PRONY_FP32, _lib.PRONY_TUNE_BATCHED, ctypes.byref(got)) == 0
+    assert got.value == 0
+    assert lib.prony_tune_get(h, 3, 19, 30, _lib.PRONY_FP32, 4, ctypes.byref(got)) == _lib.PRONY_EINVAL
+    assert lib.prony_tune_set(h, 3, 19, 30, _lib.PRONY_FP32, 0, 0) == _lib.PRONY_OK
+    assert lib.prony_autotune(h, None) == _lib.PRONY_EINVAL
+    assert lib.prony_autotune(h, str(tmp_path / "missing.json").encode()) == _lib.PRONY_EINVAL
+    cache = tmp_path / "tune.json"
+    cache.write_text('{"devices": {}, "version": 1}')
+    assert lib.prony_autotune(h, str(cache).encode()) == _lib.PRONY_ENODEV   # needs the device's name
+
+
 def test_build_T_and_coeffs_argument_checks(vhandle):
     lib, h = vhandle
     assert lib.prony_build_T(h, 2, 15, 3, P, P, 256) == _lib.PRONY_EINVAL      # which > d

@@ -27,6 +27,12 @@ def test_tune_single_registers_caches_and_stays_correct(tmp_path, prec):
     data = json.load(open(path))
     entries = next(iter(data["devices"].values()))
     assert entries[f"{d},{n},{m},{prec},single"] in times
+    # the library's own loader (prony_autotune) reads the same cache
+    best = entries[f"{d},{n},{m},{prec},single"]
+    autotune.register(DEV, d, n, m, prec, False, 0)
+    assert autotune.registered(DEV, d, n, m, prec, False) == 0
+    autotune.load_cache_native(DEV, path)
+    assert autotune.registered(DEV, d, n, m, prec, False) == best
     assert autotune.load_cache(DEV, path) == 1
     rng = np.random.Generator(np.random.PCG64(5))
     N = (n + 1) ** d
@@ -67,3 +73,15 @@ def test_tune_batch(tmp_path):
             got = S.cpu().numpy()
             assert max(np.linalg.norm(got[l] - ref[l]) / np.linalg.norm(ref[l]) for l in range(len(ref))) <= 1e-5
         b.close()
+
+
+def test_native_cache_loader_rejects_malformed_entries(tmp_path):
+    key = autotune._device_key(DEV)
+    bad = tmp_path / "bad.json"
+    bad.write_text(json.dumps({"devices": {key: {"2,15,5,fp99,single": 3}}, "version": 1}))
+    with pytest.raises(api._lib.PronyError):
+        autotune.load_cache_native(DEV, str(bad))
+    other = tmp_path / "other.json"     # entries of another device only: nothing registered
+    other.write_text(json.dumps({"devices": {"gfx000:1": {"2,15,5,fp32,single": 3}}, "version": 1}))
+    autotune.load_cache_native(DEV, str(other))
+    assert autotune.registered(DEV, 2, 15, 5, "fp32", False) == 0
