@@ -474,6 +474,20 @@ def batched_c3(dev, args):
     batch.set_schedule("queue")        # the FP32 default: one persistent launch over all tiles
     ms_graph = time_graph()
 
+    # the batched form in FP64 (class launches, graph replays): batching alone, same precision
+    batch64 = api.Batch(dev_inst, prec="fp64")
+    batch64.capture()
+    for _ in range(2):
+        batch64.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        batch64.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph64 = e0.elapsed_time(e1) / reps
+    batch64.close()
+
     outs = [torch.empty_like(S) for S in batch.S]
 
     def loop64():
@@ -498,6 +512,8 @@ def batched_c3(dev, args):
         "ms_fp32_graph": round(ms_graph, 4),
         "schedule": "queue (one persistent launch, LPT work items)",
         "ms_fp32_graph_class_launches": round(ms_classes, 4),
+        "ms_fp64_graph_batched": round(ms_graph64, 4),
+        "speedup_fp64_batched_over_fp64_loop": round(ms_loop / ms_graph64, 2),
         "ms_fp64_loop": round(ms_loop, 4),
         "tflops_fp32_graph": round(flops / (ms_graph * 1e-3) / 1e12, 3),
         "rel_err_fp32_vs_fp64": float(f"{rel:.3e}"),
