@@ -126,10 +126,12 @@ def test_queue_schedule_rejected_for_fp64():
     batch.close()
 
 
-def test_graph_replays_match_eager_run():
+@pytest.mark.parametrize("schedule", ["queue", "classes"])
+def test_graph_replays_match_eager_run(schedule):
     inputs = _c3_inputs(512)[:96]
     dev_inst = _device_instances(inputs)
     batch = api.Batch(dev_inst, prec="fp32")
+    batch.set_schedule(schedule)
     batch.run()
     torch.cuda.synchronize()
     eager = [S.clone() for S in batch.S]
