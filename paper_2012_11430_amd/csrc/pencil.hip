@@ -409,14 +409,17 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     if constexpr (SPLIT) {
         constexpr int kVecB = (kSplitPlanes * 16 * NB * 4 + kThreads - 1) / kThreads;
         // Im-multiplier from the Re-multiplier of the neighbouring column (lane col ^ 1):
-        // negated (sign bits of both bfloat16 halves) on even columns
+        // negated (sign bits of both bfloat16 halves) on even columns. Every lane of
+        // the quad permutation has a source, so the update form (old value 0, bound
+        // control on) equals a plain move and lets the XOR take the DPP operand
+        // directly (one v_xor_b32_dpp per dword).
         const unsigned neg = (col & 1) ? 0u : 0x80008000u;
         auto im_of = [neg](const u32x4& x) {
             u32x4 y;
-            y.x = (unsigned)__builtin_amdgcn_mov_dpp((int)x.x, 0xB1, 0xF, 0xF, false) ^ neg;
-            y.y = (unsigned)__builtin_amdgcn_mov_dpp((int)x.y, 0xB1, 0xF, 0xF, false) ^ neg;
-            y.z = (unsigned)__builtin_amdgcn_mov_dpp((int)x.z, 0xB1, 0xF, 0xF, false) ^ neg;
-            y.w = (unsigned)__builtin_amdgcn_mov_dpp((int)x.w, 0xB1, 0xF, 0xF, false) ^ neg;
+            y.x = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x.x, 0xB1, 0xF, 0xF, true) ^ neg;
+            y.y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x.y, 0xB1, 0xF, 0xF, true) ^ neg;
+            y.z = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x.z, 0xB1, 0xF, 0xF, true) ^ neg;
+            y.w = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x.w, 0xB1, 0xF, 0xF, true) ^ neg;
             return y;
         };
         const int nkb = P.kc / kSplitK;
