@@ -209,13 +209,16 @@ def main():
     value = F / (ms_step * 1e-3) / 1e12
     achieved = tile_flops(d, N, m) / (tiles_avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.prec]
+    # HBM bytes per launch from the stored counters of the same code, workload,
+    # precision and split target (the partial rows written depend on the plan)
     traffic = None
+    target = autotune.registered(dev, d, n, m, args.prec, False) or 4 * torch.cuda.get_device_properties(dev).multi_processor_count
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
         if rec.get("source_digest") == source_digest() and rec.get("workload") == args.workload \
                 and rec.get("prec") == args.prec:
-            traffic = rec.get("hbm_bytes_per_launch")
+            traffic = rec.get("by_target", {}).get(str(target), {}).get("hbm_bytes_per_launch")
 
     result = {
         "metric": METRIC,
@@ -247,6 +250,7 @@ def main():
             "avg_launch_ms": round(tiles_avg_ms, 5),
             "launches_timed": launches,
             "flops_per_launch": tile_flops(d, N, m),
+            "split_target_wgs": target,
         },
         "s_build": sbuild,
         "build_T": build_T,
