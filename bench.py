@@ -129,7 +129,7 @@ def main():
     tuned = {}
     if not args.no_tune:
         for prec in ("fp32", "fp64", "bf16x3"):
-            times = autotune.tune_single(dev, d, n, m, prec, reps=5)
+            times = autotune.tune_single(dev, d, n, m, prec, reps=20)
             tuned[prec] = min(times, key=times.get)
     else:
         tuned["cache_entries_loaded"] = autotune.load_cache(dev)
@@ -381,11 +381,14 @@ def noise_sweep_c2(dev, args):
     import numpy as np
     import torch
 
-    from paper_2012_11430_amd import api, host
+    from paper_2012_11430_amd import api, autotune, host
     from workload import config_instances, random_orthonormal
 
     inst = config_instances("c2", count=1)[0]
     d, n, m, N = inst.d, inst.n, inst.m, inst.N
+    if not args.no_tune:
+        for prec in ("fp64", "fp32", "bf16x3"):
+            autotune.tune_single(dev, d, n, m, prec, reps=10)
     rng = np.random.Generator(np.random.PCG64(2020))
     blocks = (random_orthonormal(rng, N, 2 * m), random_orthonormal(rng, N, 2 * m))
     t_d = torch.from_numpy(inst.t).to(dev)

@@ -22,7 +22,7 @@ import torch
 from . import _lib, api
 
 CACHE_ENV = "PRONY_TUNE_CACHE"
-SINGLE_CANDIDATES = (1, 2, 4, 8)          # x compute units
+SINGLE_CANDIDATES = (1, 2, 3, 4, 8)       # x compute units
 BATCH_CANDIDATES = (1, 2, 4)              # chunks of the h' range per instance
 
 

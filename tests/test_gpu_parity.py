@@ -144,7 +144,7 @@ def test_build_S_c1_full_size(prec):
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
 def test_build_S_c1_every_tuner_target(prec):
     # the launch configurations bench.py may time: every split target the autotuner
-    # chooses from (1, 2, 4, 8 x CUs), registered explicitly, then removed
+    # chooses from (its candidate multiples of the CU count), registered explicitly, then removed
     from paper_2012_11430_amd import autotune
     inst, grid, U, s, V = _problem("c1")
     ref = O.pencil_matrices(grid, inst.d, inst.n, U, s, V)
