@@ -490,12 +490,32 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                 }
             }
             const u32x4* bb = bst + (kTwo ? (kb & 1) * bunits : 0);
+            // With 4 or more column blocks the B planes of block cb + 1 are read before
+            // the MFMAs of block cb (measured 3-6 % faster on 8 and 12 blocks, neutral
+            // on 5, 1 % slower on 2).
+            constexpr bool kPrefetchB = NB >= 4;
+            u32x4 xb[kSplitPlanes], xn[kSplitPlanes];
+            if constexpr (kPrefetchB) {
+#pragma unroll
+                for (int pl = 0; pl < kSplitPlanes; ++pl) xb[pl] = bb[((pl * P.nrp + col) << 2) | (g ^ swz)];
+            }
 #pragma unroll
             for (int cb = 0; cb < NB; ++cb) {
+                if constexpr (kPrefetchB) {
+                    if (cb + 1 < NB) {
+#pragma unroll
+                        for (int pl = 0; pl < kSplitPlanes; ++pl)
+                            xn[pl] = bb[((pl * P.nrp + 16 * (cb + 1) + col) << 2) | (g ^ swz)];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                } else {
+#pragma unroll
+                    for (int pl = 0; pl < kSplitPlanes; ++pl) xb[pl] = bb[((pl * P.nrp + 16 * cb + col) << 2) | (g ^ swz)];
+                }
                 bf16x8 b[2 * kSplitPlanes];
 #pragma unroll
                 for (int pl = 0; pl < kSplitPlanes; ++pl) {
-                    const u32x4 x = bb[((pl * P.nrp + 16 * cb + col) << 2) | (g ^ swz)];
+                    const u32x4 x = xb[pl];
                     b[pl] = __builtin_bit_cast(bf16x8, x);
                     b[kSplitPlanes + pl] = __builtin_bit_cast(bf16x8, im_of(x));
                 }
@@ -516,6 +536,10 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                     c = mfma(ai[f][0], b[4], c);
                     c = mfma(ai[f][0], b[3], c);
                     acc[f][cb] = c;
+                }
+                if constexpr (kPrefetchB) {
+#pragma unroll
+                    for (int pl = 0; pl < kSplitPlanes; ++pl) xb[pl] = xn[pl];
                 }
             }
             // with two buffers the other one was last read before the previous barrier;
