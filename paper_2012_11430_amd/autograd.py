@@ -24,13 +24,14 @@ class PronyS(torch.autograd.Function):
         S = api.build_S(f.detach().contiguous(), d, n, U, sigma, V, prec=prec_forward)
         ctx.save_for_backward(U, sigma, V)
         ctx.d, ctx.n, ctx.prec_backward = d, n, prec_backward
+        ctx.f_shape = f.shape
         return S
 
     @staticmethod
     def backward(ctx, gS):
         U, sigma, V = ctx.saved_tensors
         gf = api.build_S_adjoint(gS.contiguous(), ctx.d, ctx.n, U, sigma, V, prec=ctx.prec_backward)
-        return gf, None, None, None, None, None, None, None
+        return gf.view(ctx.f_shape), None, None, None, None, None, None, None
 
 
 def pencil(f, d: int, n: int, U, sigma, V, prec_forward: str = "fp32", prec_backward: str = "fp32"):

@@ -4,7 +4,9 @@ HIP-graph replay, against the CPU oracle.
 Inputs per instance: the c3 workload (d ~ U{1,2,3}, N in [64, 4096], m in [2, 32],
 noise 1e-7); U, Sigma, V are the exact reduced SVD of the noise-free T obtained
 from the QR factorisation of its Vandermonde factor (T = V_z diag(c) V_z^*).
-Tolerances as in test_gpu_parity: normwise relative 1e-12 (FP64), 1e-5 (FP32).
+Tolerances as in test_gpu_parity: 1e-12 (FP64), 1e-5 (FP32), normwise and entry by
+entry. The full batch is also compared under every per-instance chunk count the
+autotuner can register (the configurations the benchmark may time).
 """
 import functools
 import sys
@@ -15,6 +17,7 @@ import torch
 
 from oracle import prony_oracle as O
 from paper_2012_11430_amd import api
+from tests._close import assert_close, assert_close_per_matrix
 from workload import config_instances
 
 pytestmark = pytest.mark.gpu
@@ -56,10 +59,6 @@ def _device_instances(inputs):
     return [(inst.d, inst.n, _dev(grid), _dev(U), _dev(s), _dev(V)) for inst, grid, U, s, V in inputs]
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batched_matches_oracle_on_sampled_c3_instances(prec):
     inputs = _c3_inputs(512)
@@ -72,9 +71,8 @@ def test_batched_matches_oracle_on_sampled_c3_instances(prec):
     for (inst, grid, U, s, V), S in zip(picked, batch.S):
         ref = O.pencil_matrices(grid, inst.d, inst.n, U, s, V)
         got = S.cpu().numpy()
-        err = max(_rel(got[l], ref[l]) for l in range(inst.d))
-        worst = max(worst, err)
-        assert err <= TOL[prec], (inst.d, inst.n, inst.m, err)
+        norm, entry = assert_close_per_matrix(got, ref, TOL[prec], f"d={inst.d} n={inst.n} m={inst.m}")
+        worst = max(worst, norm, entry)
     batch.close()
     _say(f"  worst rel err {worst:.3e}")
 
@@ -88,10 +86,41 @@ def test_full_c3_batch_matches_single_instance_calls():
         batch = api.Batch(dev_inst, prec=prec)
         batch.run()
         torch.cuda.synchronize()
-        errs = [_rel(b.cpu().numpy(), a.cpu().numpy()) for a, b in zip(singles, batch.S)]
-        _say(f"  {prec}: max rel diff to single FP64 calls {max(errs):.3e}")
-        assert max(errs) <= TOL[prec]
+        worst = 0.0
+        for i, (a, b) in enumerate(zip(singles, batch.S)):
+            worst = max(worst, *assert_close_per_matrix(b.cpu().numpy(), a.cpu().numpy(), TOL[prec],
+                                                        f"{prec} instance {i}"))
+        _say(f"  {prec}: max rel diff to single FP64 calls {worst:.3e}")
         batch.close()
+
+
+@pytest.mark.parametrize("chunks", [1, 2, 4])
+def test_full_c3_batch_at_every_tuned_chunk_count(chunks):
+    # the FP32 batch the benchmark replays (queue schedule), with each chunk count
+    # the autotuner chooses from registered for every shape, against single FP64
+    # calls (which are themselves pinned to the oracle above)
+    from paper_2012_11430_amd import autotune
+    assert chunks in autotune.BATCH_CANDIDATES
+    inputs = _c3_inputs(512)
+    dev_inst = _device_instances(inputs)
+    shapes = sorted({(inst.d, inst.n, inst.m) for inst, *_r in inputs})
+    _say(f"full c3 batch, {chunks} chunk(s) per instance")
+    singles = [api.build_S(f, d, n, U, s, V, prec="fp64") for d, n, f, U, s, V in dev_inst]
+    try:
+        for d, n, m in shapes:
+            autotune.register(DEV, d, n, m, "fp32", True, chunks)
+        batch = api.Batch(dev_inst, prec="fp32")
+        batch.run()
+        torch.cuda.synchronize()
+        worst = 0.0
+        for i, (a, b) in enumerate(zip(singles, batch.S)):
+            worst = max(worst, *assert_close_per_matrix(b.cpu().numpy(), a.cpu().numpy(), TOL["fp32"],
+                                                        f"chunks {chunks} instance {i}"))
+        batch.close()
+        _say(f"  worst {worst:.3e}")
+    finally:
+        for d, n, m in shapes:
+            autotune.register(DEV, d, n, m, "fp32", True, 0)
 
 
 def test_queue_schedule_is_bitwise_equal_to_class_launches():
@@ -162,6 +191,5 @@ def test_graph_replay_sees_new_sample_values():
     torch.cuda.synchronize()
     for (inst, grid, U, s, V), S in zip(inputs, batch.S):
         ref = O.pencil_matrices(2.0 * grid, inst.d, inst.n, U, s, V)
-        got = S.cpu().numpy()
-        assert max(_rel(got[l], ref[l]) for l in range(inst.d)) <= 1e-12
+        assert_close_per_matrix(S.cpu().numpy(), ref, 1e-12, "replay after f *= 2")
     batch.close()
