@@ -208,61 +208,67 @@ def lanczos_bidiagonalization(A: np.ndarray, p1: np.ndarray, tol: float, restart
     return U @ UB, s, V[:, :ncol] @ VBh.conj().T, rank
 
 
+def pivoted_rank_cut(W: np.ndarray, tol: float):
+    """Numerical rank of W from a QR factorisation with column pivoting (Sec. 2.2):
+    W Pi = Q R, and the rank is the first i whose trailing block R(i:, i:) has
+    Frobenius norm at most tol ||R||_F (all columns when there is none).
+    Returns (Q, R Pi^T, rank), so that W = Q (R Pi^T) exactly."""
+    Q, R, perm = scipy.linalg.qr(W, mode="economic", pivoting=True)
+    Pi = np.eye(W.shape[1])[:, perm]
+    total = np.linalg.norm(R)
+    rank = R.shape[0]
+    for i in range(R.shape[0]):
+        if np.linalg.norm(R[i:, i:]) <= tol * total:
+            rank = i
+            break
+    return Q, R @ Pi.T, rank
+
+
 def block_power_svd(A: np.ndarray, U0: np.ndarray, V0: np.ndarray, tol: float,
                     rank: int | None = None, max_sweeps: int = 60):
-    """Block power method for the SVD with rank determination (Sec. 2.2, Algorithm 3).
+    """Block power method for the SVD with rank determination (Sec. 2.2, Algorithm 3),
+    written as a subspace iteration.
+
+    The iteration keeps orthonormal bases U (left) and V (right) and their coupling
+    C = U^* A V; the pair is converged when the residual A V - U C has Frobenius norm
+    at most tol ||A||_F. One sweep maps the right basis to the left one,
+    U = orth(A V), and back: A^* U = V C^* is a QR factorisation of A^* U, with
+    column pivoting in the first sweep, whose rank cut (pivoted_rank_cut) fixes the
+    number of right vectors kept. The singular triplets are those of C in the two
+    bases.
 
     U0, V0: starting blocks with r0 columns (orthonormalised here).
-    tol:    stopping tolerance for ||R_k||_F <= tol ||A||_F and the rank cut of
-            the pivoted QR, ||R_V(i:, i:)||_F <= tol ||R_V||_F.
-    rank:   if given, the rank used after the first sweep (the detected rank is
-            still returned as a diagnostic).
+    rank:   if given, the number of right vectors kept after the first sweep (the
+            detected rank is still returned as a diagnostic).
 
-    Reading: the pivoted-QR identity A^* U_k = V_k R_V P^T determines
-    Q_k^* = (R_V P^T)(1:r_k, :), i.e. all columns of U_k are kept and Q_k is
-    r_{k-1} x r_k in the sweep that cuts the rank.
+    Reading: A^* U = Q (R Pi^T) with Q cut to its first r columns keeps all r0
+    columns of U, so C^* = (R Pi^T)(1:r, :) and C is r0 x r in the sweep that cuts
+    the rank.
     Returns (U, sigma, V, detected_rank, sweeps).
     """
     U = _orthonormal_columns(U0)
     V = _orthonormal_columns(V0)
-    normA = np.linalg.norm(A)
-    Q = U.conj().T @ A @ V
-    R = A @ V - U @ Q
+    norm_A = np.linalg.norm(A)
+    C = U.conj().T @ A @ V
     sweeps = 0
     detected = None
-    while np.linalg.norm(R) > tol * normA:
-        if sweeps >= max_sweeps:
-            break
-        sweeps += 1
-        Ubar = A @ V
-        U, _ = np.linalg.qr(Ubar)
-        Vbar = A.conj().T @ U
-        if sweeps == 1:
-            Vq, RV, piv = scipy.linalg.qr(Vbar, mode="economic", pivoting=True)
-            normRV = np.linalg.norm(RV)
-            r = RV.shape[1]
-            for i in range(RV.shape[1]):
-                if np.linalg.norm(RV[i:, i:]) <= tol * normRV:
-                    r = i
-                    break
-            detected = r
-            if rank is not None:
-                r = rank
-            P = np.eye(RV.shape[1])[:, piv]
-            V = Vq[:, :r]
-            Qstar = (RV @ P.T)[:r, :]
-            Q = Qstar.conj().T
+    while np.linalg.norm(A @ V - U @ C) > tol * norm_A and sweeps < max_sweeps:
+        U = _orthonormal_columns(A @ V)
+        W = A.conj().T @ U                  # = V C^* for the next right basis V
+        if detected is None:
+            Q, RPt, detected = pivoted_rank_cut(W, tol)
+            kept = detected if rank is None else rank
+            V = Q[:, :kept]
+            C = RPt[:kept, :].conj().T
         else:
-            V, RV = np.linalg.qr(Vbar)
-            Q = RV.conj().T
-        R = A @ V - U @ Q
+            V, RW = np.linalg.qr(W)
+            C = RW.conj().T
+        sweeps += 1
     if detected is None:
         detected = V.shape[1]
-    UQ, s, VQh = np.linalg.svd(Q, full_matrices=False)
+    UC, s, VCh = np.linalg.svd(C, full_matrices=False)
     r = V.shape[1] if rank is None else rank
-    Uo = (U @ UQ)[:, :r]
-    Vo = (V @ VQh.conj().T)[:, :r]
-    return Uo, s[:r], Vo, detected, sweeps
+    return (U @ UC)[:, :r], s[:r], (V @ VCh.conj().T)[:, :r], detected, sweeps
 
 
 # ---------------------------------------------------------------------------

@@ -72,38 +72,57 @@ class GpuToeplitz:
         return float(np.sqrt(np.sum(np.abs(g) ** 2 * w)))
 
 
+def pivoted_rank_basis(W: np.ndarray, tol: float, rank: int | None = None):
+    """Rank-revealing orthonormal basis of the column space of W (QR with column
+    pivoting, W P = Q R). The numerical rank is the first i at which the trailing
+    rows R[i:, :] (upper triangular, so the block R[i:, i:]) have Frobenius norm
+    at most tol ||R||_F — the rank test of Sec. 2.2; `rank` overrides it.
+    Returns (Q[:, :r], Q[:, :r]^* W, detected rank)."""
+    Q, R, perm = scipy.linalg.qr(W, mode="economic", pivoting=True)
+    tail = np.sqrt(np.cumsum((np.abs(R) ** 2).sum(axis=1)[::-1])[::-1])
+    small = np.nonzero(tail <= tol * np.linalg.norm(R))[0]
+    detected = int(small[0]) if small.size else R.shape[0]
+    r = detected if rank is None else rank
+    coords = np.empty_like(R)
+    coords[:, perm] = R                        # R P^T: the coordinates of W's columns
+    return Q[:, :r], coords[:r], detected
+
+
 def power_svd(T, start_u: np.ndarray, start_v: np.ndarray, tol: float, rank: int | None = None,
-              max_sweeps: int = 60):
-    """Block power SVD with pivoted-QR rank determination in the first sweep
-    (Sec. 2.2, Algorithm 3). T is a matrix or an operator with matmul, rmatmul and
-    fro_norm (GpuToeplitz). Returns (U, sigma, V, detected_rank, sweeps)."""
+              max_sweeps: int = 60, info: dict | None = None):
+    """Dominant singular triplets of T by block power (subspace) iteration with the
+    rank determination of Sec. 2.2 (Algorithm 3).
+
+    Orthonormal bases U (left) and V (right) and their coupling B = U^* T V are kept;
+    they are accurate when ||T V - U B||_F <= tol ||T||_F. A sweep maps the right
+    basis to the left, U = orth(T V), and back: T^* U = V B^* gives the next V and B
+    by QR — in the first sweep a pivoted QR whose rank cut (pivoted_rank_basis)
+    fixes how many right vectors are kept. The SVD of B yields the triplets.
+    T is a matrix or an operator with matmul, rmatmul and fro_norm (GpuToeplitz).
+    Returns (U, sigma, V, detected_rank, sweeps); `info`, if given, receives the
+    singular values of T^* U in the first sweep ("first_sweep_sigma": estimates of
+    sigma_1..sigma_r0, used for sigma_m / sigma_{m+1} when only m are kept)."""
     op = DenseToeplitz(T) if isinstance(T, np.ndarray) else T
-    Uk, Vk = _orth(start_u), _orth(start_v)
-    norm_t = op.fro_norm()
-    TV = op.matmul(Vk)
-    Qk = Uk.conj().T @ TV
-    sweeps, detected = 0, Vk.shape[1]
-    while np.linalg.norm(TV - Uk @ Qk) > tol * norm_t and sweeps < max_sweeps:
-        sweeps += 1
-        Uk = _orth(op.matmul(Vk))
-        W = op.rmatmul(Uk)
-        if sweeps == 1:
-            Qv, Rv, perm = scipy.linalg.qr(W, mode="economic", pivoting=True)
-            tail = np.sqrt(np.cumsum((np.abs(Rv) ** 2).sum(axis=1)[::-1])[::-1])
-            cut = np.nonzero(tail <= tol * np.linalg.norm(Rv))[0]
-            detected = int(cut[0]) if cut.size else Rv.shape[0]
-            r = detected if rank is None else rank
-            inv = np.empty_like(perm)
-            inv[perm] = np.arange(perm.size)
-            Vk = Qv[:, :r]
-            Qk = Rv[:r, inv].conj().T
+    U, V = _orth(start_u), _orth(start_v)
+    threshold = tol * op.fro_norm()
+    TV = op.matmul(V)
+    B = U.conj().T @ TV
+    sweeps, detected = 0, V.shape[1]
+    while np.linalg.norm(TV - U @ B) > threshold and sweeps < max_sweeps:
+        U = _orth(TV)
+        TtU = op.rmatmul(U)
+        if sweeps == 0:
+            if info is not None:
+                info["first_sweep_sigma"] = np.linalg.svd(TtU, compute_uv=False)
+            V, Bh, detected = pivoted_rank_basis(TtU, tol, rank)
         else:
-            Vk, Rv = np.linalg.qr(W)
-            Qk = Rv.conj().T
-        TV = op.matmul(Vk)
-    Uq, s, Vqh = np.linalg.svd(Qk, full_matrices=False)
-    r = Vk.shape[1] if rank is None else rank
-    return (Uk @ Uq)[:, :r], s[:r], (Vk @ Vqh.conj().T)[:, :r], detected, sweeps
+            V, Bh = np.linalg.qr(TtU)
+        B = Bh.conj().T
+        sweeps += 1
+        TV = op.matmul(V)
+    Ub, sigma, Vbh = np.linalg.svd(B, full_matrices=False)
+    r = V.shape[1] if rank is None else rank
+    return (U @ Ub)[:, :r], sigma[:r], (V @ Vbh.conj().T)[:, :r], detected, sweeps
 
 
 def _project_out(x: np.ndarray, Q: list) -> np.ndarray:
@@ -205,6 +224,30 @@ def solve_normal_equations(gram: np.ndarray, rhs: np.ndarray) -> np.ndarray:
         return np.linalg.solve(gram, rhs)
 
 
+def numerical_rank(sigma: np.ndarray, tol: float) -> int:
+    """Number of singular values at or above tol * sigma_1 (the first i with
+    sigma_i < tol sigma_1 ends the rank; Sec. 5)."""
+    sigma = np.asarray(sigma)
+    below = np.nonzero(sigma < tol * sigma[0])[0]
+    return int(below[0]) if below.size else int(sigma.size)
+
+
+def start_blocks_for(N: int, r0: int, seed: int = 0):
+    """Two random N x r0 complex Gaussian starting blocks of the block power method
+    (Algorithm 3 starts from random bases), from a seeded generator."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    def draw():
+        return (rng.standard_normal((N, r0)) + 1j * rng.standard_normal((N, r0))) / np.sqrt(2.0)
+    return draw(), draw()
+
+
+def samples_on_index_set(f: np.ndarray, d: int, n: int) -> np.ndarray:
+    """f restricted to I_n = {0..n}^d, row-major (the right-hand side of eq. ls_probl):
+    grid point p sits at offset p + n along every axis."""
+    side = 2 * n + 2
+    return np.asarray(f).reshape((side,) * d)[(slice(n, 2 * n + 1),) * d].reshape(-1)
+
+
 @dataclasses.dataclass
 class Solution:
     t: np.ndarray
@@ -214,42 +257,82 @@ class Solution:
     sigma: np.ndarray
     U: np.ndarray
     V: np.ndarray
+    m: int                    # number of terms used (given, or the detected rank)
+    rank: int                 # numerical rank found by the SVD step at tolerance tol
+    residual: float           # ||A^T c - f_I|| / ||f_I||: the operational accuracy estimate (Sec. 5)
+    sigma_ratio: float | None  # sigma_m / sigma_{m+1} (None when sigma_{m+1} is not known)
 
 
-def solve(f: torch.Tensor, d: int, n: int, m: int, mu: np.ndarray, prec: str = "fp64",
-          start_blocks=None, svd: str = "dense") -> Solution:
+def solve(f: torch.Tensor, d: int, n: int, m: int | None, mu: np.ndarray, prec: str = "fp64",
+          start_blocks=None, svd: str = "dense", tol: float | None = None, seed: int = 0,
+          r0: int | None = None) -> Solution:
     """Algorithm 1 on one GPU plus the host: reduced SVD of T -> S_l (GPU) -> nodes
-    (host) -> Vandermonde products (GPU) -> coefficients (host).
+    (host) -> Vandermonde products (GPU) -> coefficients (host) -> relative LS residual.
+
+    m: number of terms, or None to use the numerical rank the SVD step detects at
+    tolerance tol (default N eps, the criterion of Sec. 5; raise it to the noise
+    level for noisy samples). The relative residual ||A^T c - f_I|| / ||f_I|| tells
+    whether the rank was well determined: a rank below the true number of terms
+    leaves a residual far above the noise level (Sec. 5, discussion of Table 1).
 
     svd="dense": T formed on the GPU and decomposed on the host (LAPACK for
-    N <= 1024, else Algorithm 3 on the dense T); svd="gpu": Algorithm 3 with the
-    block products on the GPU (start_blocks required), T never formed;
-    svd="lanczos": Algorithm 2 with GPU products (start_blocks = (p1, restart
-    vectors)), T never formed."""
+    N <= 1024 or without start blocks, else Algorithm 3 on the dense T); svd="gpu":
+    Algorithm 3 with the block products on the GPU, T never formed (start_blocks, or
+    seeded random blocks of r0 = 2m columns, 64 when m is None); svd="lanczos":
+    Algorithm 2 with GPU products, T never formed (start_blocks = (p1, restart
+    vectors), or seeded random ones)."""
     dev = f.device
+    N = (n + 1) ** d
+    tol = N * np.finfo(float).eps if tol is None else tol
+    ratio = None
     if svd == "gpu":
         if start_blocks is None:
-            raise ValueError("svd='gpu' needs start_blocks (two N x r blocks)")
-        N = (n + 1) ** d
-        U, s, V, _, _ = power_svd(GpuToeplitz(f, d, n), start_blocks[0], start_blocks[1],
-                                  N * np.finfo(float).eps, rank=m)
+            start_blocks = start_blocks_for(N, min(N, r0 or (2 * m if m else 64)), seed)
+        info = {}
+        U, s, V, rank, _ = power_svd(GpuToeplitz(f, d, n), start_blocks[0], start_blocks[1], tol, rank=m,
+                                     info=info)
+        m = rank if m is None else m
+        est = info.get("first_sweep_sigma")
+        if est is not None and est.size > m:
+            ratio = float(s[m - 1] / est[m]) if est[m] > 0 else float("inf")
     elif svd == "lanczos":
         if start_blocks is None:
-            raise ValueError("svd='lanczos' needs start_blocks = (p1, restart vectors)")
-        N = (n + 1) ** d
-        U, s, V, _ = lanczos_svd(GpuToeplitz(f, d, n), start_blocks[0], N * np.finfo(float).eps, start_blocks[1])
+            rng = np.random.Generator(np.random.PCG64(seed))
+            draw = lambda: rng.standard_normal(N) + 1j * rng.standard_normal(N)   # noqa: E731
+            start_blocks = (draw(), [draw() for _ in range(8)])
+        U, s, V, rank = lanczos_svd(GpuToeplitz(f, d, n), start_blocks[0], tol, start_blocks[1])
+        m = rank if m is None else m
+        if s.size > m:
+            ratio = float(s[m - 1] / s[m]) if s[m] > 0 else float("inf")
         U, s, V = U[:, :m], s[:m], V[:, :m]
     elif svd == "dense":
         T = api.build_T(f, d, n, 0).cpu().numpy()
-        U, s, V, _ = reduced_svd(T, m, start_blocks)
+        if N <= 1024 or start_blocks is None:
+            Uf, s_all, Vh = np.linalg.svd(T)
+            rank = numerical_rank(s_all, tol)
+            m = rank if m is None else m
+            U, s, V = Uf[:, :m], s_all[:m], Vh[:m].conj().T
+            if s_all.size > m:
+                ratio = float(s_all[m - 1] / s_all[m]) if s_all[m] > 0 else float("inf")
+        else:
+            info = {}
+            U, s, V, rank, _ = power_svd(T, start_blocks[0], start_blocks[1], tol, rank=m, info=info)
+            m = rank if m is None else m
+            est = info.get("first_sweep_sigma")
+            if est is not None and est.size > m:
+                ratio = float(s[m - 1] / est[m]) if est[m] > 0 else float("inf")
         del T
     else:
         raise ValueError("svd must be 'dense', 'gpu' or 'lanczos'")
+    if m < 1:
+        raise ValueError("the SVD step found no nonzero singular value above the tolerance")
     Ud = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
     Vd = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
     sd = torch.from_numpy(np.ascontiguousarray(s)).to(dev)
     S = api.build_S(f, d, n, Ud, sd, Vd, prec=prec).cpu().numpy()
     z, t = nodes(S, mu)
-    gram, rhs = api.coeffs(torch.from_numpy(np.ascontiguousarray(z)).to(dev), f, d, n)
+    gram, rhs, AT = api.coeffs(torch.from_numpy(np.ascontiguousarray(z)).to(dev), f, d, n, want_AT=True)
     c = solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy())
-    return Solution(t=t, c=c, z=z, S=S, sigma=s, U=U, V=V)
+    fI = samples_on_index_set(f.cpu().numpy(), d, n)
+    residual = float(np.linalg.norm(AT.cpu().numpy() @ c - fI) / np.linalg.norm(fI))
+    return Solution(t=t, c=c, z=z, S=S, sigma=s, U=U, V=V, m=m, rank=rank, residual=residual, sigma_ratio=ratio)

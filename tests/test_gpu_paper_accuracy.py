@@ -96,3 +96,41 @@ def test_rank_detection_with_gpu_lanczos(golden_dir):
         _, _, _, rank = host.lanczos_svd(host.GpuToeplitz(f, d, n), p1, N * O.EPS64, restarts)
         print(f"lanczos rank d={d} n={n} m={m}: detected {rank} ({rel})", flush=True)
         assert (rank == m) if rel == "eq" else (rank < m)
+
+
+def test_residual_flags_a_wrongly_determined_rank():
+    # Sec. 5, after Table 1: at eps = 1e-3 the rank test with tol = eps finds rank 4
+    # (sigma_5 / sigma_1 ~ 9e-4) and the errors are large; tol = 1e-4 finds rank 5.
+    # The relative LS residual, which needs no knowledge of the true parameters,
+    # reveals the difference (the operational accuracy estimate).
+    d, n, m, eps = 3, 20, 5, 1e-3
+    N = (n + 1) ** d
+    t_true, c_true = paper_efficiency_inputs(d, m)
+    grid = O.samples(t_true, c_true, n) * (1.0 + paper_relative_noise(1, d, n, eps))
+    f = _dev(grid)
+    mu = MU / np.linalg.norm(MU)
+    blocks = host.start_blocks_for(N, 2 * m, seed=7)
+    sols = {tol: host.solve(f, d, n, None, mu, svd="gpu", tol=tol, start_blocks=blocks) for tol in (1e-3, 1e-4)}
+    for tol, sol in sols.items():
+        dt, dc = O.recovery_errors(dict(t=sol.t, c=sol.c), t_true, c_true) if sol.m == m else (None, None)
+        print(f"eps=1e-3 tol={tol:g}: rank {sol.rank}, residual {sol.residual:.3e}, "
+              f"sigma_m/sigma_m+1 {sol.sigma_ratio}, dt {dt}, dc {dc}", flush=True)
+    wrong, right = sols[1e-3], sols[1e-4]
+    assert wrong.rank == 4 and wrong.m == 4
+    assert right.rank == 5 and right.m == 5
+    # right rank: residual at the noise level (Table 1: 3.0e-4); wrong rank: far above it
+    assert 3e-5 < right.residual < 3e-3
+    assert wrong.residual > 10 * right.residual
+    # the kept singular values are well separated from the next one when the rank is right
+    assert right.sigma_ratio is not None and right.sigma_ratio > 10
+
+
+def test_solve_with_default_start_blocks_and_fixed_m():
+    # host.solve(svd="gpu") draws its own seeded start blocks when none are given
+    d, n, m = 3, 20, 5
+    t_true, c_true = paper_efficiency_inputs(d, m)
+    f = _dev(O.samples(t_true, c_true, n))
+    sol = host.solve(f, d, n, m, MU, svd="gpu")
+    dt, dc = O.recovery_errors(dict(t=sol.t, c=sol.c), t_true, c_true)
+    assert sol.m == m and sol.rank == m
+    assert dt < 1e-10 and dc < 1e-8 and sol.residual < 1e-10
