@@ -9,11 +9,19 @@ of one problem (default workload c1: d=2, n=63, N=4096, m=20, noise 1e-6):
 The host steps (SVD, eigendecomposition, m x m solve) run once, untimed, to
 produce the inputs U, Sigma, V and z of the timed GPU steps.
 
-value = S-build flops F_S = d (8 N^2 m + 8 N m^2 + 2 m^2) divided by the time
-of one whole step, in TFLOP/s. The JSON line also carries the S-build alone in
-FP32 and FP64, the roofline of the dominant kernel (measured with HIP events
-around its launches in the timed region) and the CPU oracle on a bounded
-sample of the same workload.
+value = S-build flops F_S = d (8 N^2 m + 8 N m^2 + 2 m^2) (the paper's dense
+work, a complex multiply-add counted as 8) divided by the time of one whole
+step, in TFLOP/s; the timed step computes S in FP64 (the paper's arithmetic)
+unless --prec says otherwise. The JSON line also carries the S-build alone in
+FP64, FP32-MFMA and split bfloat16, the roofline of the dominant kernel of each
+precision (its own MFMA work per launch over its launch time, measured with HIP
+events around its launches), and the CPU oracle on a bounded sample of the same
+workload.
+
+Own work of the tile kernel (row-extended form): the product T_row V over the
+(n+2)^d rows k' and N columns h, 8 (n+2)^d N m flops, plus the reductions with the
+shifted U_l, 8 ells (n+2)^d m^2 flops (ells = d matrices). It is below F_S by about
+the factor d: F_S counts the d products T_l V that the row-extended form shares.
 """
 from __future__ import annotations
 
@@ -40,9 +48,12 @@ def s_flops(d, N, m):
     return d * (8.0 * N * N * m + 8.0 * N * m * m + 2.0 * m * m)
 
 
-def tile_flops(d, N, m):
-    # algorithmic work of one pencil_tiles launch: T_l V and the U^* reduction
-    return d * (8.0 * N * N * m + 8.0 * N * m * m)
+def tile_flops(d, n, m, ells=None):
+    """Own work of one pencil_tiles launch: Z = T_row V on the (n+2)^d row-extended
+    rows, and the ells reductions U_l^* Z (ells = d without S_0)."""
+    ells = d if ells is None else ells
+    NR, N = (n + 2) ** d, (n + 1) ** d
+    return 8.0 * NR * N * m + 8.0 * ells * NR * m * m
 
 
 def source_digest():
@@ -63,8 +74,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", choices=["fp32", "fp64", "bf16x3"], default="fp32",
-                    help="S-build precision of the timed step (bf16x3: split bfloat16 on the bf16 MFMA)")
+    ap.add_argument("--prec", choices=["fp32", "fp64", "bf16x3"], default="fp64",
+                    help="S-build precision of the timed step (fp64: the paper's arithmetic; fp32: FP32 MFMA; "
+                         "bf16x3: split bfloat16 on the bf16 MFMA)")
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2"])
     ap.add_argument("--cpu-sample-steps", type=int, default=16,
                     help="oracle steps timed for the CPU baseline (0 skips it)")
@@ -181,8 +193,9 @@ def main():
         api.profile_enable(dev, None)
         med = float(np.median(times))
         sbuild[prec] = {"ms_median": round(med, 5), "ms_mean": round(float(np.mean(times)), 5),
-                        "tflops": round(s_flops(d, N, m) / (med * 1e-3) / 1e12, 3),
-                        "tiles_ms": round(tot / max(1, nl), 5), "calls": len(times)}
+                        "fs_equivalent_tflops": round(s_flops(d, N, m) / (med * 1e-3) / 1e12, 3),
+                        "own_work_tflops": round(tile_flops(d, n, m) / (med * 1e-3) / 1e12, 3),
+                        "tiles_ms": round(tot / max(1, nl), 5), "tiles_launches": nl, "calls": len(times)}
         S_out[prec] = Sbuf.cpu().numpy().copy()
 
     # ---------------- T alone (HBM-write-bound): GB/s against the 8 TB/s peak
@@ -201,24 +214,44 @@ def main():
         gram, rhs = api.coeffs(to_dev(z_p), f, d, n)
         recovered[prec] = (t_p, host.solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy()))
     for prec in sbuild:
-        sbuild[prec]["frac_of_mfma_peak"] = round(sbuild[prec]["tflops"] / PEAK_TFLOPS[prec], 4)
+        # the whole call (pack, tiles, finish) on the kernel's own work
+        sbuild[prec]["own_work_frac_of_peak"] = round(sbuild[prec]["own_work_tflops"] / PEAK_TFLOPS[prec], 4)
     sbuild["speedup_fp32_over_fp64"] = round(sbuild["fp64"]["ms_median"] / sbuild["fp32"]["ms_median"], 3)
     sbuild["speedup_bf16x3_over_fp32"] = round(sbuild["fp32"]["ms_median"] / sbuild["bf16x3"]["ms_median"], 3)
 
     F = s_flops(d, N, m)
     value = F / (ms_step * 1e-3) / 1e12
-    achieved = tile_flops(d, N, m) / (tiles_avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.prec]
-    # HBM bytes per launch from the stored counters of the same code, workload,
-    # precision and split target (the partial rows written depend on the plan)
-    traffic = None
-    target = autotune.registered(dev, d, n, m, args.prec, False) or 4 * torch.cuda.get_device_properties(dev).multi_processor_count
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    traffic_rec = {}
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh)
-        if rec.get("source_digest") == source_digest() and rec.get("workload") == args.workload \
-                and rec.get("prec") == args.prec:
-            traffic = rec.get("by_target", {}).get(str(target), {}).get("hbm_bytes_per_launch")
+            traffic_rec = json.load(fh)
+
+    def roofline_of(prec, avg_ms, nlaunch):
+        """Roofline of the tile kernel of one precision: its own MFMA work per launch
+        over its average launch time (HIP events); HBM bytes per launch from the stored
+        counters of the same code, workload, precision and split target (the partial
+        rows written depend on the plan), else null."""
+        target = autotune.registered(dev, d, n, m, prec, False) or 4 * cus
+        traffic = None
+        if traffic_rec.get("source_digest") == source_digest() and traffic_rec.get("workload") == args.workload:
+            traffic = traffic_rec.get("entries", {}).get(prec, {}).get(str(target), {}).get("hbm_bytes_per_launch")
+        achieved = tile_flops(d, n, m) / (avg_ms * 1e-3) / 1e12
+        return {
+            "bound": "mfma",
+            "kernel": "pencil_tiles_split" if prec == "bf16x3" else DOMINANT,
+            "precision": prec,
+            "achieved": round(achieved, 3),
+            "peak": PEAK_TFLOPS[prec],
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS[prec], 4),
+            "traffic": traffic,
+            "avg_launch_ms": round(avg_ms, 5),
+            "launches_timed": nlaunch,
+            "flops_per_launch": tile_flops(d, n, m),
+            "fs_equivalent_tflops": round(F / (avg_ms * 1e-3) / 1e12, 3),
+            "split_target_wgs": target,
+        }
 
     result = {
         "metric": METRIC,
@@ -239,19 +272,9 @@ def main():
             "s_build_precision": args.prec,
             "seed": list(inst.seed),
         },
-        "roofline": {
-            "bound": "mfma",
-            "kernel": DOMINANT,
-            "achieved": round(achieved, 3),
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4),
-            "traffic": traffic,
-            "avg_launch_ms": round(tiles_avg_ms, 5),
-            "launches_timed": launches,
-            "flops_per_launch": tile_flops(d, N, m),
-            "split_target_wgs": target,
-        },
+        "roofline": roofline_of(args.prec, tiles_avg_ms, launches),
+        "rooflines": {p: roofline_of(p, sbuild[p]["tiles_ms"], sbuild[p]["tiles_launches"])
+                      for p in ("fp64", "fp32", "bf16x3")},
         "s_build": sbuild,
         "build_T": build_T,
         "tuned_split_targets": tuned,
@@ -259,7 +282,7 @@ def main():
     }
     if not args.no_extra:
         result["svd_products"] = svd_products(dev, args, f, d, n, m, sig, blocks, per_call_ms)
-        result["noise_sweep_c2"] = noise_sweep_c2(dev, args)
+        result["noise_sweep_c2"] = noise_sweep_c2(dev, args, per_call_ms)
         result["paper_workload"] = paper_workload(dev, args, per_call_ms)
         result["batched"] = batched_c3(dev, args)
         result["adjoint"] = adjoint_c4(dev, args)
@@ -350,12 +373,23 @@ def paper_workload(dev, args, per_call_ms):
         row = {"paper_t_S_s": PAPER_T_S[m], "lanczos_svd_gpu_products": lanczos,
                "paper_gflops": round(s_flops(d, N, m) / PAPER_T_S[m] / 1e9, 1),
                "algorithm1_gpu_path_s": round(wall, 4), "svd_sweeps": sweeps}
+        S_p = {}
         for prec in ("fp64", "fp32", "bf16x3"):
             for _ in range(args.warmup):
                 api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
-            ms = float(np.median(per_call_ms(lambda: api.build_S(f, d, n, Ud, sd, Vd, prec=prec), 10)))
-            row[prec] = {"s_build_ms": round(ms, 4), "tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 2),
+            ms = float(np.median(per_call_ms(lambda: api.build_S(f, d, n, Ud, sd, Vd, prec=prec), 20)))
+            S_p[prec] = api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
+            row[prec] = {"s_build_ms": round(ms, 4),
+                         "fs_equivalent_tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 2),
+                         "own_work_tflops": round(tile_flops(d, n, m) / (ms * 1e-3) / 1e12, 2),
                          "speedup_vs_paper_t_S": round(PAPER_T_S[m] / (ms * 1e-3), 1)}
+        # the S of each precision against the FP64 S on the same factors: the paper's
+        # inputs at m >= 10 have sigma_m / sigma_1 down to ~3e-12, and Sigma^{-1}
+        # amplifies the rounding of FP32 inputs by sigma_1 / sigma_m
+        row["sigma_m_over_sigma_1"] = float(f"{s[-1] / s[0]:.3e}")
+        for p in ("fp32", "bf16x3"):
+            row[p]["s_rel_diff_vs_fp64"] = float(
+                f"{float(torch.linalg.norm(S_p[p] - S_p['fp64']) / torch.linalg.norm(S_p['fp64'])):.3e}")
         out["m"][str(m)] = row
     return out
 
@@ -373,11 +407,12 @@ def _match_errors(t_est, c_est, t_true, c_true):
     return dt, dc
 
 
-def noise_sweep_c2(dev, args):
+def noise_sweep_c2(dev, args, per_call_ms):
     """c2 (d=3, n=19, N=8000, m=30) over its noise levels: the SVD by Algorithm 3
     with GPU block products (T is never formed), S in FP64, FP32-MFMA and split
-    bfloat16, and the recovered t_j, c_j of each against the truth, with the
-    S-build times."""
+    bfloat16, and the recovered t_j, c_j of each against the truth; the S-build
+    of each precision timed as the median of per-call HIP events, with the tile
+    kernel's launch time and its fraction of the MFMA peak on its own work."""
     import numpy as np
     import torch
 
@@ -403,24 +438,34 @@ def noise_sweep_c2(dev, args):
         row = {"noise": level, "svd_sweeps": sweeps}
         S = {}
         for prec in ("fp64", "fp32", "bf16x3"):
-            api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
             S[prec] = api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
-            e1.record()
-            torch.cuda.synchronize()
             z_p, t_p = host.nodes(S[prec].cpu().numpy(), inst.mu)
             gram, rhs = api.coeffs(torch.from_numpy(z_p).to(dev), f, d, n)
             c_p = host.solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy())
             dt, dc = _match_errors(t_p, c_p, inst.t, inst.c)
-            ms = e0.elapsed_time(e1)
-            row[prec] = {"s_build_ms": round(ms, 4), "tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 2),
-                         "max_dt_vs_truth": float(f"{dt:.3e}"), "rel_dc_vs_truth": float(f"{dc:.3e}")}
+            row[prec] = {"max_dt_vs_truth": float(f"{dt:.3e}"), "rel_dc_vs_truth": float(f"{dc:.3e}")}
         for p in ("fp32", "bf16x3"):
             row[f"s_rel_diff_{p}_vs_fp64"] = float(f"{float(torch.linalg.norm(S[p] - S['fp64']) / torch.linalg.norm(S['fp64'])):.3e}")
         rows.append(row)
-    return {"workload": "c2: d=3, n=19, N=8000, m=30, separation 0.08, |c| log-uniform [1e-2, 1]", "levels": rows}
+    # timing (values do not matter): the last level's inputs, every precision
+    timing = {}
+    reps = max(20, args.steps)
+    for prec in ("fp64", "fp32", "bf16x3"):
+        for _ in range(args.warmup):
+            api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
+        api.profile_enable(dev, DOMINANT)
+        ms = float(np.median(per_call_ms(lambda: api.build_S(f, d, n, Ud, sd, Vd, prec=prec), reps)))
+        nl, tot = api.profile_read(dev)
+        api.profile_enable(dev, None)
+        tiles = tot / max(1, nl)
+        own = tile_flops(d, n, m)
+        timing[prec] = {"s_build_ms_median": round(ms, 5), "calls": reps,
+                        "fs_equivalent_tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 2),
+                        "tiles_ms": round(tiles, 5), "tiles_own_work_tflops": round(own / (tiles * 1e-3) / 1e12, 2),
+                        "tiles_frac_of_peak": round(own / (tiles * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4),
+                        "split_target_wgs": autotune.registered(dev, d, n, m, prec, False) or None}
+    return {"workload": "c2: d=3, n=19, N=8000, m=30, separation 0.08, |c| log-uniform [1e-2, 1]", "levels": rows,
+            "s_build": timing, "own_work_flops_per_launch": tile_flops(d, n, m)}
 
 
 def _closed_form_factors(t, c, d, n):
@@ -446,7 +491,7 @@ def batched_c3(dev, args):
 
     insts = config_instances("c3")
     dev_inst = []
-    flops = 0.0
+    flops = own = 0.0
     for inst in insts:
         U, s, V = _closed_form_factors(inst.t, inst.c, inst.d, inst.n)
         f = api.samples(torch.from_numpy(inst.t).to(dev), torch.from_numpy(inst.c).to(dev), inst.n,
@@ -454,6 +499,7 @@ def batched_c3(dev, args):
         dev_inst.append((inst.d, inst.n, f, torch.from_numpy(U).to(dev), torch.from_numpy(s).to(dev),
                          torch.from_numpy(V).to(dev)))
         flops += s_flops(inst.d, inst.N, inst.m)
+        own += tile_flops(inst.d, inst.n, inst.m)
     tuned = None
     if not args.no_tune:
         times = autotune.tune_batch(dev_inst, "fp32", reps=2)
@@ -522,7 +568,8 @@ def batched_c3(dev, args):
         "ms_fp64_graph_batched": round(ms_graph64, 4),
         "speedup_fp64_batched_over_fp64_loop": round(ms_loop / ms_graph64, 2),
         "ms_fp64_loop": round(ms_loop, 4),
-        "tflops_fp32_graph": round(flops / (ms_graph * 1e-3) / 1e12, 3),
+        "fs_equivalent_tflops_fp32_graph": round(flops / (ms_graph * 1e-3) / 1e12, 3),
+        "own_work_tflops_fp32_graph": round(own / (ms_graph * 1e-3) / 1e12, 3),
         "rel_err_fp32_vs_fp64": float(f"{rel:.3e}"),
         "tuned_chunks_per_instance": tuned,
     }
@@ -584,15 +631,21 @@ def adjoint_c4(dev, args):
     bp.close()
     inst = insts[0]
     f1 = s_flops(inst.d, inst.N, inst.m)
+    # own work of the adjoint tiles (row-extended form): the (n+2)^d x N product of
+    # inner dimension m, 8 (n+2)^d N m flops
+    adj_own = 8.0 * (inst.n + 2) ** inst.d * inst.N * inst.m
     flops = len(insts) * 2 * f1
     return {
         "workload": "c4: 64 instances of d=2, n=47, m=16, noise 1e-6; L = sum_l ||S_l - S_l^ref||_F^2 "
                     "= sum_l ||S_l(f - f0)||_F^2",
         "ms_forward_backward_64_batched": round(ms_batched, 4),
-        "tflops_forward_plus_adjoint_batched": round(flops / (ms_batched * 1e-3) / 1e12, 3),
+        "fs_equivalent_tflops_forward_plus_adjoint_batched": round(flops / (ms_batched * 1e-3) / 1e12, 3),
         "ms_batched_forward_kernels": round(ms_fwd, 4),
         "ms_batched_adjoint_kernels": round(ms_adj, 4),
-        "tflops_batched_adjoint_kernels": round(len(insts) * f1 / (ms_adj * 1e-3) / 1e12, 3),
+        "fs_equivalent_tflops_batched_adjoint_kernels": round(len(insts) * f1 / (ms_adj * 1e-3) / 1e12, 3),
+        "own_work_tflops_batched_adjoint_kernels": round(len(insts) * adj_own / (ms_adj * 1e-3) / 1e12, 3),
+        "own_work_tflops_batched_forward_kernels": round(len(insts) * tile_flops(inst.d, inst.n, inst.m)
+                                                         / (ms_fwd * 1e-3) / 1e12, 3),
         "ms_forward_backward_64_one_instance_at_a_time": round(ms_loop, 4),
     }
 
@@ -650,6 +703,8 @@ def cpu_baseline(inst, U, sig, V, z, S_gpu, steps, recovered, grid_gpu):
         "value": round(F / el / 1e12, 6),
         "unit": "TFLOP/s",
         "cores": int(threads),
+        "cores_note": "BLAS threads the oracle's matrix products ran on (the rest of the oracle is one thread)",
+        "host_cpus_available": len(os.sched_getaffinity(0)),
         "kind": "oracle",
         "sample": f"{steps} whole oracle steps (samples, T, S_1..S_d, Gram/rhs) of the same workload, "
                   f"{el:.3f} s per step",

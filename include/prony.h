@@ -31,7 +31,10 @@
  *    prony_last_error() returns a text for the last failure on the handle.
  *  - Documented preconditions that are not checked on the device: sigma_j > 0
  *    and finite inputs. NaN inputs propagate to the outputs.
- *  - A handle may be used by one host thread at a time.
+ *  - A handle may be used by one host thread at a time. Its single-instance
+ *    calls share one workspace; prony_set_stream orders a new stream after the
+ *    work already queued on the previous one, so calls through one handle on
+ *    several streams do not overwrite each other's operands (see there).
  */
 #ifndef PRONY_H
 #define PRONY_H
@@ -80,7 +83,12 @@ prony_status_t prony_create(prony_handle_t* handle, int device);
 /* Free the workspace and the handle. Waits for the handle's stream first. */
 prony_status_t prony_destroy(prony_handle_t handle);
 
-/* Enqueue all later work on `stream` (a hipStream_t owned by the caller). */
+/* Enqueue all later work on `stream` (a hipStream_t owned by the caller).
+   When `stream` differs from the current one, the new stream first waits, on the
+   device, for the work already queued on the previous stream (an event recorded
+   there), because every call through the handle shares the handle's workspace.
+   While either stream is being captured no such ordering is recorded: set the
+   stream before beginning a capture. */
 prony_status_t prony_set_stream(prony_handle_t handle, void* stream);
 
 /* Wait for the handle's stream; reports asynchronous kernel faults as PRONY_EHIP. */
@@ -91,7 +99,12 @@ const char* prony_last_error(prony_handle_t handle);
 
 /* Pre-size the workspace for problems up to (d_max, n_max, m_max) so that later
    single-instance calls (samples, build_T, build_S, build_S_adjoint, coeffs)
-   allocate nothing (needed before capturing such calls into a HIP graph). */
+   allocate nothing (needed before capturing such calls into a HIP graph). The
+   S-build is planned for every precision (PRONY_BF16X3 included), with and
+   without S_0, at the default split target, at every target the autotuner
+   chooses from and at the target registered for the shape, for m = m_max (or
+   N when smaller) and the 16 largest n up to n_max. Register tuning entries
+   before reserving. */
 prony_status_t prony_reserve(prony_handle_t handle, int d_max, int n_max, int m_max);
 
 /* Profiling aid. With a non-NULL `kernel` name, every later launch of that kernel

@@ -15,6 +15,7 @@ import torch
 from . import _lib
 
 _handles: dict = {}
+_call_locks: dict = {}
 _lock = threading.Lock()
 
 
@@ -31,20 +32,27 @@ def _handle(device: torch.device):
                 raise _lib.PronyError(st, f"prony_create(device={idx}) failed")
             h = hp
             _handles[idx] = h
+            _call_locks[idx] = threading.Lock()
     return h
 
 
 def _call(name: str, device: torch.device, *args):
+    """Run one library call on torch's current stream. The handle is shared by the
+    threads of the process; its lock keeps one call (stream switch and call) at a
+    time. The library orders a new stream after the previous one's queued work."""
     lib = _lib.load()
     h = _handle(device)
+    idx = device.index if device.index is not None else torch.cuda.current_device()
     stream = torch.cuda.current_stream(device)
-    st = lib.prony_set_stream(h, ctypes.c_void_p(stream.cuda_stream))
-    if st != _lib.PRONY_OK:
-        raise _lib.PronyError(st, "prony_set_stream failed")
-    st = getattr(lib, name)(h, *args)
-    if st != _lib.PRONY_OK:
-        msg = lib.prony_last_error(h)
-        raise _lib.PronyError(st, f"{name}: {msg.decode() if msg else ''}")
+    with _call_locks[idx]:
+        st = lib.prony_set_stream(h, ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.PRONY_OK:
+            msg = lib.prony_last_error(h)
+            raise _lib.PronyError(st, f"prony_set_stream: {msg.decode() if msg else ''}")
+        st = getattr(lib, name)(h, *args)
+        if st != _lib.PRONY_OK:
+            msg = lib.prony_last_error(h)
+            raise _lib.PronyError(st, f"{name}: {msg.decode() if msg else ''}")
 
 
 def _ptr(x):
@@ -110,14 +118,7 @@ def build_T(f: torch.Tensor, d: int, n: int, which: int = 0, out: torch.Tensor |
 _S_PRECS = {"fp64": _lib.PRONY_FP64, "fp32": _lib.PRONY_FP32, "bf16x3": _lib.PRONY_BF16X3}
 
 
-def build_S(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,
-            prec: str = "fp64", with_s0: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
-    """S_l = U^* T_l V Sigma^{-1}, l = 1..d (prony_build_S); shape (d[+1], m, m).
-
-    V is the right factor itself (torch.linalg.svd returns V^* as Vh: pass Vh.mH).
-    prec: 'fp64', 'fp32' or 'bf16x3' (three-term bfloat16 splits on the bf16 MFMA,
-    same error scale as 'fp32').
-    """
+def _build_S(entry: str, f, d, n, U, sigma, V, prec, with_s0, out):
     _require(f, "f", torch.complex128)
     dev = f.device
     if f.numel() != grid_size(d, n):
@@ -140,9 +141,20 @@ def build_S(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tenso
         _require(out, "out", torch.complex128, dev)
         if out.shape != (ells, m, m):
             raise ValueError("out has the wrong shape")
-    _call("prony_build_S", dev, d, n, m, _ptr(f), _ptr(U), U.stride(0), U.stride(1), _ptr(sigma),
+    _call(entry, dev, d, n, m, _ptr(f), _ptr(U), U.stride(0), U.stride(1), _ptr(sigma),
           _ptr(V), V.stride(0), V.stride(1), _S_PRECS[prec], _lib.PRONY_WITH_S0 if with_s0 else 0, _ptr(out))
     return out
+
+
+def build_S(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,
+            prec: str = "fp64", with_s0: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
+    """S_l = U^* T_l V Sigma^{-1}, l = 1..d (prony_build_S); shape (d[+1], m, m).
+
+    V is the right factor itself (torch.linalg.svd returns V^* as Vh: pass Vh.mH).
+    prec: 'fp64', 'fp32' or 'bf16x3' (three-term bfloat16 splits on the bf16 MFMA,
+    same error scale as 'fp32').
+    """
+    return _build_S("prony_build_S", f, d, n, U, sigma, V, prec, with_s0, out)
 
 
 def build_S_adjoint(gS: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,

@@ -2,16 +2,19 @@
 // generateSl), with U, Sigma, V held fixed: given gS_l = dL/dS_l (PyTorch's
 // convention, grad = dL/dRe + i dL/dIm), the gradient on the sample grid is
 //     grad(p) = sum_l sum_{k - h + e_l = p} X_l[k, h],   X_l = U gS_l Sigma^{-1} V^*.
-// With h' = h - e_l as in the forward kernel, all d terms are one product of
-//     Z = [U gS_1 Sigma^{-1} | ... | U gS_d Sigma^{-1}]      (N x d m)
-// with the stacked conjugated shifted factors W_l[h', q] = conj(V[h'+e_l, q]):
-//     grad(p) = sum_{k - h' = p} (Z W^T)[k, h'],
-// i.e. the N x (n+2)^d product is summed along its Toeplitz diagonals.
+// With k' = k + e_l as in the forward kernel (row-extended form), all d terms are
+// one product of the row-extended matrix
+//     Z[k', q] = sum_l (U gS_l Sigma^{-1})[k' - e_l, q]   (k' in {0..n+1}^d; a term
+//                 is zero where k' - e_l leaves I_n)          ((n+2)^d x m)
+// with the conjugated factor W[h, q] = conj(V[h, q]), h in I_n:
+//     grad(p) = sum_{k' - h = p} (Z W^T)[k', h],
+// i.e. the (n+2)^d x N product (inner dimension m) is summed along its Toeplitz
+// diagonals.
 //
 // adjoint_pack   forms Z (FP64, stored in T), packs W in the MFMA pair layout,
-//                writes the G(h') table and zeroes the gradient;
-// adjoint_tiles  one workgroup = 64 rows k x one chunk of h': for every block of
-//                16 h' the tile of Z W^T is formed on MFMA (K = d m), and each
+//                writes the G(h) table and zeroes the gradient;
+// adjoint_tiles  one workgroup = 64 rows k' x one chunk of h: for every block of
+//                16 h the tile of Z W^T is formed on MFMA (K = m), and each
 //                entry is added (LDS atomics, accumulation in FP64) to the bin of
 //                its diagonal in an LDS copy of the workgroup's grid window; the
 //                window is then added to the gradient in FP64 (device atomics).
@@ -28,13 +31,14 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kRows = kWaves * 16;
 constexpr int kThreads = kWaves * 64;
-constexpr int kHBlock = 16;          // h' per MFMA output block (32 real columns)
+constexpr int kHBlock = 16;          // h per MFMA output block (32 real columns)
 
 struct AdjPlan {
-    int d, n, N, m, C;
-    int cp;        // complex K padded to a multiple of 8 (2 * KS... see ksteps)
+    int d, n, N, m;
+    int NR;        // (n+2)^d row-extended rows k'
+    int cp;        // complex K (m) padded to a multiple of 8
     int ksteps;    // cp / 4
-    int rf, rows;  // 16-row fragments per wave, rows k per tile (64 rf)
+    int rf, rows;  // 16-row fragments per wave, rows k' per tile (64 rf)
     int kb, kc, sk, rt, nwg, win_cap, c0, gsize;
     size_t lds_bytes;
     size_t off_z, off_w, off_g, ws_bytes;
@@ -52,19 +56,38 @@ __device__ __forceinline__ void adj_pack_body(const AdjPlan& P, const double2* _
     const int first = blockIdx.x * blockDim.x + threadIdx.x;
     const int kbp = P.sk * P.kc;
     if (section == 0) {
-        // Z[k][c] = sum_i U[k,i] gS_l[i,q] / sigma_q, c = (l-1) m + q; rows padded to
-        // whole tiles and columns to cp with zeros
+        // Z[k'][q] = sum over l (in order) of sum_i U[k'-e_l, i] gS_l[i,q] / sigma_q for
+        // the l with k' - e_l in I_n; rows padded to whole tiles and columns to cp with zeros
         const int nz = P.rt * P.rows * P.cp;
+        const int E = P.n + 2, Pn = P.n + 1;
         for (int e = first; e < nz; e += stride) {
-            const int k = e / P.cp, c = e - (e / P.cp) * P.cp;
+            const int kr = e / P.cp, q = e - (e / P.cp) * P.cp;
             double re = 0.0, im = 0.0;
-            if (k < P.N && c < P.C) {
-                const int li = c / P.m, q = c - li * P.m;
-                for (int i = 0; i < P.m; ++i) {
-                    const double2 u = U[k * u_rs + i * u_cs];
-                    const double2 gv = gS[((size_t)li * P.m + i) * P.m + q];
-                    re = fma(u.x, gv.x, fma(-u.y, gv.y, re));
-                    im = fma(u.x, gv.y, fma(u.y, gv.x, im));
+            if (kr < P.NR && q < P.m) {
+                int dig[3] = {0, 0, 0};
+                int rem = kr;
+                for (int l = P.d - 1; l >= 0; --l) {
+                    dig[l] = rem % E;
+                    rem /= E;
+                }
+                for (int ell = 0; ell < P.d; ++ell) {
+                    bool inside = dig[ell] >= 1;
+                    int idx = 0;
+                    for (int l = 0; l < P.d; ++l) {
+                        const int coord = dig[l] - (l == ell ? 1 : 0);
+                        inside = inside && coord <= P.n;
+                        idx = idx * Pn + coord;
+                    }
+                    if (!inside) continue;
+                    double zr = 0.0, zi = 0.0;
+                    for (int i = 0; i < P.m; ++i) {
+                        const double2 u = U[idx * u_rs + i * u_cs];
+                        const double2 gv = gS[((size_t)ell * P.m + i) * P.m + q];
+                        zr = fma(u.x, gv.x, fma(-u.y, gv.y, zr));
+                        zi = fma(u.x, gv.y, fma(u.y, gv.x, zi));
+                    }
+                    re += zr;
+                    im += zi;
                 }
                 const double s = sigma[q];
                 re /= s;
@@ -73,37 +96,23 @@ __device__ __forceinline__ void adj_pack_body(const AdjPlan& P, const double2* _
             zp[e] = T2{(T)re, (T)im};
         }
     } else if (section == 1) {
-        // W pairs, row c, column j = 2 h' + part: (Re Z) multiplies .x, (Im Z) .y
-        const int E = P.n + 2, Pn = P.n + 1;
+        // W pairs, row q, column j = 2 h + part: (Re Z) multiplies .x, (Im Z) .y
         const int row = 2 * kbp;
         const int nw = P.cp * row;
         for (int e = first; e < nw; e += stride) {
-            const int c = e / row, j = e - (e / row) * row;
+            const int q = e / row, j = e - (e / row) * row;
             const int hx = j >> 1;
             double wr = 0.0, wi = 0.0;
-            if (hx < P.kb && c < P.C) {
-                const int li = c / P.m, q = c - li * P.m;
-                const int ell = li + 1;
-                int rem = hx, idx = 0, scale = 1;
-                bool inside = true;
-                for (int l = P.d - 1; l >= 0; --l) {
-                    const int qq = rem / E;
-                    const int coord = rem - qq * E - 1 + (l == ell - 1 ? 1 : 0);
-                    rem = qq;
-                    inside = inside && coord >= 0 && coord <= P.n;
-                    idx += coord * scale;
-                    scale *= Pn;
-                }
-                if (inside) {
-                    const double2 v = V[idx * v_rs + q * v_cs];
-                    wr = v.x;
-                    wi = -v.y;   // conj
-                }
+            if (hx < P.kb && q < P.m) {
+                const double2 v = V[hx * v_rs + q * v_cs];
+                wr = v.x;
+                wi = -v.y;   // conj
             }
             wp[e] = (j & 1) ? T2{(T)wi, (T)wr} : T2{(T)wr, (T)(-wi)};
         }
     } else {
-        for (int hx = first; hx < kbp; hx += stride) gt[hx] = ext_offset(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
+        for (int hx = first; hx < kbp; hx += stride)
+            gt[hx] = grid_offset_of_index(hx < P.kb ? hx : P.kb - 1, P.d, P.n);
         for (int p = first; p < P.gsize; p += stride) gf[p] = make_double2(0.0, 0.0);
     }
 }
@@ -154,11 +163,11 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
     const int g = lane >> 4, col = lane & 15;
     const int sk_i = L / P.rt, rt_i = L - (L / P.rt) * P.rt;
     const int k_first = rt_i * kTileRows;
-    const int k_last = min(k_first + kTileRows - 1, P.N - 1);
+    const int k_last = min(k_first + kTileRows - 1, P.NR - 1);
     const int h_first = sk_i * P.kc;
     const int h_last = min(h_first + P.kc, P.kb) - 1;
-    const int lo = grid_offset_of_index(k_first, P.d, P.n) - ext_offset(h_last, P.d, P.n) + P.c0;
-    const int hi = grid_offset_of_index(k_last, P.d, P.n) - ext_offset(h_first, P.d, P.n) + P.c0;
+    const int lo = rowext_offset(k_first, P.d, P.n) - grid_offset_of_index(h_last, P.d, P.n) + P.c0;
+    const int hi = rowext_offset(k_last, P.d, P.n) - grid_offset_of_index(h_first, P.d, P.n) + P.c0;
     const int W = hi - lo + 1;
     const int rowlen = 2 * P.sk * P.kc;
     const int nblk = P.kc / kHBlock;
@@ -186,8 +195,8 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
     for (int f = 0; f < RF; ++f)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            gk[f][r] = grid_offset_of_index(min(k_first + 16 * RF * wave + 16 * f + M::row(g, r), P.N - 1), P.d,
-                                            P.n) + P.c0 - lo;
+            gk[f][r] = rowext_offset(min(k_first + 16 * RF * wave + 16 * f + M::row(g, r), P.NR - 1), P.d, P.n) +
+                       P.c0 - lo;
 #pragma unroll
     for (int u = 0; u < kStg; ++u) wst[tid + u * kThreads] = stg[u];
     __syncthreads();
@@ -217,7 +226,8 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
             }
         }
         // element r of lane (g, col) in block cb of fragment f: row 16 f + row(g,r),
-        // real column j = 16 cb + col, i.e. h' = 16 hb + j/2 and part j&1
+        // real column j = 16 cb + col, i.e. h = 16 hb + j/2 and part j&1 (rows past
+        // the last row of Z are zero rows: they add zeros)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             const int j = cb * 16 + col;
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_tiles_batched(const AdjEntry
     adjoint_body<T, KS, RF>(e.P, ptr, id - e.tile_begin);
 }
 
-// A single adjoint aims at two workgroups per CU; a batch member splits its h'
+// A single adjoint aims at two workgroups per CU; a batch member splits its h
 // range only into chunks of about 256 (long enough to amortise the window flush;
 // the batch fills the GPU).
 prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize, AdjPlan& P, bool batched = false) {
@@ -296,13 +306,13 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
     P.n = n;
     P.N = (int)ipow(n + 1, d);
     P.m = m;
-    P.C = d * m;
-    P.cp = (int)align_up((size_t)P.C, 8);
+    P.NR = (int)ipow(n + 2, d);
+    P.cp = (int)align_up((size_t)m, 8);
     P.ksteps = P.cp / 4;
-    P.kb = (int)ipow(n + 2, d);
-    P.rf = adj_rf2_supported(tsize, P.ksteps) && P.N > kRows ? 2 : 1;
+    P.kb = P.N;
+    P.rf = adj_rf2_supported(tsize, P.ksteps) && P.NR > kRows ? 2 : 1;
     P.rows = kRows * P.rf;
-    P.rt = (P.N + P.rows - 1) / P.rows;
+    P.rt = (P.NR + P.rows - 1) / P.rows;
     P.c0 = grid_center(d, n);
     P.gsize = (int)ipow(2 * n + 2, d);
     const size_t staging = 2 * (2 * tsize) * (size_t)P.cp * 32;
@@ -311,19 +321,19 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
     const int sk_target = std::max(1, target / P.rt);
     int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), kHBlock);
     kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, kHBlock)));
-    auto span = [&](int count, int len, bool ext) {
+    auto span = [&](int count, int len, bool rowext) {
         int best = 0;
         for (int s = 0; s < count; s += len) {
             const int e = std::min(s + len, count) - 1;
-            const int a = ext ? ext_offset(s, d, n) : grid_offset_of_index(s, d, n);
-            const int b = ext ? ext_offset(e, d, n) : grid_offset_of_index(e, d, n);
+            const int a = rowext ? rowext_offset(s, d, n) : grid_offset_of_index(s, d, n);
+            const int b = rowext ? rowext_offset(e, d, n) : grid_offset_of_index(e, d, n);
             best = std::max(best, b - a);
         }
         return best;
     };
-    const int rowspan = span(P.N, P.rows, false);
+    const int rowspan = span(P.NR, P.rows, true);
     for (;;) {
-        const int win = rowspan + span(P.kb, kc, true) + 1;
+        const int win = rowspan + span(P.kb, kc, false) + 1;
         const size_t lds = adj_bins_bytes(win) + adj_gt_bytes(kc) + staging;
         if (lds <= budget) {
             P.kc = kc;
@@ -400,17 +410,9 @@ prony_status_t launch_adjoint(prony_handle_t h, const AdjPlan& P, const double* 
         PRONY_ADJ_CASE(4)
         PRONY_ADJ_CASE(6)
         PRONY_ADJ_CASE(8)
-        PRONY_ADJ_CASE(10)
-        PRONY_ADJ_CASE(12)
-        PRONY_ADJ_CASE(14)
-        PRONY_ADJ_CASE(16)
-        PRONY_ADJ_CASE(18)
-        PRONY_ADJ_CASE(20)
-        PRONY_ADJ_CASE(22)
-        PRONY_ADJ_CASE(24)
 #undef PRONY_ADJ_CASE
         default:
-            return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint: d*m too large");
+            return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint: m too large");
     }
     if (st != PRONY_OK) return st;
     return check_launch(h, "adjoint_tiles");
@@ -561,17 +563,9 @@ prony_status_t adj_batch_launch(prony_handle_t h, const AdjBatch* A, const doubl
             PRONY_ADJ_BCASE(4)
             PRONY_ADJ_BCASE(6)
             PRONY_ADJ_BCASE(8)
-            PRONY_ADJ_BCASE(10)
-            PRONY_ADJ_BCASE(12)
-            PRONY_ADJ_BCASE(14)
-            PRONY_ADJ_BCASE(16)
-            PRONY_ADJ_BCASE(18)
-            PRONY_ADJ_BCASE(20)
-            PRONY_ADJ_BCASE(22)
-            PRONY_ADJ_BCASE(24)
 #undef PRONY_ADJ_BCASE
             default:
-                return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint_batched: d*m too large");
+                return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint_batched: m too large");
         }
         if (st != PRONY_OK) return st;
         if ((st = check_launch(h, "adjoint_tiles_batched")) != PRONY_OK) return st;

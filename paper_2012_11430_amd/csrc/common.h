@@ -32,6 +32,8 @@ struct prony_handle_s {
     hipEvent_t fork = nullptr;
     hipEvent_t join[kAux] = {};
     bool aux_ready = false;
+    // orders the previous stream's work before the next stream's on a stream change
+    hipEvent_t order = nullptr;
 };
 
 namespace prony {

@@ -142,6 +142,21 @@ extern "C" prony_status_t prony_create(prony_handle_t* handle, int device) {
         h->num_cus = prop.multiProcessorCount;
         h->lds_per_block = prop.sharedMemPerBlock;
     }
+    prony_status_t st = PRONY_OK;
+    {
+        DeviceGuard g(device);
+        if (!g.ok) {
+            st = PRONY_EHIP;
+        } else if (hipEventCreateWithFlags(&h->order, hipEventDisableTiming) != hipSuccess) {
+            h->order = nullptr;
+            st = PRONY_EHIP;
+        }
+    }
+    if (st != PRONY_OK) {
+        if (h->order) (void)hipEventDestroy(h->order);
+        delete h;
+        return st;
+    }
     *handle = h;
     return PRONY_OK;
 }
@@ -167,13 +182,39 @@ extern "C" prony_status_t prony_destroy(prony_handle_t h) {
         if (h->join[a]) (void)hipEventDestroy(h->join[a]);
     }
     if (h->fork) (void)hipEventDestroy(h->fork);
+    if (h->order) (void)hipEventDestroy(h->order);
     delete h;
     return st;
 }
 
+// Every call through a handle shares its workspace. On a change of stream the new
+// stream waits (on the device, through an event) for the work already queued on the
+// previous one, so a call on the new stream cannot overwrite operands or partial
+// sums that a kernel still running on the old stream reads. Under stream capture
+// (of either stream) no ordering is recorded: set the stream before capturing.
 extern "C" prony_status_t prony_set_stream(prony_handle_t h, void* stream) {
     if (!h) return PRONY_EINVAL;
-    h->stream = reinterpret_cast<hipStream_t>(stream);
+    hipStream_t next = reinterpret_cast<hipStream_t>(stream);
+    if (next == h->stream || h->device < 0 || !h->order) {
+        h->stream = next;
+        return PRONY_OK;
+    }
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    hipStreamCaptureStatus a = hipStreamCaptureStatusNone, b = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(h->stream, &a);
+    if (e == hipSuccess) e = hipStreamIsCapturing(next, &b);
+    if (e != hipSuccess) {
+        // a query refused because some capture is in progress: treat as capturing
+        (void)hipGetLastError();
+        a = hipStreamCaptureStatusActive;
+    }
+    if (a == hipStreamCaptureStatusNone && b == hipStreamCaptureStatusNone) {
+        e = hipEventRecord(h->order, h->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(next, h->order, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "stream ordering");
+    }
+    h->stream = next;
     return PRONY_OK;
 }
 

@@ -58,6 +58,20 @@ __device__ __forceinline__ double swap_lane_pair(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Grid offset G(k') = sum_l k'_l (2n+2)^(d-l) of the row-extended index k',
+// row-major over {0..n+1}^d (digits in base n+2).
+__host__ __device__ inline int rowext_offset(int r, int d, int n) {
+    const int E = n + 2, Q = 2 * n + 2;
+    int g = 0, scale = 1;
+    for (int l = d - 1; l >= 0; --l) {
+        const int q = r / E;
+        g += (r - q * E) * scale;
+        r = q;
+        scale *= Q;
+    }
+    return g;
+}
+
 // Grid offset of the extended index h' (row-major over {-1..n}^d).
 __host__ __device__ inline int ext_offset(int hx, int d, int n) {
     const int E = n + 2, Q = 2 * n + 2;

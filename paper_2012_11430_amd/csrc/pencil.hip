@@ -1,24 +1,30 @@
 // Pencil matrices S_l = U^* T_l V Sigma^{-1} (Sec. 1, eq. generateSl) on MFMA.
 //
-// Formulation. With h' = h - e_l, T_l[k,h] = f(k - h') and the d products
-// Y_l = T_l V are one product of the shift-free "extended" Toeplitz matrix
-// T_ext[k,h'] = f(k-h'), h' in {-1..n}^d, with the stacked shifted right
-// factors V_l[h',q] = V[h'+e_l, q] (zero where h'+e_l leaves I_n):
-//     [Y_1 .. Y_d] = T_ext [V_1 .. V_d].
+// Formulation (row-extended). With k' = k + e_l, T_l[k,h] = f(k' - h), so the d
+// products Y_l = T_l V are rows of ONE product of the row-extended Toeplitz matrix
+// T_row[k',h] = f(k'-h), k' in {0..n+1}^d, h in I_n, with V itself:
+//     Z = T_row V,   Y_l[k] = Z[k + e_l],
+// and the U^* reduction of the pencil matrices becomes
+//     U^* T_l V = sum_k' U_l[k']^* Z[k'],   U_l[k'] = U[k' - e_l]
+// (zero where k' - e_l leaves I_n; U_0 = U for S_0). The MFMA work of the large
+// product is that of one N x N by N x m product on (n+2)^d rows, not d of them;
+// the d shifted copies of U enter only the m-row reduction of each tile.
 // The complex product is run as a real one: every complex column q yields the
 // real columns (Re, Im) and every complex T entry a contributes two MFMAs, one
 // with Re(a) against (Re v, Im v) and one with Im(a) against (-Im v, Re v).
 // The second factor is packed once per call in that pair layout.
 //
 // Kernels:
-//   pencil_pack         packs V_l (pair layout, or bfloat16 split planes), U
-//                       (Re/Im pairs) and the grid offsets G(h') of the extended
-//                       index set into the workspace;
-//   pencil_tiles        one workgroup = 64 rf rows k x one chunk of h'; the T_ext
+//   pencil_pack         packs V (pair layout, or bfloat16 split planes), U in the
+//                       row-extended layout (Re/Im pairs, zero rows where k' leaves
+//                       I_n, zero guard rows in front so that every shift k' - e_l
+//                       is a plain row offset) and the grid offsets G(h);
+//   pencil_tiles        one workgroup = 64 rf rows k' x one chunk of h; the T_row
 //                       tile is generated from a flat window of the sample grid
 //                       staged in LDS, multiplied on MFMA (FP32 or FP64) against
-//                       the packed V_l, then the U^* reduction over the tile's rows
-//                       runs on MFMA as well and the m x (d m) partial is stored;
+//                       the packed V, then the reductions with the shifted U_l over
+//                       the tile's rows run on MFMA as well and the m x (d m)
+//                       partial is stored;
 //   pencil_tiles_split  the same tile with both operands as three bfloat16 terms
 //                       on the bf16 MFMA (FP32-accurate products);
 //   pencil_finish       sums the partials of all workgroups in FP64 in a fixed
@@ -60,21 +66,24 @@ constexpr bool rf2_supported(size_t tsize, int nb) { return nb <= (tsize == 4 ? 
 
 struct PencilPlan {
     int d, n, N, m;
-    int mode;       // 0: S-build (extended h', U^* epilogue); 1: product Y = T X (h in I_n)
+    int mode;       // 0: S-build (row-extended k', shifted U^* epilogue); 1: product Y = T X
     int conj_grid;  // product mode: stage conj(f(-p)), i.e. multiply by T^* instead of T
     int split;      // 1: operands as three bfloat16 terms on the bf16 MFMA (T = float)
     int bbufs;      // split: LDS buffers of the staged B planes (2, or 1 when two do not fit)
     int ells;       // stacked matrices: d, or d + 1 with S_0
     int first_ell;  // 0 with S_0, else 1
-    int C;          // complex columns ells * m
-    int nb;         // 16-wide blocks of the 2C real columns
+    int C;          // complex columns of the result rows: ells * m (product: r)
+    int CB;         // complex columns of the second operand V (or X): m
+    int nb;         // 16-wide blocks of the 2 CB real columns of the second operand
     int nrp;        // 16 * nb
     int mbi;        // 16-row blocks of the m output rows
-    int kb;         // (n+2)^d extended indices h' (N plain indices h in product mode)
-    int kc;         // h' per chunk (multiple of 16)
+    int NR;         // rows of the large product: (n+2)^d row-extended k' (product: N)
+    int ug;         // zero guard rows in front of the packed U: (n+2)^(d-1), the largest shift
+    int kb;         // N indices h of I_n (the K range)
+    int kc;         // h per chunk (multiple of 16)
     int sk;         // chunks
     int rf;         // 16-row fragments per wave (1 or 2)
-    int rows;       // rows k per tile: 64 rf
+    int rows;       // rows k' per tile: 64 rf
     int rt;         // row tiles
     int nbp;        // 16-column blocks per pass of the cross-wave sum
     int nwg;        // rt * sk workgroups
@@ -86,10 +95,21 @@ struct PencilPlan {
 };
 
 
-// Grid offset of the K index hx: extended h' for the S-build, plain h of I_n
-// for the product.
-__host__ __device__ inline int h_offset(const PencilPlan& P, int hx) {
-    return P.mode ? grid_offset_of_index(hx, P.d, P.n) : ext_offset(hx, P.d, P.n);
+// Grid offset of the K index h of I_n.
+__host__ __device__ inline int h_offset(const PencilPlan& P, int hx) { return grid_offset_of_index(hx, P.d, P.n); }
+
+// Grid offset of row r of the large product: row-extended k' for the S-build,
+// k of I_n for the product.
+__host__ __device__ inline int row_offset(const PencilPlan& P, int r) {
+    return P.mode ? grid_offset_of_index(r, P.d, P.n) : rowext_offset(r, P.d, P.n);
+}
+
+// Row-extended shift of e_l: (n+2)^(d-l) for l = 1..d, 0 for l = 0.
+__host__ __device__ inline int rowext_shift(const PencilPlan& P, int ell) {
+    if (ell <= 0) return 0;
+    int s = 1;
+    for (int l = ell; l < P.d; ++l) s *= P.n + 2;
+    return s;
 }
 
 // Three-term bfloat16 split x = h + m + l (each term rounded to nearest; the
@@ -111,30 +131,15 @@ __device__ __forceinline__ void split3(float x, unsigned short& h, unsigned shor
 }
 
 // Pair values of the second operand at (row hx, real column j): .x multiplies
-// Re(a), .y multiplies Im(a) (see pack_body).
+// Re(a), .y multiplies Im(a); zero past the N rows and the CB columns.
 __device__ __forceinline__ double2 pair_of(const PencilPlan& P, const double2* __restrict__ V, int64_t v_rs,
                                            int64_t v_cs, int hx, int j) {
     const int c = j >> 1;
     double vr = 0.0, vi = 0.0;
-    if (hx < P.kb && c < P.C) {
-        const int E = P.n + 2, Pn = P.n + 1;
-        const int li = c / P.m, q = c - li * P.m;
-        const int ell = li + P.first_ell;
-        int rem = hx, idx = 0, scale = 1;
-        bool inside = true;
-        for (int l = P.d - 1; l >= 0; --l) {
-            const int qq = rem / E;
-            const int coord = rem - qq * E - 1 + (l == ell - 1 ? 1 : 0);
-            rem = qq;
-            inside = inside && coord >= 0 && coord <= P.n;
-            idx += coord * scale;
-            scale *= Pn;
-        }
-        if (inside) {
-            const double2 v = V[idx * v_rs + q * v_cs];
-            vr = v.x;
-            vi = v.y;
-        }
+    if (hx < P.kb && c < P.CB) {
+        const double2 v = V[hx * v_rs + c * v_cs];
+        vr = v.x;
+        vi = v.y;
     }
     return (j & 1) ? make_double2(vi, vr) : make_double2(vr, -vi);
 }
@@ -171,10 +176,13 @@ __device__ __forceinline__ void pack_split(const PencilPlan& P, const double2* _
     }
 }
 
-// Packs, per call: (y = 0) the stacked shifted factors V_l in the pair layout,
-// rows h' of the extended index set padded with zeros to sk*kc + kPrefetchRows;
-// (y = 1) the (Re U, Im U) pairs, rows padded to whole 64-row tiles and
-// columns to 16*mbi; (y = 2) the grid offsets G(h'). All index arithmetic fits in 32 bits (checked by the host plan).
+// Packs, per call: (y = 0) the second factor (V, or X of the product) in the pair
+// layout, rows h padded with zeros to sk*kc + kPrefetchRows; (y = 1) the (Re U,
+// Im U) pairs in the row-extended layout: ug zero guard rows, then row k' of
+// {0..n+1}^d (padded to whole tiles) holding U[k'] where k' lies in I_n and zero
+// elsewhere, columns padded to 16*mbi, so that U_l[k'] = U[k' - e_l] is the packed
+// row ug + k' - shift(e_l); (y = 2) the grid offsets G(h). All index arithmetic
+// fits in 32 bits (checked by the host plan).
 template <typename T>
 __device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __restrict__ U, int64_t u_rs,
                                           int64_t u_cs, const double2* __restrict__ V, int64_t v_rs, int64_t v_cs,
@@ -187,51 +195,39 @@ __device__ __forceinline__ void pack_body(const PencilPlan& P, const double2* __
     if (section == 0 && P.split) {
         pack_split(P, V, v_rs, v_cs, reinterpret_cast<u32x4*>(vp), first, stride);
     } else if (section == 0) {
-        const int E = P.n + 2, Pn = P.n + 1;
         const int nv = kbp * P.nrp;
         for (int i = first; i < nv; i += stride) {
             const int hx = i / P.nrp;
             const int j = i - hx * P.nrp;
-            const int c = j >> 1;
-            double vr = 0.0, vi = 0.0;
-            if (P.mode && hx < P.N && c < P.C) {
-                const double2 v = V[hx * v_rs + c * v_cs];
-                vr = v.x;
-                vi = v.y;
-            } else if (!P.mode && hx < P.kb && c < P.C) {
-                const int li = c / P.m, q = c - li * P.m;
-                const int ell = li + P.first_ell;   // 0 = T itself, l = shift along axis l
-                int rem = hx, idx = 0, scale = 1;
-                bool inside = true;
-                for (int l = P.d - 1; l >= 0; --l) {
-                    const int qq = rem / E;
-                    const int coord = rem - qq * E - 1 + (l == ell - 1 ? 1 : 0);
-                    rem = qq;
-                    inside = inside && coord >= 0 && coord <= P.n;
-                    idx += coord * scale;
-                    scale *= Pn;
-                }
-                if (inside) {
-                    const double2 v = V[idx * v_rs + q * v_cs];
-                    vr = v.x;
-                    vi = v.y;
-                }
-            }
             // (Re a) multiplies the first member, (Im a) the second.
-            vp[i] = (j & 1) ? T2{(T)vi, (T)vr} : T2{(T)vr, (T)(-vi)};
+            const double2 pr = pair_of(P, V, v_rs, v_cs, hx, j);
+            vp[i] = T2{(T)pr.x, (T)pr.y};
         }
     } else if (section == 1) {
         if (P.mode) return;   // the product has no U^* epilogue
         const int mup = P.mbi * 16;
-        const int nu = P.rt * P.rows * mup;
+        const int nu = (P.ug + P.rt * P.rows) * mup;
+        const int E = P.n + 2, Pn = P.n + 1;
         for (int r = first; r < nu; r += stride) {
-            const int k = r / mup;
-            const int col = r - k * mup;
+            const int kr = r / mup - P.ug;   // row-extended index k'
+            const int col = r - (r / mup) * mup;
             double ur = 0.0, ui = 0.0;
-            if (k < P.N && col < P.m) {
-                const double2 u = U[k * u_rs + col * u_cs];
-                ur = u.x;
-                ui = u.y;
+            if (kr >= 0 && kr < P.NR && col < P.m) {
+                int rem = kr, idx = 0, scale = 1;
+                bool inside = true;
+                for (int l = P.d - 1; l >= 0; --l) {
+                    const int qq = rem / E;
+                    const int coord = rem - qq * E;
+                    rem = qq;
+                    inside = inside && coord <= P.n;
+                    idx += coord * scale;
+                    scale *= Pn;
+                }
+                if (inside) {
+                    const double2 u = U[idx * u_rs + col * u_cs];
+                    ur = u.x;
+                    ui = u.y;
+                }
             }
             up[r] = T2{(T)ur, (T)ui};
         }
@@ -270,9 +266,9 @@ struct TilePtrs {
     double2* S;
 };
 
-// One workgroup tile of the S-build: rows 64 rt_i .. +63 of I_n against chunk
-// sk_i of the extended indices h', where L = sk_i * rt + rt_i. See the file
-// comment for the formulation.
+// One workgroup tile: rows kRows rt_i .. +kRows-1 of the large product (row-extended
+// k' for the S-build, k of I_n for the product) against chunk sk_i of the indices h
+// of I_n, where L = sk_i * rt + rt_i. See the file comment for the formulation.
 template <typename T, int NB, int RF, int MODE, bool SPLIT = false>
 __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>& ptr, const int L) {
     static_assert(!SPLIT || sizeof(T) == 4, "the split operands accumulate in FP32");
@@ -304,11 +300,11 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     const int sk_i = L / P.rt, rt_i = L - (L / P.rt) * P.rt;
 
     const int k_first = rt_i * kRows;
-    const int k_last = min(k_first + kRows - 1, P.N - 1);
+    const int k_last = min(k_first + kRows - 1, P.NR - 1);
     const int h_first = sk_i * P.kc;
     const int h_last = min(h_first + P.kc, P.kb) - 1;
-    const int lo = grid_offset_of_index(k_first, P.d, P.n) - h_offset(P, h_last) + P.c0;
-    const int hi = grid_offset_of_index(k_last, P.d, P.n) - h_offset(P, h_first) + P.c0;
+    const int lo = row_offset(P, k_first) - h_offset(P, h_last) + P.c0;
+    const int hi = row_offset(P, k_last) - h_offset(P, h_first) + P.c0;
     const int W = hi - lo + 1;
     // T^* X multiplies by the Toeplitz matrix of g(p) = conj(f(-p)): grid offsets
     // are affine in p, so g at offset o is conj(f at 2 c0 - o).
@@ -364,12 +360,12 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         for (int e = tid; e < bunits; e += kThreads) bst[bslot(e)] = bsrc[e];
     __syncthreads();
 
-    // Rows of this wave: k_first + 16 (RF wave + f) + col for fragment f.
+    // Rows of this wave: k_first + 16 (RF wave + f) + col for fragment f (rows past
+    // the last read the last row's offsets; their results are discarded).
     const int krow0 = k_first + kRowsPerWave * RF * wave + col;
     int gk[RF];
 #pragma unroll
-    for (int f = 0; f < RF; ++f)
-        gk[f] = grid_offset_of_index(min(krow0 + kRowsPerWave * f, P.N - 1), P.d, P.n) + P.c0 - lo;
+    for (int f = 0; f < RF; ++f) gk[f] = row_offset(P, min(krow0 + kRowsPerWave * f, P.NR - 1)) + P.c0 - lo;
 
     acc_t acc[RF][NB];
 #pragma unroll
@@ -589,31 +585,53 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         return;
     }
 
-    // U^* reduction over this wave's rows. The accumulators are the second
-    // MFMA operand directly: element r of lane (g, col) of fragment f is
-    // Y[16 f + row(g,r)][16cb+col] (rows relative to the wave's first row).
-    // Output column 2c gets Re(U^* Y)_c and 2c+1 gets Im: with the partner lane's
-    // value y' (column j^1), Re = Ur.Yr + Ui.Yi and Im = Ur.Yi - Ui.Yr.
-    // The U pairs of the first kUPre 16-row blocks of U^* are requested before
-    // the barrier, so their latency overlaps the other waves' K loops.
-    const int mup = P.mbi * 16;
-    const T2* urow = up + (size_t)(k_first + kRowsPerWave * RF * wave) * mup + col;
-    constexpr int kUPre = RF == 1 ? 2 : 1;
-    T2 upre[kUPre][RF][4];
-#pragma unroll
-    for (int ib = 0; ib < kUPre; ++ib)
+    // Rows past the last row of the product (padding of the last row tile) hold
+    // copies of that row's sums; they must not meet the shifted U_l rows below.
+    const int wrow0 = k_first + kRowsPerWave * RF * wave;
+    if (wrow0 + kRowsPerWave * RF > P.NR) {
 #pragma unroll
         for (int f = 0; f < RF; ++f)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (ib < P.mbi) upre[ib][f][r] = urow[(size_t)(kRowsPerWave * f + M::row(g, r)) * mup + ib * 16];
+                if (wrow0 + kRowsPerWave * f + M::row(g, r) >= P.NR)
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb) acc[f][cb][r] = T(0);
+    }
+
+    // Reductions with the shifted U_l over this wave's rows: for every 16-row block
+    // ib of U_l^* and every stored matrix l, e = U_l[rows]^* Z[rows], with
+    // U_l[k'] = packed U row ug + k' - shift(e_l). The accumulators are the second
+    // MFMA operand directly: element r of lane (g, col) of fragment f is
+    // Z[16 f + row(g,r)][16cb+col] (rows relative to the wave's first row).
+    // Output column 2c gets Re(U_l^* Z)_c and 2c+1 gets Im: with the partner lane's
+    // value y' (column j^1), Re = Ur.Yr + Ui.Yi and Im = Ur.Yi - Ui.Yr.
+    // The U pairs of the first (block, matrix) are requested before the barrier,
+    // so their latency overlaps the other waves' K loops; later ones one item ahead.
+    const int mup = P.mbi * 16;
+    const T2* ubase = up + (size_t)(P.ug + wrow0) * mup + col;
+    auto load_u = [&](T2 (&u)[RF][4], int ib, int li) {
+        const T2* src = ubase - (size_t)rowext_shift(P, li + P.first_ell) * mup + ib * 16;
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) u[f][r] = src[(size_t)(kRowsPerWave * f + M::row(g, r)) * mup];
+    };
+    T2 ucur[RF][4];
+    load_u(ucur, 0, 0);
     __syncthreads();   // the window is dead from here on; its bytes become the slabs
 
-    // One 16-row block of U^* Y: every wave multiplies its rows and writes its
-    // result into its own slab (lane-major, conflict-free); after a barrier all
-    // threads add the four slabs in wave order and store the block's partial
-    // pairs. The slabs hold nbp column blocks at a time (one pass when they fit).
-    auto reduce_block = [&](int ib, const T2 (&u)[RF][4]) {
+    // Every wave writes its block into its own slab (lane-major, conflict free):
+    // virtual 16-column block (l - l0) NB + cb of the pass. A pass holds lpp
+    // matrices (nbp >= NB blocks per wave); after one barrier all threads add the
+    // four slabs in wave order and store the partial pairs of the pass.
+    const T2* slab2 = reinterpret_cast<const T2*>(slab);
+    const int lpp = max(1, P.nbp / NB);
+    const int items = P.mbi * P.ells;
+    for (int it = 0; it < items; ++it) {
+        const int ib = it / P.ells, li = it - ib * P.ells;
+        const int l0 = li - li % lpp;
+        T2 unext[RF][4];
+        if (it + 1 < items) load_u(unext, (it + 1) / P.ells, (it + 1) % P.ells);
         acc_t e[NB];
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) e[cb] = acc_t{0, 0, 0, 0};
@@ -625,47 +643,39 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                 for (int cb = 0; cb < NB; ++cb) {
                     const T y = acc[f][cb][r];
                     const T ys = swap_lane_pair(y);
-                    e[cb] = M::fma(u[f][r].x, y, e[cb]);
-                    e[cb] = M::fma(u[f][r].y, odd ? -ys : ys, e[cb]);
+                    e[cb] = M::fma(ucur[f][r].x, y, e[cb]);
+                    e[cb] = M::fma(ucur[f][r].y, odd ? -ys : ys, e[cb]);
                 }
             }
-        const T2* slab2 = reinterpret_cast<const T2*>(slab);
-        const int rows = min(16, P.m - ib * 16);
-        T2* out = part + (size_t)L * P.m * P.C + (size_t)ib * 16 * P.C;
-        for (int cb0 = 0; cb0 < NB; cb0 += P.nbp) {
+        const int vb0 = (li - l0) * NB;
 #pragma unroll
-            for (int cb = 0; cb < NB; ++cb)
-                if (cb >= cb0 && cb < cb0 + P.nbp)
+        for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) slab[((wave * P.nbp + cb - cb0) * 4 + r) * 64 + lane] = e[cb][r];
+            for (int r = 0; r < 4; ++r) slab[((wave * P.nbp + vb0 + cb) * 4 + r) * 64 + lane] = e[cb][r];
+        if (li + 1 == P.ells || li + 1 - l0 == lpp) {
             __syncthreads();
-            // column pairs c with Re in column 2c of blocks cb0 .. cb0 + nbp - 1
-            const int c_lo = cb0 * 8, nc = min(P.C, (cb0 + P.nbp) * 8) - c_lo;
-            for (int o = tid; o < rows * nc; o += kThreads) {
-                const int il = o / nc, c = c_lo + (o - (o / nc) * nc);
+            const int nl = li + 1 - l0;
+            const int rows = min(16, P.m - ib * 16);
+            T2* out = part + (size_t)L * P.m * P.C + (size_t)ib * 16 * P.C + (size_t)l0 * P.m;
+            for (int o = tid; o < rows * nl * P.m; o += kThreads) {
+                const int il = o / (nl * P.m), rem = o - il * (nl * P.m);
+                const int lj = rem / P.m, c = rem - lj * P.m;
                 const int j = 2 * c;   // Re in column j, Im in column j + 1 (lane + 1)
-                const int s0 = (((j >> 4) - cb0) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 + (j & 15);
+                const int s0 = ((lj * NB + (j >> 4)) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 + (j & 15);
                 T2 sum = slab2[s0 >> 1];
                 for (int w = 1; w < kWaves; ++w) {
                     const T2 v = slab2[(s0 + w * P.nbp * 256) >> 1];
                     sum.x += v.x;
                     sum.y += v.y;
                 }
-                out[(size_t)il * P.C + c] = sum;
+                out[(size_t)il * P.C + lj * P.m + c] = sum;
             }
             __syncthreads();   // slabs are rewritten by the next pass
         }
-    };
-#pragma unroll
-    for (int ib = 0; ib < kUPre; ++ib)
-        if (ib < P.mbi) reduce_block(ib, upre[ib]);
-    for (int ib = kUPre; ib < P.mbi; ++ib) {
-        T2 u[RF][4];
 #pragma unroll
         for (int f = 0; f < RF; ++f)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) u[f][r] = urow[(size_t)(kRowsPerWave * f + M::row(g, r)) * mup + ib * 16];
-        reduce_block(ib, u);
+            for (int r = 0; r < 4; ++r) ucur[f][r] = unext[f][r];
     }
 }
 template <typename T, int NB, int RF>
@@ -761,16 +771,37 @@ size_t lds_bytes_for(int win, int kc, int nbp, size_t tsize, int split_nrp = 0, 
 }
 
 // Largest G-span of the aligned runs of `len` consecutive indices (row tiles of
-// I_n, or chunks of the extended set {-1..n}^d).
-int max_span(int count, int len, int d, int n, bool ext) {
+// I_n or of the row-extended set {0..n+1}^d, or chunks of I_n).
+int max_span(int count, int len, int d, int n, bool rowext) {
     int best = 0;
     for (int s = 0; s < count; s += len) {
         const int e = std::min(s + len, count) - 1;
-        const int a = ext ? ext_offset(s, d, n) : grid_offset_of_index(s, d, n);
-        const int b = ext ? ext_offset(e, d, n) : grid_offset_of_index(e, d, n);
+        const int a = rowext ? rowext_offset(s, d, n) : grid_offset_of_index(s, d, n);
+        const int b = rowext ? rowext_offset(e, d, n) : grid_offset_of_index(e, d, n);
         best = std::max(best, b - a);
     }
     return best;
+}
+
+// Bytes of the packed second factor, the packed U, the offset table and the
+// partial sums of a plan (the workspace sections, each aligned to 256 bytes).
+struct PlanBytes {
+    size_t v, u, g, p;
+};
+PlanBytes plan_bytes(const PencilPlan& P, size_t tsize) {
+    const size_t t2 = 2 * tsize;
+    PlanBytes b;
+    if (P.split)   // three bfloat16 planes per K block, 32 values per (plane, column)
+        b.v = align_up(((size_t)P.sk * P.kc / kSplitK) * kSplitPlanes * P.nrp * 64, 256);
+    else
+        b.v = align_up(t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
+    b.u = align_up(t2 * ((size_t)P.ug + (size_t)P.rt * P.rows) * P.mbi * 16, 256);
+    b.g = align_up(4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
+    if (P.mode)   // partial Y rows of every chunk, real columns
+        b.p = align_up(tsize * (size_t)P.sk * P.rt * P.rows * P.nrp, 256);
+    else
+        b.p = align_up(t2 * (size_t)P.nwg * P.m * P.C, 256);
+    return b;
 }
 
 // Registered split target for a shape class (0 if none).
@@ -796,19 +827,23 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.ells = mode ? 1 : d + (with_s0 ? 1 : 0);
     P.first_ell = mode || with_s0 ? 0 : 1;
     P.C = P.ells * m;
-    P.nb = (2 * P.C + 15) / 16;
+    P.CB = m;
+    P.nb = (2 * P.CB + 15) / 16;
     P.nrp = 16 * P.nb;
     P.mbi = mode ? 0 : (m + 15) / 16;
-    P.kb = mode ? P.N : (int)ipow(n + 2, d);
-    P.rf = allow_rf2 && rf2_supported(tsize, P.nb) && P.N > kRowsPerTile ? 2 : 1;
+    P.NR = mode ? P.N : (int)ipow(n + 2, d);
+    P.ug = mode ? 0 : (int)ipow(n + 2, d - 1);
+    P.kb = P.N;
+    P.rf = allow_rf2 && rf2_supported(tsize, P.nb) && P.NR > kRowsPerTile ? 2 : 1;
     P.rows = kRowsPerTile * P.rf;
-    P.rt = (P.N + P.rows - 1) / P.rows;
+    P.rt = (P.NR + P.rows - 1) / P.rows;
     P.c0 = grid_center(d, n);
 
     // two workgroups per CU; the split kernel, which also stages B planes, may
-    // take the whole LDS when its window does not fit otherwise
+    // take the whole LDS when its window does not fit otherwise. The epilogue's
+    // slabs hold nbp 16-column blocks per wave, at least the NB of one matrix.
     size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
-    P.nbp = std::max(1, std::min(P.nb, (int)(budget / (tsize * kWaves * 16 * 16))));
+    P.nbp = std::max(P.nb, std::min(P.ells * P.nb, (int)(budget / (tsize * kWaves * 16 * 16))));
     P.bbufs = 2;
     const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
@@ -816,9 +851,9 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), kal);
     kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, kal)));
     const int kc0 = kc;
-    const int rowspan = max_span(P.N, P.rows, d, n, false);
+    const int rowspan = max_span(P.NR, P.rows, d, n, !mode);
     for (;;) {
-        const int colspan = max_span(P.kb, kc, d, n, !mode);
+        const int colspan = max_span(P.kb, kc, d, n, false);
         const int win = rowspan + colspan + 1;
         size_t lds = lds_bytes_for(win, kc, mode ? 0 : P.nbp, tsize, split ? P.nrp : 0, 2);
         if (split && lds > budget) {   // one B buffer (two barriers per K block) before smaller chunks
@@ -847,26 +882,15 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.nwg = P.rt * P.sk;
     if (((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp >= (int64_t(1) << 31) ||
         (int64_t)P.nwg * P.m * P.C >= (int64_t(1) << 31) ||
+        ((int64_t)P.ug + (int64_t)P.rt * P.rows) * P.mbi * 16 >= (int64_t(1) << 31) ||
         (int64_t)P.sk * P.rt * P.rows * P.nrp >= (int64_t(1) << 31))
         return fail(h, PRONY_ENOTSUP, "prony_build_S: problem too large for 32-bit tile indexing");
-    const size_t t2 = 2 * tsize;
-    const size_t tot = (size_t)P.m * P.C;
-    size_t off = 0;
-    P.off_v = off;
-    if (split)   // three bfloat16 planes per K block, 32 values per (plane, column)
-        off = align_up(off + ((size_t)P.sk * P.kc / kSplitK) * kSplitPlanes * P.nrp * 64, 256);
-    else
-        off = align_up(off + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
-    P.off_u = off;
-    off = align_up(off + t2 * (size_t)P.rt * P.rows * P.mbi * 16, 256);
-    P.off_g = off;
-    off = align_up(off + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
-    P.off_p = off;
-    if (mode)   // partial Y rows of every chunk, real columns
-        off = align_up(off + tsize * (size_t)P.sk * P.rt * P.rows * P.nrp, 256);
-    else
-        off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
-    P.ws_bytes = off;
+    const PlanBytes b = plan_bytes(P, tsize);
+    P.off_v = 0;
+    P.off_u = P.off_v + b.v;
+    P.off_g = P.off_u + b.u;
+    P.off_p = P.off_g + b.g;
+    P.ws_bytes = P.off_p + b.p;
     return PRONY_OK;
 }
 
@@ -926,7 +950,8 @@ prony_status_t launch_tiles_split(prony_handle_t h, const PencilPlan& P, const T
     return PRONY_OK;
 }
 
-#define PRONY_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+// Column blocks of the S-build's second operand: 2m <= 64 real columns.
+#define PRONY_NB_CASES(X) X(1) X(2) X(3) X(4)
 
 // Work item of the queue schedule: a tile L of the instance at position `entry`
 // of the batch's entry table.
@@ -1010,21 +1035,21 @@ prony_status_t dispatch_batched(prony_handle_t h, int nb, int rf, const BatchEnt
     }
 }
 
+// The three launches of one S-build with the packed operands and partial sums in
+// the workspace at `ws` (P.ws_bytes bytes, owned by the caller of this function).
 template <typename T>
-prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, const double* f, const double* U, int64_t u_rs,
-                             int64_t u_cs, const double* sigma, const double* V, int64_t v_rs, int64_t v_cs,
-                             double* S) {
+prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, unsigned char* ws, const double* f,
+                             const double* U, int64_t u_rs, int64_t u_cs, const double* sigma, const double* V,
+                             int64_t v_rs, int64_t v_cs, double* S) {
     using T2 = pair_t<T>;
-    prony_status_t st = ensure_workspace(h, P.ws_bytes);
-    if (st != PRONY_OK) return st;
-    unsigned char* ws = static_cast<unsigned char*>(h->ws);
+    prony_status_t st = PRONY_OK;
     T2* vp = reinterpret_cast<T2*>(ws + P.off_v);
     T2* up = reinterpret_cast<T2*>(ws + P.off_u);
     int* gt = reinterpret_cast<int*>(ws + P.off_g);
     T2* part = reinterpret_cast<T2*>(ws + P.off_p);
 
     const int64_t kbp = (int64_t)P.sk * P.kc + kPrefetchRows;
-    const int64_t largest = std::max<int64_t>(kbp * P.nrp, (int64_t)P.rt * P.rows * P.mbi * 16);
+    const int64_t largest = std::max<int64_t>(kbp * P.nrp, ((int64_t)P.ug + (int64_t)P.rt * P.rows) * P.mbi * 16);
     const int pack_blocks = (int)std::min<int64_t>((largest + 255) / 256, 2 * (int64_t)h->num_cus);
     {
         ProfileScope prof(h, "pencil_pack");
@@ -1108,17 +1133,63 @@ prony_status_t launch_toeplitz_mm(prony_handle_t h, const PencilPlan& P, const d
 
 }  // namespace
 
-// Workspace bytes of one build_S call (used by prony_reserve).
+// Workspace bytes of one build_S call of shape (d, n, m) under any plan the
+// handle may choose (used by prony_reserve): every precision (the split-bfloat16
+// plan included), with and without S_0, at the default target, every target the
+// autotuner chooses from (1, 2, 3, 4 and 8 workgroups per compute unit) and the
+// target registered for the shape.
 size_t pencil_workspace_bytes(prony_handle_t h, int d, int n, int m) {
     size_t best = 0;
-    for (int s0 = 0; s0 < 2; ++s0)
-        for (size_t ts : {sizeof(float), sizeof(double)}) {
-            PencilPlan P;
-            if (make_plan(h, d, n, m, s0 == 1, ts, P, 0, true) == PRONY_OK) best = std::max(best, P.ws_bytes);
-        }
+    const std::string saved = h->err;   // plans that do not fit only fail here
+    for (int prec : {PRONY_FP64, PRONY_FP32, PRONY_BF16X3}) {
+        const size_t ts = prec == PRONY_FP64 ? sizeof(double) : sizeof(float);
+        const int targets[] = {0, h->num_cus, 2 * h->num_cus, 3 * h->num_cus, 4 * h->num_cus, 8 * h->num_cus,
+                               tuned_target(h, d, n, m, prec, 0)};
+        for (int s0 = 0; s0 < 2; ++s0)
+            for (int tg : targets) {
+                PencilPlan P;
+                if (make_plan(h, d, n, m, s0 == 1, ts, P, tg, true, 0, prec == PRONY_BF16X3) == PRONY_OK)
+                    best = std::max(best, P.ws_bytes);
+            }
+    }
+    h->err = saved;
     return best;
 }
 
+namespace {
+
+// Host-side validation of prony_build_S, and the plan of the call.
+prony_status_t plan_build_S(prony_handle_t h, const char* who, int d, int n, int m, const double* f,
+                            const double* U, int64_t u_rs, int64_t u_cs, const double* sigma, const double* V,
+                            int64_t v_rs, int64_t v_cs, prony_prec_t prec, unsigned flags, double* S,
+                            PencilPlan& P) {
+    prony_status_t st = check_dn(h, d, n);
+    if (st != PRONY_OK) return st;
+    const std::string w(who);
+    const int64_t N = ipow(n + 1, d);
+    if (m < 1 || m > N) return fail(h, PRONY_EINVAL, w + ": m must be in 1..N");
+    if (m > 32) return fail(h, PRONY_ENOTSUP, w + ": m > 32 is not supported");
+    if (!f || !U || !V || !sigma || !S) return fail(h, PRONY_EINVAL, w + ": null pointer");
+    if (u_rs < 1 || u_cs < 1 || v_rs < 1 || v_cs < 1) return fail(h, PRONY_EINVAL, w + ": strides must be >= 1");
+    if ((N - 1) * u_rs + (m - 1) * u_cs >= (int64_t(1) << 40) || (N - 1) * v_rs + (m - 1) * v_cs >= (int64_t(1) << 40))
+        return fail(h, PRONY_EINVAL, w + ": strides out of range");
+    if (prec != PRONY_FP64 && prec != PRONY_FP32 && prec != PRONY_BF16X3)
+        return fail(h, PRONY_EINVAL, w + ": bad precision");
+    if (flags & ~PRONY_WITH_S0) return fail(h, PRONY_EINVAL, w + ": unknown flag");
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    const bool s0 = (flags & PRONY_WITH_S0) != 0;
+    const size_t ts = prec == PRONY_FP64 ? sizeof(double) : sizeof(float);
+    return make_plan(h, d, n, m, s0, ts, P, tuned_target(h, d, n, m, prec, 0), true, 0, prec == PRONY_BF16X3);
+}
+
+prony_status_t run_build_S(prony_handle_t h, const PencilPlan& P, unsigned char* ws, prony_prec_t prec,
+                           const double* f, const double* U, int64_t u_rs, int64_t u_cs, const double* sigma,
+                           const double* V, int64_t v_rs, int64_t v_cs, double* S) {
+    if (prec == PRONY_FP64) return launch_pencil<double>(h, P, ws, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
+    return launch_pencil<float>(h, P, ws, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
+}
+
+}  // namespace
 }  // namespace prony
 
 using namespace prony;
@@ -1127,33 +1198,14 @@ extern "C" prony_status_t prony_build_S(prony_handle_t h, int d, int n, int m, c
                                         int64_t u_rs, int64_t u_cs, const double* sigma, const double* V,
                                         int64_t v_rs, int64_t v_cs, prony_prec_t prec, unsigned flags, double* S) {
     if (!h) return PRONY_EINVAL;
-    prony_status_t st = check_dn(h, d, n);
+    PencilPlan P;
+    prony_status_t st =
+        plan_build_S(h, "prony_build_S", d, n, m, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, prec, flags, S, P);
     if (st != PRONY_OK) return st;
-    const int64_t N = ipow(n + 1, d);
-    if (m < 1 || m > N) return fail(h, PRONY_EINVAL, "prony_build_S: m must be in 1..N");
-    if (m > 32) return fail(h, PRONY_ENOTSUP, "prony_build_S: m > 32 is not supported");
-    if (!f || !U || !V || !sigma || !S) return fail(h, PRONY_EINVAL, "prony_build_S: null pointer");
-    if (u_rs < 1 || u_cs < 1 || v_rs < 1 || v_cs < 1)
-        return fail(h, PRONY_EINVAL, "prony_build_S: strides must be >= 1");
-    if ((N - 1) * u_rs + (m - 1) * u_cs >= (int64_t(1) << 40) || (N - 1) * v_rs + (m - 1) * v_cs >= (int64_t(1) << 40))
-        return fail(h, PRONY_EINVAL, "prony_build_S: strides out of range");
-    if (prec != PRONY_FP64 && prec != PRONY_FP32 && prec != PRONY_BF16X3)
-        return fail(h, PRONY_EINVAL, "prony_build_S: bad precision");
-    if (flags & ~PRONY_WITH_S0) return fail(h, PRONY_EINVAL, "prony_build_S: unknown flag");
-    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
-    const bool s0 = (flags & PRONY_WITH_S0) != 0;
-    PencilPlan P;
-    if (prec == PRONY_FP32 || prec == PRONY_BF16X3) {
-        if ((st = make_plan(h, d, n, m, s0, sizeof(float), P, tuned_target(h, d, n, m, prec, 0), true, 0,
-                            prec == PRONY_BF16X3)) != PRONY_OK)
-            return st;
-        return launch_pencil<float>(h, P, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
-    }
-    if ((st = make_plan(h, d, n, m, s0, sizeof(double), P, tuned_target(h, d, n, m, prec, 0), true)) != PRONY_OK)
-        return st;
-    return launch_pencil<double>(h, P, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
+    if ((st = ensure_workspace(h, P.ws_bytes)) != PRONY_OK) return st;
+    return run_build_S(h, P, static_cast<unsigned char*>(h->ws), prec, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
 }
 
 extern "C" prony_status_t prony_reserve(prony_handle_t h, int d_max, int n_max, int m_max) {
@@ -1164,15 +1216,19 @@ extern "C" prony_status_t prony_reserve(prony_handle_t h, int d_max, int n_max, 
     if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    // The plans are sized at the largest m; over n, the largest plans come from the
+    // top of the range (the operands grow with n, the partial sums with the target),
+    // so the last 16 values of n are planned.
     size_t need = 0;
-    for (int d = 1; d <= d_max; ++d) {
-        const int m = std::min<int64_t>(m_max, ipow(n_max + 1, d));
-        if (m <= 32) {
-            need = std::max(need, pencil_workspace_bytes(h, d, n_max, m));
-            need = std::max(need, adjoint_workspace_bytes(h, d, n_max, m));
+    for (int d = 1; d <= d_max; ++d)
+        for (int n = std::max(1, n_max - 15); n <= n_max; ++n) {
+            const int m = (int)std::min<int64_t>(m_max, ipow(n + 1, d));
+            if (m <= 32) {
+                need = std::max(need, pencil_workspace_bytes(h, d, n, m));
+                need = std::max(need, adjoint_workspace_bytes(h, d, n, m));
+            }
+            need = std::max(need, coeffs_workspace_bytes(d, n, m));
         }
-        need = std::max(need, coeffs_workspace_bytes(d, n_max, m));
-    }
     return ensure_workspace(h, need);
 }
 
@@ -1199,8 +1255,9 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         if (!x.f || !x.U || !x.sigma || !x.V || !x.S) return fail(h, PRONY_EINVAL, who + "null pointer");
         // batch members: split into the tuned number of chunks (default 1)
         const int chunks = tuned_target(h, x.d, x.n, x.m, sizeof(T) == 4 ? PRONY_FP32 : PRONY_FP64, 1);
-        const int rf = rf2_supported(sizeof(T), (2 * x.d * x.m + 15) / 16) && N > kRowsPerTile ? 2 : 1;
-        const int rt = (int)((N + kRowsPerTile * rf - 1) / (kRowsPerTile * rf));
+        const int64_t NR = ipow(x.n + 2, x.d);
+        const int rf = rf2_supported(sizeof(T), (2 * x.m + 15) / 16) && NR > kRowsPerTile ? 2 : 1;
+        const int rt = (int)((NR + kRowsPerTile * rf - 1) / (kRowsPerTile * rf));
         prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], std::max(1, chunks) * rt, true);
         if (st != PRONY_OK) return fail(h, st, who + h->err);
     }
@@ -1218,20 +1275,14 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     for (int i = 0; i < count; ++i) nitems += (size_t)plans[i].nwg;
     if (nitems > (size_t)INT32_MAX) return fail(h, PRONY_ENOTSUP, "prony_batch_create: too many tiles");
     // workspace layout: entries, queue counter, work items, then per instance vp | up | gt | part
-    const size_t t2 = 2 * sizeof(T);
     const size_t off_counter = align_up(sizeof(BatchEntry<T>) * (size_t)count, 256);
     const size_t off_items = off_counter + 256;
     size_t off = align_up(off_items + sizeof(WorkItem) * nitems, 256);
     std::vector<BatchEntry<T>> host(count);
     std::vector<size_t> base(count);
     for (int pos = 0; pos < count; ++pos) {
-        const PencilPlan& P = plans[order[pos]];
         base[pos] = off;
-        const size_t tot = (size_t)P.m * P.C;
-        off = align_up(off + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
-        off = align_up(off + t2 * (size_t)P.rt * P.rows * P.mbi * 16, 256);
-        off = align_up(off + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
-        off = align_up(off + t2 * (size_t)P.nwg * tot, 256);
+        off += plans[order[pos]].ws_bytes;
     }
     void* ws = nullptr;
     hipError_t e = hipMalloc(&ws, off);
@@ -1248,18 +1299,14 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         const int i = order[pos];
         const PencilPlan& P = plans[i];
         const prony_instance_t& x = inst[i];
-        const size_t tot = (size_t)P.m * P.C;
-        size_t o = base[pos];
+        unsigned char* o = w + base[pos];
         BatchEntry<T>& E = host[pos];
         E.P = P;
         E.ptr.grid = reinterpret_cast<const double2*>(x.f);
-        E.ptr.vp = reinterpret_cast<const T2*>(w + o);
-        o = align_up(o + t2 * ((size_t)P.sk * P.kc + kPrefetchRows) * P.nrp, 256);
-        E.ptr.up = reinterpret_cast<const T2*>(w + o);
-        o = align_up(o + t2 * (size_t)P.rt * P.rows * P.mbi * 16, 256);
-        E.ptr.gtab = reinterpret_cast<const int*>(w + o);
-        o = align_up(o + 4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
-        E.ptr.part = reinterpret_cast<T2*>(w + o);
+        E.ptr.vp = reinterpret_cast<const T2*>(o + P.off_v);
+        E.ptr.up = reinterpret_cast<const T2*>(o + P.off_u);
+        E.ptr.gtab = reinterpret_cast<const int*>(o + P.off_g);
+        E.ptr.part = reinterpret_cast<T2*>(o + P.off_p);
         E.ptr.sigma = x.sigma;
         E.ptr.S = reinterpret_cast<double2*>(x.S);
         E.U = reinterpret_cast<const double2*>(x.U);
@@ -1277,7 +1324,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         cl.lds = std::max(cl.lds, P.lds_bytes);
         cl.work += (double)P.nwg * P.kc * P.rf * P.nb;
         const int64_t big = std::max<int64_t>(((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp,
-                                              (int64_t)P.rt * P.rows * P.mbi * 16);
+                                              ((int64_t)P.ug + (int64_t)P.rt * P.rows) * P.mbi * 16);
         largest = (int)std::max<int64_t>(largest, (big + 255) / 256);
     }
     B->pack_x = std::min(largest, 64);

@@ -126,9 +126,10 @@ def _check_S(inst, grid, U, s, V, prec, with_s0):
     return got, errs
 
 
-def _every_tuner_target(d, n, m, grid, U, s, V, ref, precs, label):
+def _every_tuner_target(d, n, m, grid, U, s, V, ref, precs, label, tol=None):
     """S under each split target the autotuner chooses from (multiples of the CU
     count), registered explicitly and removed afterwards, plus the default plan."""
+    tol = dict(TOL, **(tol or {}))
     from paper_2012_11430_amd import autotune
     cus = torch.cuda.get_device_properties(DEV).multi_processor_count
     args = (_dev(grid), d, n, _dev(U), _dev(s), _dev(V))
@@ -137,7 +138,7 @@ def _every_tuner_target(d, n, m, grid, U, s, V, ref, precs, label):
             for c in (0,) + tuple(autotune.SINGLE_CANDIDATES):
                 autotune.register(DEV, d, n, m, prec, False, c * cus)
                 got = api.build_S(*args, prec=prec).cpu().numpy()
-                norm, entry = assert_close_per_matrix(got, ref, TOL[prec], f"{label} {prec} target {c} x CUs")
+                norm, entry = assert_close_per_matrix(got, ref, tol[prec], f"{label} {prec} target {c} x CUs")
                 _say(f"  {label} {prec} target {c} x CUs: {norm:.2e} / {entry:.2e}")
         finally:
             autotune.register(DEV, d, n, m, prec, False, 0)
@@ -188,16 +189,21 @@ def _closed_form_factors(t, c, d, n):
 def test_build_S_paper_efficiency_shape(m):
     # The paper's efficiency workload (Sec. 5: d=3, n=20, N=9261, deterministic
     # nodes and coefficients, noise-free) under the default and every tuner target.
-    # m = 5 uses the exact factors of its T (sigma_m / sigma_1 ~ 9e-4). For m >= 10
-    # the exact factors are so ill-conditioned (sigma_m / sigma_1 ~ 3e-12 at m = 20)
-    # that rounding of the inputs alone, amplified by Sigma^{-1}, exceeds any fixed
-    # bound in either precision; those shapes take the paper's sample grid with
-    # random orthonormal U, V and sigma in [0.5, 2], which keeps the S_l parity
-    # bounds meaningful while running exactly the plans the benchmark times.
+    # m = 5 uses the exact factors of its T (sigma_1 / sigma_m ~ 1.1e3). Rounding
+    # the inputs to FP32 (relative error u = 2^-24) perturbs T_l by about u ||T_l||_F,
+    # which Sigma^{-1} turns into an error of S_l of about u ||T_l||_F / sigma_m
+    # (the perturbation bound of Sec. 4): the FP32 and split-bfloat16 tolerance is
+    # that bound relative to ||S_l||_F (3.4e-5 here; the FP64 bound stays 1e-12).
+    # For m >= 10 the exact factors are so ill-conditioned (sigma_m / sigma_1 ~ 3e-12
+    # at m = 20) that this bound exceeds 1 even in FP64; those shapes take the
+    # paper's sample grid with random complex Gaussian U, V and sigma in [0.5, 2],
+    # which keeps the bounds of the well-conditioned configurations while running
+    # exactly the plans the benchmark times.
     d, n = 3, 20
     N = (n + 1) ** d
     t, c = paper_efficiency_inputs(d, m)
     grid = O.samples(t, c, n)
+    tol = None
     if m == 5:
         U, s, V = _closed_form_factors(t, c, d, n)
     else:
@@ -206,7 +212,12 @@ def test_build_S_paper_efficiency_shape(m):
         s = rng.uniform(0.5, 2.0, m)
     _say(f"build_S paper shape d=3 n=20 m={m}")
     ref = O.pencil_matrices(grid, d, n, U, s, V)
-    _every_tuner_target(d, n, m, grid, U, s, V, ref, ["fp64", "fp32", "bf16x3"], f"paper m={m}")
+    if m == 5:
+        fro_T = np.linalg.norm(O.toeplitz(grid, d, n, 0))
+        bound = 2.0 ** -24 * fro_T / s[-1] / min(np.linalg.norm(ref[l]) for l in range(d))
+        _say(f"  FP32 perturbation bound {bound:.2e}")
+        tol = {"fp32": max(TOL["fp32"], bound), "bf16x3": max(TOL["bf16x3"], bound)}
+    _every_tuner_target(d, n, m, grid, U, s, V, ref, ["fp64", "fp32", "bf16x3"], f"paper m={m}", tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
