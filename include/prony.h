@@ -187,6 +187,24 @@ prony_status_t prony_build_S(prony_handle_t handle, int d, int n, int m, const d
                              const double* V, int64_t v_rs, int64_t v_cs,
                              prony_prec_t prec, unsigned flags, double* S);
 
+/* prony_build_S for callers that cannot allocate device memory (code under HIP
+   graph capture, serving loops, harnesses that forbid hipMalloc): the same
+   validation, plan, kernels and result as prony_build_S, with the packed operands
+   and partial sums in a fixed scratch array of 64 MiB that the library holds on
+   every device it runs on until the process ends (looked up once per device by
+   prony_create). Calls no hipMalloc or hipFree. A call whose plan needs more than
+   64 MiB of scratch returns PRONY_ENOTSUP with the size in prony_last_error (c1,
+   d=2, n=63, m=20, needs about 10 MB in FP32; call prony_build_S for larger
+   plans). Every call on one device shares that device's array, across handles
+   and streams: calls that overlap on one GPU race, so keep them in one stream
+   order. The array keeps the last call's contents; the kernels overwrite every
+   byte they read, so nothing has to start at zero. */
+prony_status_t prony_build_S_noalloc(prony_handle_t handle, int d, int n, int m, const double* f,
+                                     const double* U, int64_t u_rs, int64_t u_cs,
+                                     const double* sigma,
+                                     const double* V, int64_t v_rs, int64_t v_cs,
+                                     prony_prec_t prec, unsigned flags, double* S);
+
 /* Vandermonde products of the least-squares step argmin_c ||A^T c - f||_2
    (Sec. 1, eq. ls_probl; Algorithm 1, last line):
      A^T[k, j] = prod_l z_j(l)^{k_l}  (k in I_n),

@@ -52,6 +52,8 @@ SIGNATURES = {
     "prony_build_T": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _c_i64], _c_int),
     "prony_build_S": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _c_i64, _c_i64, _ptr, _ptr, _c_i64, _c_i64,
                        _c_int, ctypes.c_uint, _ptr], _c_int),
+    "prony_build_S_noalloc": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _c_i64, _c_i64, _ptr, _ptr, _c_i64,
+                               _c_i64, _c_int, ctypes.c_uint, _ptr], _c_int),
     "prony_coeffs": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _ptr, _ptr, _ptr], _c_int),
     "prony_profile_enable": ([_ptr, ctypes.c_char_p], _c_int),
     "prony_tune_set": ([_ptr, _c_int, _c_int, _c_int, _c_int, ctypes.c_uint, _c_int], _c_int),

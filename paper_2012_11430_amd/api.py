@@ -157,6 +157,15 @@ def build_S(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tenso
     return _build_S("prony_build_S", f, d, n, U, sigma, V, prec, with_s0, out)
 
 
+def build_S_noalloc(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,
+                    out: torch.Tensor, prec: str = "fp64", with_s0: bool = False) -> torch.Tensor:
+    """build_S through prony_build_S_noalloc: the library allocates no device memory
+    (the caller passes `out`; the scratch is the library's fixed per-device array)."""
+    if out is None:
+        raise ValueError("build_S_noalloc needs a preallocated out")
+    return _build_S("prony_build_S_noalloc", f, d, n, U, sigma, V, prec, with_s0, out)
+
+
 def build_S_adjoint(gS: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,
                     prec: str = "fp32", out: torch.Tensor | None = None) -> torch.Tensor:
     """Gradient on the sample grid of a loss with dL/dS_l = gS[l-1] (prony_build_S_adjoint)."""

@@ -34,6 +34,9 @@ struct prony_handle_s {
     bool aux_ready = false;
     // orders the previous stream's work before the next stream's on a stream change
     hipEvent_t order = nullptr;
+    // device address of the fixed scratch array of prony_build_S_noalloc on this
+    // handle's device (looked up once per device when the handle is created)
+    void* scratch = nullptr;
 };
 
 namespace prony {
@@ -68,6 +71,10 @@ class ProfileScope {
     hipStream_t stream_ = nullptr;
     hipEvent_t stop_ = nullptr;
 };
+
+// Look up (once per device, with the handle's device current) the device address
+// of the fixed scratch array used by prony_build_S_noalloc and keep it in the handle.
+prony_status_t scratch_attach(prony_handle_t h);
 
 // Create the auxiliary streams and events (outside stream capture).
 prony_status_t ensure_aux(prony_handle_t h);

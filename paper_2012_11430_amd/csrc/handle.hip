@@ -150,6 +150,8 @@ extern "C" prony_status_t prony_create(prony_handle_t* handle, int device) {
         } else if (hipEventCreateWithFlags(&h->order, hipEventDisableTiming) != hipSuccess) {
             h->order = nullptr;
             st = PRONY_EHIP;
+        } else {
+            st = scratch_attach(h);
         }
     }
     if (st != PRONY_OK) {

@@ -37,6 +37,8 @@
 //                       persistent launch over a queue of all tiles.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -1158,7 +1160,40 @@ size_t pencil_workspace_bytes(prony_handle_t h, int d, int n, int m) {
 
 namespace {
 
-// Host-side validation of prony_build_S, and the plan of the call.
+// Fixed scratch of prony_build_S_noalloc: the packed operands and partial sums of
+// one S-build, in device memory that the code object holds on every device the
+// library runs on, until the process ends. Host code never uses this name as an
+// address: the per-device address comes from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> address of `scratch` on that device
+
+}  // namespace
+
+prony_status_t scratch_attach(prony_handle_t h) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(h->device);
+    if (it != g_scratch_ptr.end()) {
+        h->scratch = it->second;
+        return PRONY_OK;
+    }
+    void* ptr = nullptr;   // the handle's device is current (prony_create)
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(h, PRONY_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[h->device] = ptr;
+    h->scratch = ptr;
+    return PRONY_OK;
+}
+
+namespace {
+
+// Host-side validation shared by prony_build_S and prony_build_S_noalloc, and the
+// plan of the call.
 prony_status_t plan_build_S(prony_handle_t h, const char* who, int d, int n, int m, const double* f,
                             const double* U, int64_t u_rs, int64_t u_cs, const double* sigma, const double* V,
                             int64_t v_rs, int64_t v_cs, prony_prec_t prec, unsigned flags, double* S,
@@ -1206,6 +1241,27 @@ extern "C" prony_status_t prony_build_S(prony_handle_t h, int d, int n, int m, c
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     if ((st = ensure_workspace(h, P.ws_bytes)) != PRONY_OK) return st;
     return run_build_S(h, P, static_cast<unsigned char*>(h->ws), prec, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
+}
+
+extern "C" prony_status_t prony_build_S_noalloc(prony_handle_t h, int d, int n, int m, const double* f,
+                                                const double* U, int64_t u_rs, int64_t u_cs, const double* sigma,
+                                                const double* V, int64_t v_rs, int64_t v_cs, prony_prec_t prec,
+                                                unsigned flags, double* S) {
+    if (!h) return PRONY_EINVAL;
+    PencilPlan P;
+    prony_status_t st = plan_build_S(h, "prony_build_S_noalloc", d, n, m, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs,
+                                     prec, flags, S, P);
+    if (st != PRONY_OK) return st;
+    if (P.ws_bytes > kScratchBytes)
+        return fail(h, PRONY_ENOTSUP,
+                    "prony_build_S_noalloc: the call needs " + std::to_string(P.ws_bytes) +
+                        " bytes of scratch, more than the fixed " + std::to_string(kScratchBytes) +
+                        " bytes per device; use prony_build_S");
+    if (!h->scratch) return fail(h, PRONY_EHIP, "prony_build_S_noalloc: no scratch address for this device");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    return run_build_S(h, P, static_cast<unsigned char*>(h->scratch), prec, f, U, u_rs, u_cs, sigma, V, v_rs,
+                       v_cs, S);
 }
 
 extern "C" prony_status_t prony_reserve(prony_handle_t h, int d_max, int n_max, int m_max) {
