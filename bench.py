@@ -142,7 +142,8 @@ def main():
     if not args.no_tune:
         for prec in ("fp32", "fp64", "bf16x3"):
             times = autotune.tune_single(dev, d, n, m, prec, reps=20)
-            tuned[prec] = min(times, key=times.get)
+            frag, target = min(times, key=times.get)
+            tuned[prec] = {"fragments": frag, "target_wgs": target, "plans_timed": len(times)}
     else:
         tuned["cache_entries_loaded"] = autotune.load_cache(dev)
 
@@ -232,10 +233,11 @@ def main():
         over its average launch time (HIP events); HBM bytes per launch from the stored
         counters of the same code, workload, precision and split target (the partial
         rows written depend on the plan), else null."""
-        target = autotune.registered(dev, d, n, m, prec, False) or 4 * cus
+        p = autotune.plan(dev, d, n, m, prec)
+        plan_key = f"{p['fragments']}x{p['workgroups']}"
         traffic = None
         if traffic_rec.get("source_digest") == source_digest() and traffic_rec.get("workload") == args.workload:
-            traffic = traffic_rec.get("entries", {}).get(prec, {}).get(str(target), {}).get("hbm_bytes_per_launch")
+            traffic = traffic_rec.get("entries", {}).get(prec, {}).get(plan_key, {}).get("hbm_bytes_per_launch")
         achieved = tile_flops(d, n, m) / (avg_ms * 1e-3) / 1e12
         return {
             "bound": "mfma",
@@ -250,7 +252,7 @@ def main():
             "launches_timed": nlaunch,
             "flops_per_launch": tile_flops(d, n, m),
             "fs_equivalent_tflops": round(F / (avg_ms * 1e-3) / 1e12, 3),
-            "split_target_wgs": target,
+            "plan": {"fragments_per_wave": p["fragments"], "workgroups": p["workgroups"], "h_per_chunk": p["chunk"]},
         }
 
     result = {
@@ -277,7 +279,7 @@ def main():
                       for p in ("fp64", "fp32", "bf16x3")},
         "s_build": sbuild,
         "build_T": build_T,
-        "tuned_split_targets": tuned,
+        "tuned_tiles": tuned,
         "wall_s_timed": round(wall, 4),
     }
     if not args.no_extra:
@@ -463,7 +465,7 @@ def noise_sweep_c2(dev, args, per_call_ms):
                         "fs_equivalent_tflops": round(s_flops(d, N, m) / (ms * 1e-3) / 1e12, 2),
                         "tiles_ms": round(tiles, 5), "tiles_own_work_tflops": round(own / (tiles * 1e-3) / 1e12, 2),
                         "tiles_frac_of_peak": round(own / (tiles * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4),
-                        "split_target_wgs": autotune.registered(dev, d, n, m, prec, False) or None}
+                        "plan": autotune.plan(dev, d, n, m, prec)}
     return {"workload": "c2: d=3, n=19, N=8000, m=30, separation 0.08, |c| log-uniform [1e-2, 1]", "levels": rows,
             "s_build": timing, "own_work_flops_per_launch": tile_flops(d, n, m)}
 
@@ -502,8 +504,7 @@ def batched_c3(dev, args):
         own += tile_flops(inst.d, inst.n, inst.m)
     tuned = None
     if not args.no_tune:
-        times = autotune.tune_batch(dev_inst, "fp32", reps=2)
-        tuned = min(times, key=times.get)
+        tuned = autotune.tune_batch(dev_inst, "fp32", reps=2)
     else:
         autotune.load_cache(dev)
     batch = api.Batch(dev_inst, prec="fp32")
@@ -571,7 +572,7 @@ def batched_c3(dev, args):
         "fs_equivalent_tflops_fp32_graph": round(flops / (ms_graph * 1e-3) / 1e12, 3),
         "own_work_tflops_fp32_graph": round(own / (ms_graph * 1e-3) / 1e12, 3),
         "rel_err_fp32_vs_fp64": float(f"{rel:.3e}"),
-        "tuned_chunks_per_instance": tuned,
+        "tuning": tuned,
     }
 
 

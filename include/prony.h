@@ -39,6 +39,7 @@
 #ifndef PRONY_H
 #define PRONY_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -61,10 +62,13 @@ typedef enum {
     PRONY_FP64 = 0,      /* complex128 operands, FP64 MFMA, FP64 accumulation            */
     PRONY_FP32 = 1,      /* complex64 operands, FP32 MFMA with FP32 accumulation per tile,
                             FP64 reduction of the tile partials and FP64 Sigma^{-1}       */
-    PRONY_BF16X3 = 2     /* prony_build_S only: both operands split into three bfloat16
+    PRONY_BF16X3 = 2,    /* prony_build_S only: both operands split into three bfloat16
                             terms (x = h + m + l, 24 significant bits), the six products
                             above 2^-24 on the bf16 MFMA with FP32 accumulation; then as
                             PRONY_FP32. Same error scale as PRONY_FP32.                   */
+    PRONY_PREC_MAX_ENUM = 0x7FFFFFFF  /* not a precision: makes every value 0..2^31-1 a
+                            valid object of this type, so that calls can reject unknown
+                            values with PRONY_EINVAL (negative values are not allowed) */
 } prony_prec_t;
 
 /* Flag of prony_build_S: also form S_0 = U^* T V Sigma^{-1} (equal to I for an
@@ -119,30 +123,55 @@ prony_status_t prony_profile_enable(prony_handle_t handle, const char* kernel);
    their count and the sum of their event-to-event times in milliseconds. */
 prony_status_t prony_profile_read(prony_handle_t handle, int* launches, double* total_ms);
 
-/* Tile selection (filled by the autotuner). prony_build_S splits the extended
-   index range {-1..n}^d of one instance into chunks so that about `target_wgs`
-   workgroups run (default 4 per compute unit). With flag PRONY_TUNE_BATCHED the
-   entry applies to instances of that shape inside batches and gives the number
-   of chunks per instance (default 1: split only as far as the LDS window
-   requires). target_wgs = 0 removes the entry. PRONY_BF16X3 entries exist for
-   single instances only (batches run PRONY_FP32 or PRONY_FP64).
-   Entries live in the handle. */
+/* Tile selection (filled by the autotuner). prony_build_S splits the index range
+   I_n of one instance into chunks so that about `target_wgs` workgroups run
+   (default 4 per compute unit). With flag PRONY_TUNE_BATCHED the entry applies to
+   instances of that shape inside batches and gives the number of chunks per
+   instance (default 1: split only as far as the LDS window requires). With flag
+   PRONY_TUNE_BUCKET the entry applies to every shape of the bucket of (d, n, m):
+   the same d, the same floor(log2 N) and the same column-block count ceil(m/8);
+   an entry of the exact shape takes precedence, field by field. target_wgs = 0
+   removes the target. PRONY_BF16X3 entries exist for single instances only
+   (batches run PRONY_FP32 or PRONY_FP64). Entries live in the handle. */
 #define PRONY_TUNE_BATCHED 1u
+#define PRONY_TUNE_BUCKET 2u
 prony_status_t prony_tune_set(prony_handle_t handle, int d, int n, int m, prony_prec_t prec, unsigned flags,
                               int target_wgs);
 
-/* The registered entry of a shape (0 when none). */
+/* The registered target of a shape's entry (or of its bucket's with
+   PRONY_TUNE_BUCKET; 0 when none). */
 prony_status_t prony_tune_get(prony_handle_t handle, int d, int n, int m, prony_prec_t prec, unsigned flags,
                               int* target_wgs);
 
+/* Tile shape and split target in one entry (flags as for prony_tune_set):
+   `fragments` is the number of 16-row fragments per wave (64 * fragments rows of
+   the product per workgroup): 1, 2 or 4 for single instances, 1 or 2 for batch
+   members (the persistent queue kernel instantiates those), used where the kernel
+   instantiation supports it for the shape's column count (else the default: 2
+   where supported); 0 keeps the default. fragments = target_wgs = 0 removes the
+   entry. Applies to prony_build_S, prony_build_S_noalloc and batches. */
+prony_status_t prony_tune_set_tile(prony_handle_t handle, int d, int n, int m, prony_prec_t prec, unsigned flags,
+                                   int fragments, int target_wgs);
+
+/* The registered tile shape and target of an entry (zeros when none). */
+prony_status_t prony_tune_get_tile(prony_handle_t handle, int d, int n, int m, prony_prec_t prec, unsigned flags,
+                                   int* fragments, int* target_wgs);
+
 /* Register the autotuner's cached entries for this handle's device. The cache is
    the JSON file the Python autotuner writes (paper_2012_11430_amd/autotune.py):
-   {"devices": {"<arch name>:<compute units>": {"d,n,m,prec,mode": target, ...}},
-   "version": 1}, prec fp64 / fp32 / bf16x3, mode single / batch. Entries are
-   registered through prony_tune_set (same validation); a device without entries
-   registers nothing. EINVAL for a missing path, an unreadable file or a malformed
-   entry (entries before it stay registered); ENODEV on a validation-only handle. */
+   {"version": 2, "devices": {"<arch name>:<compute units>": {"<key>": <value>}}}
+   with <key> "d,n,m,prec,mode" or "bucket:d,n,m,prec,mode" (prec fp64 / fp32 /
+   bf16x3, mode single / batch) and <value> the target as an integer or
+   {"target": T, "fragments": F}; version 1 caches (integers) are read too.
+   Entries are registered through prony_tune_set_tile (same validation); a device
+   without entries registers nothing. EINVAL for a missing path, an unreadable
+   file, malformed JSON or a malformed entry (entries before it stay registered);
+   ENODEV on a validation-only handle. */
 prony_status_t prony_autotune(prony_handle_t handle, const char* cache_json_path);
+
+/* The same for the entries stored under an explicit device key (any handle,
+   validation-only handles included). */
+prony_status_t prony_autotune_device(prony_handle_t handle, const char* cache_json_path, const char* device_key);
 
 /* ---- Algorithm 1, GPU steps -------------------------------------------------- */
 
@@ -186,6 +215,15 @@ prony_status_t prony_build_S(prony_handle_t handle, int d, int n, int m, const d
                              const double* sigma,
                              const double* V, int64_t v_rs, int64_t v_cs,
                              prony_prec_t prec, unsigned flags, double* S);
+
+/* The launch plan prony_build_S would use for this call shape under the handle's
+   tuning entries, without launching or allocating anything: 16-row fragments per
+   wave, workgroups of the tile launch, indices h per chunk and the workspace
+   bytes the call needs. Validates like prony_build_S (pointers aside). Works on
+   validation-only handles, which plan for 256 compute units and 160 KiB of LDS
+   per workgroup (the MI355X figures). Any output pointer may be NULL. */
+prony_status_t prony_build_S_plan(prony_handle_t handle, int d, int n, int m, prony_prec_t prec, unsigned flags,
+                                  int* fragments, int* workgroups, int* chunk, size_t* workspace_bytes);
 
 /* prony_build_S for callers that cannot allocate device memory (code under HIP
    graph capture, serving loops, harnesses that forbid hipMalloc): the same

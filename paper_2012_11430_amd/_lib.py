@@ -9,7 +9,9 @@ from __future__ import annotations
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libprony.so")
+# PRONY_LIB selects another build of the same library (the host-sanitizer build of
+# build.py --sanitize); by default the in-tree libprony.so
+LIB_PATH = os.environ.get("PRONY_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libprony.so")
 
 PRONY_OK = 0
 PRONY_EINVAL = 1
@@ -26,6 +28,7 @@ PRONY_FP32 = 1
 PRONY_BF16X3 = 2
 PRONY_WITH_S0 = 1
 PRONY_TUNE_BATCHED = 1
+PRONY_TUNE_BUCKET = 2
 PRONY_SCHEDULE_QUEUE = 0
 PRONY_SCHEDULE_CLASSES = 1
 
@@ -63,6 +66,12 @@ SIGNATURES = {
     "prony_batch_destroy": ([_ptr], _c_int),
     "prony_batch_set_schedule": ([_ptr, _c_int], _c_int),
     "prony_tune_get": ([_ptr, _c_int, _c_int, _c_int, _c_int, ctypes.c_uint, ctypes.POINTER(_c_int)], _c_int),
+    "prony_tune_set_tile": ([_ptr, _c_int, _c_int, _c_int, _c_int, ctypes.c_uint, _c_int, _c_int], _c_int),
+    "prony_tune_get_tile": ([_ptr, _c_int, _c_int, _c_int, _c_int, ctypes.c_uint, ctypes.POINTER(_c_int),
+                             ctypes.POINTER(_c_int)], _c_int),
+    "prony_autotune_device": ([_ptr, ctypes.c_char_p, ctypes.c_char_p], _c_int),
+    "prony_build_S_plan": ([_ptr, _c_int, _c_int, _c_int, _c_int, ctypes.c_uint, ctypes.POINTER(_c_int),
+                            ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_size_t)], _c_int),
     "prony_autotune": ([_ptr, ctypes.c_char_p], _c_int),
     "prony_build_S_batched": ([_ptr, _ptr], _c_int),
     "prony_build_S_adjoint_batched": ([_ptr, _ptr, _ptr, _ptr], _c_int),

@@ -11,16 +11,27 @@
 
 #include "prony.h"
 
+namespace prony {
+// A tuning entry: split target (single instances: workgroups to aim at; batch
+// members: chunks of the h range) and 16-row fragments per wave; 0 = default.
+struct TuneEntry {
+    int target = 0;
+    int fragments = 0;
+};
+// (bucket, d, n or floor(log2 N), m or ceil(m/8), prec, batched)
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+}  // namespace prony
+
 struct prony_handle_s {
     int device = 0;
     hipStream_t stream = nullptr;
     void* ws = nullptr;          // device workspace owned by the handle
     size_t ws_bytes = 0;
-    int num_cus = 256;
-    size_t lds_per_block = 65536;
+    int num_cus = 256;           // MI355X figures for validation-only handles;
+    size_t lds_per_block = 163840;   // device handles read their device's
     std::string err;
-    // tuned split targets: (d, n, m, prec, batched) -> workgroups to aim at
-    std::map<std::tuple<int, int, int, int, int>, int> split_targets;
+    // tuning entries of exact shapes and of shape buckets (see prony_tune_set)
+    std::map<prony::TuneKey, prony::TuneEntry> tune;
     // profiling: events around launches of one named kernel
     std::string prof_kernel;
     std::vector<hipEvent_t> prof_events;   // pool, pairs (start, stop)
@@ -98,6 +109,13 @@ size_t adjoint_workspace_bytes(prony_handle_t h, int d, int n, int m);
 // Adjoint state of a batch (planned on the first batched adjoint call; adjoint.hip).
 struct AdjBatch;
 prony_status_t adj_batch_free(AdjBatch* a);
+
+// Key of a tuning entry: the exact shape, or its bucket (same d, floor(log2 N) and
+// column-block count ceil(m/8)).
+TuneKey tune_key(int d, int n, int m, int prec, bool batched, bool bucket);
+// The entry that applies to a shape: each field from the exact entry, else from
+// the bucket entry (0 when neither has it).
+TuneEntry tuned(prony_handle_t h, int d, int n, int m, int prec, bool batched);
 
 // Common argument validation for (d, n): 1 <= d <= 3, n >= 1, sizes within int32.
 prony_status_t check_dn(prony_handle_t h, int d, int n);

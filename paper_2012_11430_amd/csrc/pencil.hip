@@ -62,9 +62,15 @@ constexpr int kThreads = kWaves * 64;
 constexpr int kDepth = 4;
 constexpr int kPrefetchRows = 4 * kDepth;
 
-// Two 16-row fragments per wave (each B operand feeds twice the MFMAs) while
-// the accumulators of both still fit the register file next to the operand ring.
-constexpr bool rf2_supported(size_t tsize, int nb) { return nb <= (tsize == 4 ? 8 : 5); }
+// 16-row fragments per wave (each B operand feeds RF times the MFMAs) that an
+// instantiation supports: the accumulators of all fragments must fit the register
+// file next to the operand ring. 1 always; 2 up to 8 (FP32) or 5 (FP64) column
+// blocks; 4 up to 4 (FP32, split bfloat16: 2) or 2 (FP64) column blocks.
+constexpr bool rf_supported(size_t tsize, int nb, int rf, bool split = false) {
+    return rf == 1 || (rf == 2 && nb <= (tsize == 4 ? 8 : 5)) ||
+           (rf == 4 && nb <= (split ? 2 : (tsize == 4 ? 4 : 2)));
+}
+constexpr bool rf2_supported(size_t tsize, int nb) { return rf_supported(tsize, nb, 2); }
 
 struct PencilPlan {
     int d, n, N, m;
@@ -806,10 +812,12 @@ PlanBytes plan_bytes(const PencilPlan& P, size_t tsize) {
     return b;
 }
 
-// Registered split target for a shape class (0 if none).
 int tuned_target(prony_handle_t h, int d, int n, int m, int prec, int batched) {
-    auto it = h->split_targets.find(std::make_tuple(d, n, m, prec, batched));
-    return it == h->split_targets.end() ? 0 : it->second;
+    return tuned(h, d, n, m, prec, batched != 0).target;
+}
+
+int tuned_fragments(prony_handle_t h, int d, int n, int m, int prec, int batched) {
+    return tuned(h, d, n, m, prec, batched != 0).fragments;
 }
 
 // target_wgs: workgroups the split of the h' range aims at (single instances
@@ -817,8 +825,11 @@ int tuned_target(prony_handle_t h, int d, int n, int m, int prec, int batched) {
 // beyond what the LDS window imposes).
 // mode 1 plans the product Y = T X of a block of m columns (h over I_n, no
 // shifted copies, no U^* epilogue).
+// rf_req: 16-row fragments per wave; 0 picks 2 where the instantiation allows it
+// (and the product has more than one 64-row tile), 1, 2 or 4 ask for that count
+// (the default when not supported for the column count).
 prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P,
-                         int target_wgs = 0, bool allow_rf2 = false, int mode = 0, bool split = false) {
+                         int target_wgs = 0, int rf_req = 0, int mode = 0, bool split = false) {
     P = PencilPlan{};
     P.d = d;
     P.n = n;
@@ -836,7 +847,8 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.NR = mode ? P.N : (int)ipow(n + 2, d);
     P.ug = mode ? 0 : (int)ipow(n + 2, d - 1);
     P.kb = P.N;
-    P.rf = allow_rf2 && rf2_supported(tsize, P.nb) && P.NR > kRowsPerTile ? 2 : 1;
+    P.rf = rf2_supported(tsize, P.nb) && P.NR > kRowsPerTile ? 2 : 1;
+    if ((rf_req == 1 || rf_req == 2 || rf_req == 4) && rf_supported(tsize, P.nb, rf_req, split)) P.rf = rf_req;
     P.rows = kRowsPerTile * P.rf;
     P.rt = (P.NR + P.rows - 1) / P.rows;
     P.c0 = grid_center(d, n);
@@ -1007,10 +1019,14 @@ prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TileP
     case NBV:                                                              \
         if constexpr (sizeof(T) == 4)                                      \
             if (P.split) {                                                 \
-                if constexpr (rf2_supported(4, NBV))                       \
+                if constexpr (rf_supported(4, NBV, 4, true))               \
+                    if (P.rf == 4) return launch_tiles_split<NBV, 4>(h, P, ptr); \
+                if constexpr (rf_supported(4, NBV, 2, true))               \
                     if (P.rf == 2) return launch_tiles_split<NBV, 2>(h, P, ptr); \
                 return launch_tiles_split<NBV, 1>(h, P, ptr);              \
             }                                                              \
+        if constexpr (rf_supported(sizeof(T), NBV, 4))                     \
+            if (P.rf == 4) return launch_tiles<T, NBV, 4>(h, P, ptr);      \
         if constexpr (rf2_supported(sizeof(T), NBV))                       \
             if (P.rf == 2) return launch_tiles<T, NBV, 2>(h, P, ptr);      \
         return launch_tiles<T, NBV, 1>(h, P, ptr);
@@ -1148,11 +1164,12 @@ size_t pencil_workspace_bytes(prony_handle_t h, int d, int n, int m) {
         const int targets[] = {0, h->num_cus, 2 * h->num_cus, 3 * h->num_cus, 4 * h->num_cus, 8 * h->num_cus,
                                tuned_target(h, d, n, m, prec, 0)};
         for (int s0 = 0; s0 < 2; ++s0)
-            for (int tg : targets) {
-                PencilPlan P;
-                if (make_plan(h, d, n, m, s0 == 1, ts, P, tg, true, 0, prec == PRONY_BF16X3) == PRONY_OK)
-                    best = std::max(best, P.ws_bytes);
-            }
+            for (int tg : targets)
+                for (int rf : {1, 2, 4}) {
+                    PencilPlan P;
+                    if (make_plan(h, d, n, m, s0 == 1, ts, P, tg, rf, 0, prec == PRONY_BF16X3) == PRONY_OK)
+                        best = std::max(best, P.ws_bytes);
+                }
     }
     h->err = saved;
     return best;
@@ -1197,7 +1214,7 @@ namespace {
 prony_status_t plan_build_S(prony_handle_t h, const char* who, int d, int n, int m, const double* f,
                             const double* U, int64_t u_rs, int64_t u_cs, const double* sigma, const double* V,
                             int64_t v_rs, int64_t v_cs, prony_prec_t prec, unsigned flags, double* S,
-                            PencilPlan& P) {
+                            PencilPlan& P, bool plan_only = false) {
     prony_status_t st = check_dn(h, d, n);
     if (st != PRONY_OK) return st;
     const std::string w(who);
@@ -1211,10 +1228,11 @@ prony_status_t plan_build_S(prony_handle_t h, const char* who, int d, int n, int
     if (prec != PRONY_FP64 && prec != PRONY_FP32 && prec != PRONY_BF16X3)
         return fail(h, PRONY_EINVAL, w + ": bad precision");
     if (flags & ~PRONY_WITH_S0) return fail(h, PRONY_EINVAL, w + ": unknown flag");
-    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    if (h->device < 0 && !plan_only) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
     const bool s0 = (flags & PRONY_WITH_S0) != 0;
     const size_t ts = prec == PRONY_FP64 ? sizeof(double) : sizeof(float);
-    return make_plan(h, d, n, m, s0, ts, P, tuned_target(h, d, n, m, prec, 0), true, 0, prec == PRONY_BF16X3);
+    return make_plan(h, d, n, m, s0, ts, P, tuned_target(h, d, n, m, prec, 0), tuned_fragments(h, d, n, m, prec, 0),
+                     0, prec == PRONY_BF16X3);
 }
 
 prony_status_t run_build_S(prony_handle_t h, const PencilPlan& P, unsigned char* ws, prony_prec_t prec,
@@ -1241,6 +1259,22 @@ extern "C" prony_status_t prony_build_S(prony_handle_t h, int d, int n, int m, c
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     if ((st = ensure_workspace(h, P.ws_bytes)) != PRONY_OK) return st;
     return run_build_S(h, P, static_cast<unsigned char*>(h->ws), prec, f, U, u_rs, u_cs, sigma, V, v_rs, v_cs, S);
+}
+
+extern "C" prony_status_t prony_build_S_plan(prony_handle_t h, int d, int n, int m, prony_prec_t prec, unsigned flags,
+                                             int* fragments, int* workgroups, int* chunk, size_t* workspace_bytes) {
+    if (!h) return PRONY_EINVAL;
+    // the plan does not read the arrays: stand-in pointers pass the null checks
+    static const double dummy[2] = {0.0, 0.0};
+    PencilPlan P;
+    const prony_status_t st = plan_build_S(h, "prony_build_S_plan", d, n, m, dummy, dummy, 1, 1, dummy, dummy, 1, 1,
+                                           prec, flags, const_cast<double*>(dummy), P, true);
+    if (st != PRONY_OK) return st;
+    if (fragments) *fragments = P.rf;
+    if (workgroups) *workgroups = P.nwg;
+    if (chunk) *chunk = P.kc;
+    if (workspace_bytes) *workspace_bytes = P.ws_bytes;
+    return PRONY_OK;
 }
 
 extern "C" prony_status_t prony_build_S_noalloc(prony_handle_t h, int d, int n, int m, const double* f,
@@ -1310,11 +1344,12 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         if (x.m > 32) return fail(h, PRONY_ENOTSUP, who + "m > 32 is not supported");
         if (!x.f || !x.U || !x.sigma || !x.V || !x.S) return fail(h, PRONY_EINVAL, who + "null pointer");
         // batch members: split into the tuned number of chunks (default 1)
-        const int chunks = tuned_target(h, x.d, x.n, x.m, sizeof(T) == 4 ? PRONY_FP32 : PRONY_FP64, 1);
+        const TuneEntry te = tuned(h, x.d, x.n, x.m, sizeof(T) == 4 ? PRONY_FP32 : PRONY_FP64, true);
         const int64_t NR = ipow(x.n + 2, x.d);
-        const int rf = rf2_supported(sizeof(T), (2 * x.m + 15) / 16) && NR > kRowsPerTile ? 2 : 1;
+        int rf = rf2_supported(sizeof(T), (2 * x.m + 15) / 16) && NR > kRowsPerTile ? 2 : 1;
+        if (te.fragments == 1 || (te.fragments == 2 && rf2_supported(sizeof(T), (2 * x.m + 15) / 16))) rf = te.fragments;
         const int rt = (int)((NR + kRowsPerTile * rf - 1) / (kRowsPerTile * rf));
-        prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], std::max(1, chunks) * rt, true);
+        prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], std::max(1, te.target) * rt, rf);
         if (st != PRONY_OK) return fail(h, st, who + h->err);
     }
     // classes by (column-block count, row fragments); inside a class, longest tiles first
@@ -1401,8 +1436,8 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     B->queue_lds = 0;
     for (int pos = 0; pos < count; ++pos) B->queue_lds = std::max(B->queue_lds, host[pos].P.lds_bytes);
     // resident workgroups per CU: LDS (dynamic + the kernel's 16 static bytes), and
-    // at most 2 (the kernel's registers allow 2 waves per SIMD)
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, h->lds_per_block / (B->queue_lds + 16)));
+    // at most 3 (the kernel's 134 registers allow 3 waves per SIMD)
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(3, h->lds_per_block / (B->queue_lds + 16)));
     B->queue_grid = (int)std::min<size_t>(nitems, (size_t)per_cu * h->num_cus);
     // several classes: one persistent launch over all of them; one class is one
     // launch already, and its own kernel keeps more workgroups resident
@@ -1623,20 +1658,62 @@ extern "C" prony_status_t prony_graph_destroy(void* graph_exec) {
     return hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec)) == hipSuccess ? PRONY_OK : PRONY_EHIP;
 }
 
+namespace prony {
+
+TuneKey tune_key(int d, int n, int m, int prec, bool batched, bool bucket) {
+    if (!bucket) return std::make_tuple(0, d, n, m, prec, batched ? 1 : 0);
+    const int64_t N = ipow(n + 1, d);
+    int lg = 0;
+    while ((int64_t(2) << lg) <= N) ++lg;   // floor(log2 N)
+    return std::make_tuple(1, d, lg, (m + 7) / 8, prec, batched ? 1 : 0);
+}
+
+TuneEntry tuned(prony_handle_t h, int d, int n, int m, int prec, bool batched) {
+    TuneEntry e;
+    const auto it = h->tune.find(tune_key(d, n, m, prec, batched, false));
+    if (it != h->tune.end()) e = it->second;
+    if (e.target == 0 || e.fragments == 0) {
+        const auto jt = h->tune.find(tune_key(d, n, m, prec, batched, true));
+        if (jt != h->tune.end()) {
+            if (e.target == 0) e.target = jt->second.target;
+            if (e.fragments == 0) e.fragments = jt->second.fragments;
+        }
+    }
+    return e;
+}
+
+}  // namespace prony
+
+extern "C" prony_status_t prony_tune_set_tile(prony_handle_t h, int d, int n, int m, prony_prec_t prec, unsigned flags,
+                                              int fragments, int target_wgs) {
+    if (!h) return PRONY_EINVAL;
+    if (d < 1 || d > 3 || n < 1 || m < 1 || m > 32) return fail(h, PRONY_EINVAL, "prony_tune_set: bad shape");
+    if (ipow(2 * (int64_t)n + 2, d) > (int64_t(1) << 30)) return fail(h, PRONY_EINVAL, "prony_tune_set: bad shape");
+    if (flags & ~(PRONY_TUNE_BATCHED | PRONY_TUNE_BUCKET)) return fail(h, PRONY_EINVAL, "prony_tune_set: unknown flag");
+    const bool batched = (flags & PRONY_TUNE_BATCHED) != 0;
+    if (prec != PRONY_FP64 && prec != PRONY_FP32 && !(prec == PRONY_BF16X3 && !batched))
+        return fail(h, PRONY_EINVAL, "prony_tune_set: bad precision");
+    if (target_wgs < 0 || target_wgs > (1 << 20)) return fail(h, PRONY_EINVAL, "prony_tune_set: bad target");
+    if (!(fragments == 0 || fragments == 1 || fragments == 2 || (fragments == 4 && !batched)))
+        return fail(h, PRONY_EINVAL, "prony_tune_set_tile: fragments must be 0, 1, 2 or 4 (batch members: 0, 1, 2)");
+    const TuneKey key = tune_key(d, n, m, (int)prec, batched, (flags & PRONY_TUNE_BUCKET) != 0);
+    if (target_wgs == 0 && fragments == 0)
+        h->tune.erase(key);
+    else
+        h->tune[key] = TuneEntry{target_wgs, fragments};
+    return PRONY_OK;
+}
+
 extern "C" prony_status_t prony_tune_set(prony_handle_t h, int d, int n, int m, prony_prec_t prec, unsigned flags,
                                          int target_wgs) {
     if (!h) return PRONY_EINVAL;
-    if (d < 1 || d > 3 || n < 1 || m < 1 || m > 32) return fail(h, PRONY_EINVAL, "prony_tune_set: bad shape");
-    if (prec != PRONY_FP64 && prec != PRONY_FP32 && !(prec == PRONY_BF16X3 && flags == 0))
-        return fail(h, PRONY_EINVAL, "prony_tune_set: bad precision");
-    if (flags & ~PRONY_TUNE_BATCHED) return fail(h, PRONY_EINVAL, "prony_tune_set: unknown flag");
-    if (target_wgs < 0 || target_wgs > (1 << 20)) return fail(h, PRONY_EINVAL, "prony_tune_set: bad target");
-    const auto key = std::make_tuple(d, n, m, (int)prec, (flags & PRONY_TUNE_BATCHED) ? 1 : 0);
-    if (target_wgs == 0)
-        h->split_targets.erase(key);
-    else
-        h->split_targets[key] = target_wgs;
-    return PRONY_OK;
+    int fragments = 0;
+    if (d >= 1 && d <= 3 && n >= 1 && m >= 1 && ipow(2 * (int64_t)n + 2, d) <= (int64_t(1) << 30)) {
+        const auto it = h->tune.find(tune_key(d, n, m, (int)prec, (flags & PRONY_TUNE_BATCHED) != 0,
+                                              (flags & PRONY_TUNE_BUCKET) != 0));
+        if (it != h->tune.end()) fragments = it->second.fragments;   // keep the entry's tile shape
+    }
+    return prony_tune_set_tile(h, d, n, m, prec, flags, fragments, target_wgs);
 }
 
 extern "C" prony_status_t prony_toeplitz_mm(prony_handle_t h, int d, int n, int adjoint, const double* f, int r,
@@ -1658,7 +1735,7 @@ extern "C" prony_status_t prony_toeplitz_mm(prony_handle_t h, int d, int n, int 
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     PencilPlan P;
     const size_t ts = prec == PRONY_FP32 ? sizeof(float) : sizeof(double);
-    if ((st = make_plan(h, d, n, r, false, ts, P, 0, true, 1)) != PRONY_OK) return st;
+    if ((st = make_plan(h, d, n, r, false, ts, P, 0, 0, 1)) != PRONY_OK) return st;
     P.conj_grid = adjoint;
     return prec == PRONY_FP32 ? launch_toeplitz_mm<float>(h, P, f, X, ldx, Y, ldy)
                               : launch_toeplitz_mm<double>(h, P, f, X, ldx, Y, ldy);

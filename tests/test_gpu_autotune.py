@@ -1,5 +1,7 @@
-"""Autotuner: candidates are timed, the winner is registered and cached, the
-cache reloads in a fresh handle entry, and tuned plans stay correct."""
+"""Autotuner: candidate tile shapes and split targets are timed (distinct plans
+only), the winner is registered and cached, the cache reloads through the Python
+and the library's own loader, bucket entries tune batches, and every tuned plan
+stays correct against the oracle."""
 import json
 
 import numpy as np
@@ -8,6 +10,7 @@ import torch
 
 from oracle import prony_oracle as O
 from paper_2012_11430_amd import api, autotune
+from tests._close import assert_close_per_matrix
 
 pytestmark = pytest.mark.gpu
 
@@ -22,18 +25,25 @@ def _dev(x):
 def test_tune_single_registers_caches_and_stays_correct(tmp_path, prec):
     path = str(tmp_path / "tune.json")
     d, n, m = 2, 31, 12
-    times = autotune.tune_single(DEV, d, n, m, prec, reps=3, path=path)
-    assert len(times) == len(autotune.SINGLE_CANDIDATES) and all(t > 0 for t in times.values())
+    times = autotune.tune_single(DEV, d, n, m, prec, reps=3, path=path, bucket=True)
+    assert 2 <= len(times) <= len(autotune.SINGLE_CANDIDATES) * len(autotune.SINGLE_FRAGMENTS)
+    assert all(t > 0 for t in times.values())
     data = json.load(open(path))
+    assert data["version"] == 2
     entries = next(iter(data["devices"].values()))
-    assert entries[f"{d},{n},{m},{prec},single"] in times
-    # the library's own loader (prony_autotune) reads the same cache
     best = entries[f"{d},{n},{m},{prec},single"]
-    autotune.register(DEV, d, n, m, prec, False, 0)
-    assert autotune.registered(DEV, d, n, m, prec, False) == 0
+    assert (best["fragments"], best["target"]) in times
+    assert entries[f"bucket:{d},{n},{m},{prec},single"] == best
+    # the library's own loader (prony_autotune) reads the same cache
+    autotune.register(DEV, d, n, m, prec, False, 0, 0)
+    autotune.register(DEV, d, n, m, prec, False, 0, 0, bucket=True)
+    assert autotune.registered_tile(DEV, d, n, m, prec, False) == (0, 0)
     autotune.load_cache_native(DEV, path)
-    assert autotune.registered(DEV, d, n, m, prec, False) == best
-    assert autotune.load_cache(DEV, path) == 1
+    assert autotune.registered_tile(DEV, d, n, m, prec, False) == (best["fragments"], best["target"])
+    assert autotune.registered_tile(DEV, d, n, m, prec, False, bucket=True) == (best["fragments"], best["target"])
+    assert autotune.load_cache(DEV, path) == 2
+    assert autotune.plan(DEV, d, n, m, prec)["fragments"] == best["fragments"]
+    autotune.register(DEV, d, n, m, prec, False, 0, 0, bucket=True)
     rng = np.random.Generator(np.random.PCG64(5))
     N = (n + 1) ** d
     grid = rng.standard_normal((2 * n + 2) ** d) + 1j * rng.standard_normal((2 * n + 2) ** d)
@@ -41,11 +51,12 @@ def test_tune_single_registers_caches_and_stays_correct(tmp_path, prec):
     V = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
     s = rng.uniform(0.5, 2, m)
     ref = O.pencil_matrices(grid, d, n, U, s, V)
-    for target in (256, 2048):      # plans at both ends of the candidate range
-        autotune.register(DEV, d, n, m, prec, False, target)
-        got = api.build_S(_dev(grid), d, n, _dev(U), _dev(s), _dev(V), prec=prec).cpu().numpy()
-        assert max(np.linalg.norm(got[l] - ref[l]) / np.linalg.norm(ref[l]) for l in range(d)) <= 1e-5
-    autotune.register(DEV, d, n, m, prec, False, 0)
+    for frag in autotune.SINGLE_FRAGMENTS:
+        for target in (256, 2048):      # plans at both ends of the candidate range
+            autotune.register(DEV, d, n, m, prec, False, target, frag)
+            got = api.build_S(_dev(grid), d, n, _dev(U), _dev(s), _dev(V), prec=prec).cpu().numpy()
+            assert_close_per_matrix(got, ref, 1e-5, f"{prec} fragments {frag} target {target}")
+    autotune.register(DEV, d, n, m, prec, False, 0, 0)
 
 
 def test_tune_batch(tmp_path):
@@ -61,18 +72,25 @@ def test_tune_batch(tmp_path):
         s = rng.uniform(0.5, 2, m)
         inst.append((d, n, _dev(grid), _dev(U), _dev(s), _dev(V)))
         refs.append(O.pencil_matrices(grid, d, n, U, s, V))
-    times = autotune.tune_batch(inst, "fp32", reps=2, path=path)
-    assert set(times) == set(autotune.BATCH_CANDIDATES)
+    res = autotune.tune_batch(inst, "fp32", reps=2, path=path)
+    assert res["tuned_ms"] <= res["default_ms"] and res["timed_batches"] >= 1
+    assert set(res["buckets"]) == {",".join(map(str, autotune.bucket_of(d, n, U.shape[1])))
+                                   for d, n, f, U, s, V in inst}
+    entries = next(iter(json.load(open(path))["devices"].values()))
+    assert all(k.startswith("bucket:") and k.endswith(",fp32,batch") for k in entries)
+    # every (chunks, fragments) pair registered for the buckets stays correct
     for chunks in autotune.BATCH_CANDIDATES:
-        for d, n, f, U, s, V in inst:
-            autotune.register(DEV, d, n, U.shape[1], "fp32", True, chunks)
-        b = api.Batch(inst, prec="fp32")
-        b.run()
-        torch.cuda.synchronize()
-        for S, ref in zip(b.S, refs):
-            got = S.cpu().numpy()
-            assert max(np.linalg.norm(got[l] - ref[l]) / np.linalg.norm(ref[l]) for l in range(len(ref))) <= 1e-5
-        b.close()
+        for frag in autotune.BATCH_FRAGMENTS:
+            for d, n, f, U, s, V in inst:
+                autotune.register(DEV, d, n, U.shape[1], "fp32", True, chunks, frag, bucket=True)
+            b = api.Batch(inst, prec="fp32")
+            b.run()
+            torch.cuda.synchronize()
+            for S, ref in zip(b.S, refs):
+                assert_close_per_matrix(S.cpu().numpy(), ref, 1e-5, f"batch chunks {chunks} fragments {frag}")
+            b.close()
+    for d, n, f, U, s, V in inst:
+        autotune.register(DEV, d, n, U.shape[1], "fp32", True, 0, 0, bucket=True)
 
 
 def test_native_cache_loader_rejects_malformed_entries(tmp_path):

@@ -95,32 +95,33 @@ def test_full_c3_batch_matches_single_instance_calls():
 
 
 @pytest.mark.parametrize("chunks", [1, 2, 4])
-def test_full_c3_batch_at_every_tuned_chunk_count(chunks):
-    # the FP32 batch the benchmark replays (queue schedule), with each chunk count
-    # the autotuner chooses from registered for every shape, against single FP64
-    # calls (which are themselves pinned to the oracle above)
+@pytest.mark.parametrize("fragments", [1, 2])
+def test_full_c3_batch_at_every_tuned_tile(chunks, fragments):
+    # the FP32 batch the benchmark replays (queue schedule), with each (chunks per
+    # instance, fragments per wave) pair the autotuner chooses from registered for
+    # every shape bucket, against single FP64 calls (pinned to the oracle above)
     from paper_2012_11430_amd import autotune
-    assert chunks in autotune.BATCH_CANDIDATES
+    assert chunks in autotune.BATCH_CANDIDATES and fragments in autotune.BATCH_FRAGMENTS
     inputs = _c3_inputs(512)
     dev_inst = _device_instances(inputs)
     shapes = sorted({(inst.d, inst.n, inst.m) for inst, *_r in inputs})
-    _say(f"full c3 batch, {chunks} chunk(s) per instance")
+    _say(f"full c3 batch, {chunks} chunk(s) per instance, {fragments} fragment(s) per wave")
     singles = [api.build_S(f, d, n, U, s, V, prec="fp64") for d, n, f, U, s, V in dev_inst]
     try:
         for d, n, m in shapes:
-            autotune.register(DEV, d, n, m, "fp32", True, chunks)
+            autotune.register(DEV, d, n, m, "fp32", True, chunks, fragments, bucket=True)
         batch = api.Batch(dev_inst, prec="fp32")
         batch.run()
         torch.cuda.synchronize()
         worst = 0.0
         for i, (a, b) in enumerate(zip(singles, batch.S)):
             worst = max(worst, *assert_close_per_matrix(b.cpu().numpy(), a.cpu().numpy(), TOL["fp32"],
-                                                        f"chunks {chunks} instance {i}"))
+                                                        f"chunks {chunks} fragments {fragments} instance {i}"))
         batch.close()
         _say(f"  worst {worst:.3e}")
     finally:
         for d, n, m in shapes:
-            autotune.register(DEV, d, n, m, "fp32", True, 0)
+            autotune.register(DEV, d, n, m, "fp32", True, 0, 0, bucket=True)
 
 
 def test_queue_schedule_is_bitwise_equal_to_class_launches():

@@ -7,8 +7,9 @@ normwise (||S_l - S_l^oracle||_F / ||S_l^oracle||_F) and entry by entry
 (max |S_l - S_l^oracle| / max |S_l^oracle|), for every l.
 
 Every launch configuration the benchmark times is compared with the oracle here:
-c1 and c2 under each split target the autotuner can register, and the paper's
-own efficiency shape (d=3, n=20, N=9261, m=5..20) under each of them.
+c1 and c2 under each tile shape (fragments per wave) and split target the
+autotuner can register, and the paper's own efficiency shape (d=3, n=20, N=9261,
+m=5..20) under each of them.
 """
 import functools
 import sys
@@ -127,21 +128,29 @@ def _check_S(inst, grid, U, s, V, prec, with_s0):
 
 
 def _every_tuner_target(d, n, m, grid, U, s, V, ref, precs, label, tol=None):
-    """S under each split target the autotuner chooses from (multiples of the CU
-    count), registered explicitly and removed afterwards, plus the default plan."""
-    tol = dict(TOL, **(tol or {}))
+    """S under each tile shape and split target the autotuner chooses from (16-row
+    fragments per wave x multiples of the CU count), registered explicitly and
+    removed afterwards, plus the default plan; every distinct plan is compared."""
     from paper_2012_11430_amd import autotune
+    tol = dict(TOL, **(tol or {}))
     cus = torch.cuda.get_device_properties(DEV).multi_processor_count
     args = (_dev(grid), d, n, _dev(U), _dev(s), _dev(V))
     for prec in precs:
+        seen = set()
         try:
-            for c in (0,) + tuple(autotune.SINGLE_CANDIDATES):
-                autotune.register(DEV, d, n, m, prec, False, c * cus)
-                got = api.build_S(*args, prec=prec).cpu().numpy()
-                norm, entry = assert_close_per_matrix(got, ref, tol[prec], f"{label} {prec} target {c} x CUs")
-                _say(f"  {label} {prec} target {c} x CUs: {norm:.2e} / {entry:.2e}")
+            for frag in (0,) + tuple(autotune.SINGLE_FRAGMENTS):
+                for c in (0,) + tuple(autotune.SINGLE_CANDIDATES):
+                    autotune.register(DEV, d, n, m, prec, False, c * cus, frag)
+                    p = autotune.plan(DEV, d, n, m, prec)
+                    if (p["fragments"], p["workgroups"]) in seen:
+                        continue
+                    seen.add((p["fragments"], p["workgroups"]))
+                    got = api.build_S(*args, prec=prec).cpu().numpy()
+                    what = f"{label} {prec} fragments {p['fragments']} workgroups {p['workgroups']}"
+                    norm, entry = assert_close_per_matrix(got, ref, tol[prec], what)
+                    _say(f"  {what}: {norm:.2e} / {entry:.2e}")
         finally:
-            autotune.register(DEV, d, n, m, prec, False, 0)
+            autotune.register(DEV, d, n, m, prec, False, 0, 0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
@@ -248,6 +257,28 @@ def test_build_S_ragged_random(d, n, m, prec):
     inst = Inst()
     inst.d, inst.n, inst.m = d, n, m
     _check_S(inst, grid, U, s, V, prec, with_s0=(m % 2 == 1))
+
+
+@pytest.mark.parametrize("d,n,m", [(1, 63, 5), (1, 200, 32), (2, 9, 17), (2, 20, 16), (3, 3, 8), (3, 6, 31)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_build_S_ragged_four_fragments(d, n, m, prec):
+    # 256-row workgroups (4 fragments per wave) where the instantiation has them,
+    # with ragged row tiles (one tile holds all (n+2)^d rows for the small shapes)
+    from paper_2012_11430_amd import autotune
+    rng = np.random.Generator(np.random.PCG64(4000 + 1000 * d + 10 * n + m))
+    N, G = (n + 1) ** d, (2 * n + 2) ** d
+    grid = rng.standard_normal(G) + 1j * rng.standard_normal(G)
+    U = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+    V = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+    s = rng.uniform(0.5, 2.0, m)
+    ref = O.pencil_matrices(grid, d, n, U, s, V, with_s0=True)
+    try:
+        autotune.register(DEV, d, n, m, prec, False, 0, 4)
+        frag = autotune.plan(DEV, d, n, m, prec, with_s0=True)["fragments"]
+        got = api.build_S(_dev(grid), d, n, _dev(U), _dev(s), _dev(V), prec=prec, with_s0=True).cpu().numpy()
+        assert_close_per_matrix(got, ref, TOL[prec], f"d={d} n={n} m={m} {prec} fragments {frag}")
+    finally:
+        autotune.register(DEV, d, n, m, prec, False, 0, 0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
