@@ -560,13 +560,21 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         else
             kloop(std::integral_constant<bool, false>{});
     } else {
+    // The prologue issues the ring's first three steps in the order the loop body
+    // issues them (step by step, A then B), pinned by sched_barrier: the wait
+    // counters of the loop header merge this path with the back edge, and an
+    // order that differs there makes the header wait for every load in flight
+    // instead of the oldest step's.
     int4 gc = gq[0];
     load_a(a[0], gc.x);
-    load_a(a[1], gc.y);
-    load_a(a[2], gc.z);
     load_b(b[0], 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(a[1], gc.y);
     load_b(b[1], 1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(a[2], gc.z);
     load_b(b[2], 2);
+    __builtin_amdgcn_sched_barrier(0);
     // sched_barrier keeps the compiler from sinking the prefetches next to their use.
     for (int ks = 0; ks < nks; ks += kDepth) {
         const int4 gn = gq[(ks >> 2) + 1];
