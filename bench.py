@@ -198,6 +198,18 @@ def main():
                         "own_work_tflops": round(tile_flops(d, n, m) / (med * 1e-3) / 1e12, 3),
                         "tiles_ms": round(tot / max(1, nl), 5), "tiles_launches": nl, "calls": len(times)}
         S_out[prec] = Sbuf.cpu().numpy().copy()
+        # the same build with prepared factors (U, V packed once): tile and finishing launches only
+        fac = api.Factors(d, n, Ud, sd, Vd, prec=prec)
+        for _ in range(args.warmup):
+            fac.build_S(f, out=Sbuf)
+        times = per_call_ms(lambda: fac.build_S(f, out=Sbuf), max(20, args.steps))
+        torch.cuda.synchronize()
+        if not np.array_equal(Sbuf.cpu().numpy(), S_out[prec]):
+            raise RuntimeError(f"prepared-factor build differs from build_S ({prec})")
+        fac.close()
+        pmed = float(np.median(times))
+        sbuild[prec]["prepared_factors_ms_median"] = round(pmed, 5)
+        sbuild[prec]["prepared_factors_over_tiles"] = round(pmed / sbuild[prec]["tiles_ms"], 3)
 
     # ---------------- T alone (HBM-write-bound): GB/s against the 8 TB/s peak
     for _ in range(args.warmup):

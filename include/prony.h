@@ -243,6 +243,40 @@ prony_status_t prony_build_S_noalloc(prony_handle_t handle, int d, int n, int m,
                                      const double* V, int64_t v_rs, int64_t v_cs,
                                      prony_prec_t prec, unsigned flags, double* S);
 
+/* Prepared factors: the packed operands of one (U, sigma, V) for S-builds with
+   many sample grids (Sec. 1, eq. generateSl with the factors held fixed, as in
+   the differentiation and noise-sensitivity workloads). prony_build_S packs U
+   and V on every call; prony_factors_create packs them once, on the handle's
+   stream, into a device allocation owned by the factors object, under the plan
+   that is current for (d, n, m, prec, flags) at creation (later tuning entries
+   do not change it). U, sigma and V may be released once the creation's work on
+   the handle's stream has run. Arguments and requirements as for prony_build_S.
+   Allocates device memory: PRONY_ECAPTURE under stream capture, ENODEV on a
+   validation-only handle. */
+typedef struct prony_factors_s* prony_factors_t;
+prony_status_t prony_factors_create(prony_handle_t handle, int d, int n, int m,
+                                    const double* U, int64_t u_rs, int64_t u_cs,
+                                    const double* sigma,
+                                    const double* V, int64_t v_rs, int64_t v_cs,
+                                    prony_prec_t prec, unsigned flags, prony_factors_t* factors);
+
+/* S_l = U^* T_l V Sigma^{-1} for the sample grid f with prepared factors: the
+   tile and finishing launches of prony_build_S only (same kernels, plan and
+   fixed-order sums, so the result is bitwise equal to prony_build_S's under that
+   plan). f and S as for prony_build_S. The partial rows live in the handle's
+   workspace (grown as needed; PRONY_ECAPTURE if it must grow under capture, so
+   call once or prony_reserve before capturing). The factors must belong to the
+   handle's device; builds with one factors object on several streams may run
+   concurrently (the object is only read), as long as each uses its own handle. */
+prony_status_t prony_build_S_factors(prony_handle_t handle, prony_factors_t factors, const double* f, double* S);
+
+/* Shape, precision and flags of prepared factors (any pointer may be NULL). */
+prony_status_t prony_factors_info(prony_factors_t factors, int* d, int* n, int* m, prony_prec_t* prec,
+                                  unsigned* flags);
+
+/* Release prepared factors (hipFree waits for the device's work in flight). */
+prony_status_t prony_factors_destroy(prony_factors_t factors);
+
 /* Vandermonde products of the least-squares step argmin_c ||A^T c - f||_2
    (Sec. 1, eq. ls_probl; Algorithm 1, last line):
      A^T[k, j] = prod_l z_j(l)^{k_l}  (k in I_n),

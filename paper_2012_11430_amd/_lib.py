@@ -57,6 +57,12 @@ SIGNATURES = {
                        _c_int, ctypes.c_uint, _ptr], _c_int),
     "prony_build_S_noalloc": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _c_i64, _c_i64, _ptr, _ptr, _c_i64,
                                _c_i64, _c_int, ctypes.c_uint, _ptr], _c_int),
+    "prony_factors_create": ([_ptr, _c_int, _c_int, _c_int, _ptr, _c_i64, _c_i64, _ptr, _ptr, _c_i64, _c_i64,
+                              _c_int, ctypes.c_uint, ctypes.POINTER(_ptr)], _c_int),
+    "prony_build_S_factors": ([_ptr, _ptr, _ptr, _ptr], _c_int),
+    "prony_factors_info": ([_ptr, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
+                            ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_uint)], _c_int),
+    "prony_factors_destroy": ([_ptr], _c_int),
     "prony_coeffs": ([_ptr, _c_int, _c_int, _c_int, _ptr, _ptr, _ptr, _ptr, _ptr], _c_int),
     "prony_profile_enable": ([_ptr, ctypes.c_char_p], _c_int),
     "prony_tune_set": ([_ptr, _c_int, _c_int, _c_int, _c_int, ctypes.c_uint, _c_int], _c_int),

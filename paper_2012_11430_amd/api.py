@@ -166,6 +166,65 @@ def build_S_noalloc(f: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: tor
     return _build_S("prony_build_S_noalloc", f, d, n, U, sigma, V, prec, with_s0, out)
 
 
+class Factors:
+    """Prepared factors (prony_factors_create): U, sigma and V packed once for
+    S-builds with many sample grids; `build_S(f)` runs only the tile and finishing
+    launches (prony_build_S_factors) and returns what build_S would under the plan
+    current at creation. The packed copy is the factors' own: U, sigma and V may
+    be released afterwards."""
+
+    def __init__(self, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,
+                 prec: str = "fp64", with_s0: bool = False):
+        dev = U.device
+        _require(U, "U", torch.complex128, dev, contiguous=False)
+        _require(V, "V", torch.complex128, dev, contiguous=False)
+        _require(sigma, "sigma", torch.float64, dev)
+        N = (n + 1) ** d
+        if U.dim() != 2 or U.shape[0] != N or V.shape != U.shape:
+            raise ValueError("U and V must be N x m")
+        m = U.shape[1]
+        if sigma.shape != (m,):
+            raise ValueError("sigma must have shape (m,)")
+        if prec not in _S_PRECS:
+            raise ValueError("prec must be 'fp64', 'fp32' or 'bf16x3'")
+        self.d, self.n, self.m, self.prec, self.with_s0 = d, n, m, prec, with_s0
+        self.device = dev
+        self.handle = None
+        out = ctypes.c_void_p()
+        _call("prony_factors_create", dev, d, n, m, _ptr(U), U.stride(0), U.stride(1), _ptr(sigma), _ptr(V),
+              V.stride(0), V.stride(1), _S_PRECS[prec], _lib.PRONY_WITH_S0 if with_s0 else 0, ctypes.byref(out))
+        self.handle = out
+
+    def build_S(self, f: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if self.handle is None:
+            raise ValueError("factors are closed")
+        _require(f, "f", torch.complex128, self.device)
+        if f.numel() != grid_size(self.d, self.n):
+            raise ValueError("f must hold the (2n+2)^d sample grid")
+        ells = self.d + (1 if self.with_s0 else 0)
+        if out is None:
+            out = torch.empty((ells, self.m, self.m), dtype=torch.complex128, device=self.device)
+        else:
+            _require(out, "out", torch.complex128, self.device)
+            if out.shape != (ells, self.m, self.m):
+                raise ValueError("out has the wrong shape")
+        _call("prony_build_S_factors", self.device, self.handle, _ptr(f), _ptr(out))
+        return out
+
+    def close(self) -> None:
+        if self.handle is not None:
+            st = _lib.load().prony_factors_destroy(self.handle)
+            self.handle = None
+            if st != _lib.PRONY_OK:
+                raise _lib.PronyError(st, "prony_factors_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def build_S_adjoint(gS: torch.Tensor, d: int, n: int, U: torch.Tensor, sigma: torch.Tensor, V: torch.Tensor,
                     prec: str = "fp32", out: torch.Tensor | None = None) -> torch.Tensor:
     """Gradient on the sample grid of a loss with dL/dS_l = gS[l-1] (prony_build_S_adjoint)."""

@@ -621,33 +621,38 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // Z[16 f + row(g,r)][16cb+col] (rows relative to the wave's first row).
     // Output column 2c gets Re(U_l^* Z)_c and 2c+1 gets Im: with the partner lane's
     // value y' (column j^1), Re = Ur.Yr + Ui.Yi and Im = Ur.Yi - Ui.Yr.
-    // The U pairs of the first (block, matrix) are requested before the barrier,
-    // so their latency overlaps the other waves' K loops; later ones one item ahead.
+    // Items are the (block, matrix) pairs in block-major order. The U pairs of the
+    // first item are requested before the barrier, so their latency overlaps the
+    // other waves' K loops; later ones one item ahead, into the other of two
+    // register sets. A pass covers as many items as the slabs hold; within it the
+    // loads are unconditional (a pass's last item requests a pair set it does not
+    // use) and the sets alternate in a loop unrolled by two whose body holds no
+    // other memory operation: every path to an item's products then has the same
+    // loads in flight, and the wait counters make it wait for its own pairs only.
     const int mup = P.mbi * 16;
     const T2* ubase = up + (size_t)(P.ug + wrow0) * mup + col;
-    auto load_u = [&](T2 (&u)[RF][4], int ib, int li) {
+    const int items = P.mbi * P.ells;
+    auto load_u = [&](T2 (&u)[RF][4], int it) {
+        it = min(it, items - 1);
+        const int ib = it / P.ells, li = it - ib * P.ells;
         const T2* src = ubase - (size_t)rowext_shift(P, li + P.first_ell) * mup + ib * 16;
 #pragma unroll
         for (int f = 0; f < RF; ++f)
 #pragma unroll
             for (int r = 0; r < 4; ++r) u[f][r] = src[(size_t)(kRowsPerWave * f + M::row(g, r)) * mup];
     };
-    T2 ucur[RF][4];
-    load_u(ucur, 0, 0);
+    T2 ua[RF][4], ub[RF][4];
+    // the K loop's last steps prefetched operands nobody reads; let them land
+    // before the pair registers are written (same reason as at the pass end)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    load_u(ua, 0);
     __syncthreads();   // the window is dead from here on; its bytes become the slabs
 
-    // Every wave writes its block into its own slab (lane-major, conflict free):
-    // virtual 16-column block (l - l0) NB + cb of the pass. A pass holds lpp
-    // matrices (nbp >= NB blocks per wave); after one barrier all threads add the
+    // Every wave writes the blocks of slot q of a pass into its own slab
+    // (lane-major, conflict free): virtual 16-column blocks q NB + cb. A pass holds
+    // ipp items (nbp >= NB blocks per wave); after one barrier all threads add the
     // four slabs in wave order and store the partial pairs of the pass.
-    const T2* slab2 = reinterpret_cast<const T2*>(slab);
-    const int lpp = max(1, P.nbp / NB);
-    const int items = P.mbi * P.ells;
-    for (int it = 0; it < items; ++it) {
-        const int ib = it / P.ells, li = it - ib * P.ells;
-        const int l0 = li - li % lpp;
-        T2 unext[RF][4];
-        if (it + 1 < items) load_u(unext, (it + 1) / P.ells, (it + 1) % P.ells);
+    auto products = [&](const T2 (&u)[RF][4], int q) {
         acc_t e[NB];
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) e[cb] = acc_t{0, 0, 0, 0};
@@ -659,39 +664,51 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                 for (int cb = 0; cb < NB; ++cb) {
                     const T y = acc[f][cb][r];
                     const T ys = swap_lane_pair(y);
-                    e[cb] = M::fma(ucur[f][r].x, y, e[cb]);
-                    e[cb] = M::fma(ucur[f][r].y, odd ? -ys : ys, e[cb]);
+                    e[cb] = M::fma(u[f][r].x, y, e[cb]);
+                    e[cb] = M::fma(u[f][r].y, odd ? -ys : ys, e[cb]);
                 }
             }
-        const int vb0 = (li - l0) * NB;
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) slab[((wave * P.nbp + vb0 + cb) * 4 + r) * 64 + lane] = e[cb][r];
-        if (li + 1 == P.ells || li + 1 - l0 == lpp) {
-            __syncthreads();
-            const int nl = li + 1 - l0;
-            const int rows = min(16, P.m - ib * 16);
-            T2* out = part + (size_t)L * P.m * P.C + (size_t)ib * 16 * P.C + (size_t)l0 * P.m;
-            for (int o = tid; o < rows * nl * P.m; o += kThreads) {
-                const int il = o / (nl * P.m), rem = o - il * (nl * P.m);
-                const int lj = rem / P.m, c = rem - lj * P.m;
-                const int j = 2 * c;   // Re in column j, Im in column j + 1 (lane + 1)
-                const int s0 = ((lj * NB + (j >> 4)) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 + (j & 15);
-                T2 sum = slab2[s0 >> 1];
-                for (int w = 1; w < kWaves; ++w) {
-                    const T2 v = slab2[(s0 + w * P.nbp * 256) >> 1];
-                    sum.x += v.x;
-                    sum.y += v.y;
-                }
-                out[(size_t)il * P.C + lj * P.m + c] = sum;
-            }
-            __syncthreads();   // slabs are rewritten by the next pass
+            for (int r = 0; r < 4; ++r) slab[((wave * P.nbp + q * NB + cb) * 4 + r) * 64 + lane] = e[cb][r];
+    };
+    const T2* slab2 = reinterpret_cast<const T2*>(slab);
+    const int ipp = max(1, P.nbp / NB);
+    T2* out = part + (size_t)L * P.m * P.C;
+    for (int p0 = 0; p0 < items; p0 += ipp) {
+        const int np = min(ipp, items - p0);
+        if (p0 > 0) load_u(ua, p0);
+        for (int q = 0; q < np; q += 2) {
+            load_u(ub, p0 + q + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            products(ua, q);
+            if (q + 1 == np) break;
+            load_u(ua, p0 + q + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            products(ub, q + 1);
         }
-#pragma unroll
-        for (int f = 0; f < RF; ++f)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) ucur[f][r] = unext[f][r];
+        // the pass's last item requested a set it does not use: wait for it here
+        // (vmcnt 0, other counters free), so that no load into those registers is
+        // in flight on the next pass's paths and their wait counters stay exact
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __syncthreads();
+        for (int o = tid; o < np * 16 * P.m; o += kThreads) {
+            const int q = o / (16 * P.m), rem = o - q * (16 * P.m);
+            const int il = rem / P.m, c = rem - il * P.m;
+            const int it = p0 + q, ib = it / P.ells, li = it - ib * P.ells;
+            if (ib * 16 + il >= P.m) continue;
+            const int j = 2 * c;   // Re in column j, Im in column j + 1 (lane + 1)
+            const int s0 = ((q * NB + (j >> 4)) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 + (j & 15);
+            T2 sum = slab2[s0 >> 1];
+            for (int w = 1; w < kWaves; ++w) {
+                const T2 v = slab2[(s0 + w * P.nbp * 256) >> 1];
+                sum.x += v.x;
+                sum.y += v.y;
+            }
+            out[(size_t)(ib * 16 + il) * P.C + li * P.m + c] = sum;
+        }
+        if (p0 + np < items) __syncthreads();   // slabs are rewritten by the next pass
     }
 }
 template <typename T, int NB, int RF>
@@ -863,9 +880,10 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
 
     // two workgroups per CU; the split kernel, which also stages B planes, may
     // take the whole LDS when its window does not fit otherwise. The epilogue's
-    // slabs hold nbp 16-column blocks per wave, at least the NB of one matrix.
+    // slabs hold nbp 16-column blocks per wave: whole items (NB blocks each), at
+    // least one, at most all mbi * ells of them.
     size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
-    P.nbp = std::max(P.nb, std::min(P.ells * P.nb, (int)(budget / (tsize * kWaves * 16 * 16))));
+    P.nbp = P.nb * std::max(1, std::min(P.mbi * P.ells, (int)(budget / (tsize * kWaves * 16 * 16)) / std::max(1, P.nb)));
     P.bbufs = 2;
     const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
@@ -1063,17 +1081,15 @@ prony_status_t dispatch_batched(prony_handle_t h, int nb, int rf, const BatchEnt
 
 // The three launches of one S-build with the packed operands and partial sums in
 // the workspace at `ws` (P.ws_bytes bytes, owned by the caller of this function).
+// Packing launch of one S-build: V pairs (or split planes), U_ext pairs and the
+// G(h) table into the sections of `base` given by the plan's offsets.
 template <typename T>
-prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, unsigned char* ws, const double* f,
-                             const double* U, int64_t u_rs, int64_t u_cs, const double* sigma, const double* V,
-                             int64_t v_rs, int64_t v_cs, double* S) {
+prony_status_t pack_operands(prony_handle_t h, const PencilPlan& P, unsigned char* base, const double* U,
+                             int64_t u_rs, int64_t u_cs, const double* V, int64_t v_rs, int64_t v_cs) {
     using T2 = pair_t<T>;
-    prony_status_t st = PRONY_OK;
-    T2* vp = reinterpret_cast<T2*>(ws + P.off_v);
-    T2* up = reinterpret_cast<T2*>(ws + P.off_u);
-    int* gt = reinterpret_cast<int*>(ws + P.off_g);
-    T2* part = reinterpret_cast<T2*>(ws + P.off_p);
-
+    T2* vp = reinterpret_cast<T2*>(base + P.off_v);
+    T2* up = reinterpret_cast<T2*>(base + P.off_u);
+    int* gt = reinterpret_cast<int*>(base + P.off_g);
     const int64_t kbp = (int64_t)P.sk * P.kc + kPrefetchRows;
     const int64_t largest = std::max<int64_t>(kbp * P.nrp, ((int64_t)P.ug + (int64_t)P.rt * P.rows) * P.mbi * 16);
     const int pack_blocks = (int)std::min<int64_t>((largest + 255) / 256, 2 * (int64_t)h->num_cus);
@@ -1083,10 +1099,20 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, unsigned cha
             P, reinterpret_cast<const double2*>(U), u_rs, u_cs, reinterpret_cast<const double2*>(V), v_rs, v_cs, vp,
             up, gt);
     }
-    if ((st = check_launch(h, "pencil_pack")) != PRONY_OK) return st;
-    const TilePtrs<T> ptr{reinterpret_cast<const double2*>(f), vp, up, gt, part, sigma,
-                          reinterpret_cast<double2*>(S)};
-    st = dispatch_tiles<T>(h, P, ptr);
+    return check_launch(h, "pencil_pack");
+}
+
+// Tile and finishing launches of one S-build over packed operands at `base` (plan
+// offsets) and partial rows at `part`.
+template <typename T>
+prony_status_t launch_tiles_finish(prony_handle_t h, const PencilPlan& P, const unsigned char* base,
+                                   unsigned char* part_bytes, const double* f, const double* sigma, double* S) {
+    using T2 = pair_t<T>;
+    T2* part = reinterpret_cast<T2*>(part_bytes);
+    const TilePtrs<T> ptr{reinterpret_cast<const double2*>(f), reinterpret_cast<const T2*>(base + P.off_v),
+                          reinterpret_cast<const T2*>(base + P.off_u), reinterpret_cast<const int*>(base + P.off_g),
+                          part, sigma, reinterpret_cast<double2*>(S)};
+    prony_status_t st = dispatch_tiles<T>(h, P, ptr);
     if (st != PRONY_OK) return st;
     if ((st = check_launch(h, "pencil_tiles")) != PRONY_OK) return st;
     {
@@ -1096,6 +1122,15 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, unsigned cha
             P, part, sigma, reinterpret_cast<double2*>(S));
     }
     return check_launch(h, "pencil_finish");
+}
+
+template <typename T>
+prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, unsigned char* ws, const double* f,
+                             const double* U, int64_t u_rs, int64_t u_cs, const double* sigma, const double* V,
+                             int64_t v_rs, int64_t v_cs, double* S) {
+    const prony_status_t st = pack_operands<T>(h, P, ws, U, u_rs, u_cs, V, v_rs, v_cs);
+    if (st != PRONY_OK) return st;
+    return launch_tiles_finish<T>(h, P, ws, ws + P.off_p, f, sigma, S);
 }
 
 template <typename T, int NB, int RF>
@@ -1304,6 +1339,107 @@ extern "C" prony_status_t prony_build_S_noalloc(prony_handle_t h, int d, int n, 
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     return run_build_S(h, P, static_cast<unsigned char*>(h->scratch), prec, f, U, u_rs, u_cs, sigma, V, v_rs,
                        v_cs, S);
+}
+
+// Prepared factors: the packed operands of one (U, sigma, V) under the plan that
+// was current at creation, for repeated S-builds with other sample grids.
+struct prony_factors_s {
+    int device = -1;
+    prony_prec_t prec = PRONY_FP64;
+    PencilPlan P{};
+    unsigned char* mem = nullptr;   // packed V | packed U | G table | sigma
+    size_t off_sigma = 0;
+};
+
+extern "C" prony_status_t prony_factors_create(prony_handle_t h, int d, int n, int m, const double* U, int64_t u_rs,
+                                               int64_t u_cs, const double* sigma, const double* V, int64_t v_rs,
+                                               int64_t v_cs, prony_prec_t prec, unsigned flags,
+                                               prony_factors_t* factors) {
+    if (!h) return PRONY_EINVAL;
+    if (!factors) return fail(h, PRONY_EINVAL, "prony_factors_create: null output pointer");
+    *factors = nullptr;
+    // the plan does not read the grid or the output: stand-ins pass the null checks
+    static const double dummy[2] = {0.0, 0.0};
+    PencilPlan P;
+    prony_status_t st = plan_build_S(h, "prony_factors_create", d, n, m, dummy, U, u_rs, u_cs, sigma, V, v_rs, v_cs,
+                                     prec, flags, const_cast<double*>(dummy), P);
+    if (st != PRONY_OK) return st;
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(h->stream, &cs);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(h, PRONY_ECAPTURE, "prony_factors_create allocates device memory; create factors before capture");
+    prony_factors_s* F = new (std::nothrow) prony_factors_s;
+    if (!F) return fail(h, PRONY_ENOMEM, "prony_factors_create: out of host memory");
+    F->device = h->device;
+    F->prec = prec;
+    F->P = P;
+    F->off_sigma = P.off_p;   // the packed sections end where the partial rows would start
+    e = hipMalloc(reinterpret_cast<void**>(&F->mem), F->off_sigma + align_up(sizeof(double) * (size_t)m, 256));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete F;
+        return fail(h, PRONY_ENOMEM, std::string("prony_factors_create: hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    st = prec == PRONY_FP64 ? pack_operands<double>(h, P, F->mem, U, u_rs, u_cs, V, v_rs, v_cs)
+                            : pack_operands<float>(h, P, F->mem, U, u_rs, u_cs, V, v_rs, v_cs);
+    if (st == PRONY_OK) {
+        e = hipMemcpyAsync(F->mem + F->off_sigma, sigma, sizeof(double) * (size_t)m, hipMemcpyDeviceToDevice,
+                           h->stream);
+        if (e != hipSuccess) st = hip_fail(h, e, "hipMemcpyAsync(sigma)");
+    }
+    if (st != PRONY_OK) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(F->mem);
+        delete F;
+        return st;
+    }
+    *factors = F;
+    return PRONY_OK;
+}
+
+extern "C" prony_status_t prony_build_S_factors(prony_handle_t h, prony_factors_t F, const double* f, double* S) {
+    if (!h) return PRONY_EINVAL;
+    if (!F || !f || !S) return fail(h, PRONY_EINVAL, "prony_build_S_factors: null pointer");
+    if (h->device < 0) return fail(h, PRONY_ENODEV, "validation-only handle has no device");
+    if (F->device != h->device)
+        return fail(h, PRONY_EINVAL, "prony_build_S_factors: the factors belong to another device");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
+    const PencilPlan& P = F->P;
+    prony_status_t st = ensure_workspace(h, P.ws_bytes - P.off_p);
+    if (st != PRONY_OK) return st;
+    const double* sigma = reinterpret_cast<const double*>(F->mem + F->off_sigma);
+    unsigned char* part = static_cast<unsigned char*>(h->ws);
+    if (F->prec == PRONY_FP64) return launch_tiles_finish<double>(h, P, F->mem, part, f, sigma, S);
+    return launch_tiles_finish<float>(h, P, F->mem, part, f, sigma, S);
+}
+
+extern "C" prony_status_t prony_factors_info(prony_factors_t F, int* d, int* n, int* m, prony_prec_t* prec,
+                                             unsigned* flags) {
+    if (!F) return PRONY_EINVAL;
+    if (d) *d = F->P.d;
+    if (n) *n = F->P.n;
+    if (m) *m = F->P.m;
+    if (prec) *prec = F->prec;
+    if (flags) *flags = F->P.first_ell == 0 ? PRONY_WITH_S0 : 0u;
+    return PRONY_OK;
+}
+
+extern "C" prony_status_t prony_factors_destroy(prony_factors_t F) {
+    if (!F) return PRONY_EINVAL;
+    prony_status_t st = PRONY_OK;
+    {
+        DeviceGuard g(F->device);
+        if (!g.ok || hipFree(F->mem) != hipSuccess) {
+            (void)hipGetLastError();
+            st = PRONY_EHIP;
+        }
+    }
+    delete F;
+    return st;
 }
 
 extern "C" prony_status_t prony_reserve(prony_handle_t h, int d_max, int n_max, int m_max) {

@@ -350,3 +350,25 @@ def test_planner_over_a_sweep_of_shapes(vhandle):
                         rows = 64 * f
                         assert wgs % -(-((n + 2) ** d) // rows) == 0
                 assert lib.prony_tune_set_tile(h, d, n, m, prec, 0, 0, 0) == _lib.PRONY_OK
+
+
+def test_prepared_factor_validation(vhandle):
+    lib, h = vhandle
+    out = ctypes.c_void_p(0x1234)
+    # valid arguments reach ENODEV (the plan needs no device) and leave the output cleared
+    assert lib.prony_factors_create(h, 2, 15, 5, P, 5, 1, P, P, 5, 1, _lib.PRONY_FP32, 0,
+                                    ctypes.byref(out)) == _lib.PRONY_ENODEV
+    assert not out.value
+    assert lib.prony_factors_create(h, 2, 15, 5, P, 5, 1, P, P, 5, 1, _lib.PRONY_FP32, 0, None) == _lib.PRONY_EINVAL
+    assert lib.prony_factors_create(h, 2, 15, 5, NULL, 5, 1, P, P, 5, 1, _lib.PRONY_FP32, 0,
+                                    ctypes.byref(out)) == _lib.PRONY_EINVAL
+    assert lib.prony_factors_create(h, 2, 15, 40, P, 40, 1, P, P, 40, 1, _lib.PRONY_FP32, 0,
+                                    ctypes.byref(out)) == _lib.PRONY_ENOTSUP
+    assert lib.prony_factors_create(h, 2, 15, 5, P, 5, 1, P, P, 5, 1, 7, 0, ctypes.byref(out)) == _lib.PRONY_EINVAL
+    assert lib.prony_factors_create(h, 2, 15, 5, P, 5, 1, P, P, 5, 1, _lib.PRONY_FP32, 8,
+                                    ctypes.byref(out)) == _lib.PRONY_EINVAL
+    assert "flag" in _err(lib, h)
+    assert lib.prony_build_S_factors(h, NULL, P, P) == _lib.PRONY_EINVAL
+    assert lib.prony_build_S_factors(NULL, P, P, P) == _lib.PRONY_EINVAL
+    assert lib.prony_factors_destroy(NULL) == _lib.PRONY_EINVAL
+    assert lib.prony_factors_info(NULL, None, None, None, None, None) == _lib.PRONY_EINVAL
