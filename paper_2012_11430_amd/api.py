@@ -368,10 +368,9 @@ class Batch:
         self.handle = out
 
     def set_schedule(self, schedule: str) -> None:
-        """'queue' (one persistent launch over all tiles, FP32 only; the default
-        of FP32 batches with several tile classes) or 'classes' (one launch per
-        class; single-class and FP64 batches) — prony_batch_set_schedule.
-        Results are bitwise equal."""
+        """'classes' (one launch per tile class over four streams; the default)
+        or 'queue' (one persistent launch over all tiles, FP32 only) —
+        prony_batch_set_schedule. Results are bitwise equal."""
         codes = {"queue": _lib.PRONY_SCHEDULE_QUEUE, "classes": _lib.PRONY_SCHEDULE_CLASSES}
         if schedule not in codes:
             raise ValueError("schedule must be 'queue' or 'classes'")

@@ -34,7 +34,7 @@ CACHE_ENV = "PRONY_TUNE_CACHE"
 SINGLE_CANDIDATES = (1, 2, 3, 4, 8)       # split targets, x compute units
 SINGLE_FRAGMENTS = (1, 2, 4)              # 16-row fragments per wave
 BATCH_CANDIDATES = (1, 2, 4)              # chunks of the h range per instance
-BATCH_FRAGMENTS = (1, 2)                  # the queue kernel instantiates these
+BATCH_FRAGMENTS = (1, 2)                  # the batch kernels instantiate these
 
 
 def cache_path() -> str:

@@ -1583,9 +1583,11 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     // at most 3 (the kernel's 134 registers allow 3 waves per SIMD)
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(3, h->lds_per_block / (B->queue_lds + 16)));
     B->queue_grid = (int)std::min<size_t>(nitems, (size_t)per_cu * h->num_cus);
-    // several classes: one persistent launch over all of them; one class is one
-    // launch already, and its own kernel keeps more workgroups resident
-    B->schedule = sizeof(T) == 4 && B->launches.size() > 1 ? PRONY_SCHEDULE_QUEUE : PRONY_SCHEDULE_CLASSES;
+    // class launches by default: each class's own kernel keeps as many workgroups
+    // resident as its registers and LDS allow, and the lanes overlap the classes'
+    // tails (measured faster than the merged queue kernel on the 512-instance mix);
+    // the queue stays selectable for FP32 batches
+    B->schedule = PRONY_SCHEDULE_CLASSES;
     e = hipMemcpyAsync(ws, host.data(), sizeof(BatchEntry<T>) * (size_t)count, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(w + off_items, items.data(), sizeof(WorkItem) * nitems, hipMemcpyHostToDevice, h->stream);

@@ -97,7 +97,7 @@ def test_full_c3_batch_matches_single_instance_calls():
 @pytest.mark.parametrize("chunks", [1, 2, 4])
 @pytest.mark.parametrize("fragments", [1, 2])
 def test_full_c3_batch_at_every_tuned_tile(chunks, fragments):
-    # the FP32 batch the benchmark replays (queue schedule), with each (chunks per
+    # the FP32 batch the benchmark replays (default class schedule), with each (chunks per
     # instance, fragments per wave) pair the autotuner chooses from registered for
     # every shape bucket, against single FP64 calls (pinned to the oracle above)
     from paper_2012_11430_amd import autotune
@@ -129,7 +129,8 @@ def test_queue_schedule_is_bitwise_equal_to_class_launches():
     dev_inst = _device_instances(_c3_inputs(512))
     batch = api.Batch(dev_inst, prec="fp32")
     _say("queue vs class schedules: 512 instances")
-    batch.run()                        # default schedule of a several-class FP32 batch: queue
+    batch.set_schedule("queue")
+    batch.run()
     torch.cuda.synchronize()
     queued = [S.clone() for S in batch.S]
     for S in batch.S:
