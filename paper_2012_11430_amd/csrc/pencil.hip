@@ -9,10 +9,15 @@
 // (zero where k' - e_l leaves I_n; U_0 = U for S_0). The MFMA work of the large
 // product is that of one N x N by N x m product on (n+2)^d rows, not d of them;
 // the d shifted copies of U enter only the m-row reduction of each tile.
-// The complex product is run as a real one: every complex column q yields the
-// real columns (Re, Im) and every complex T entry a contributes two MFMAs, one
-// with Re(a) against (Re v, Im v) and one with Im(a) against (-Im v, Re v).
-// The second factor is packed once per call in that pair layout.
+// The complex product is run as a real one, in one of two forms chosen per shape
+// by the MFMA count. Pair form: every complex column q yields the real columns
+// (Re, Im) and every complex T entry a contributes two MFMAs, one with Re(a)
+// against (Re v, Im v) and one with Im(a) against (-Im v, Re v); 2m real columns
+// in blocks of 16. Three-product form: the complex columns are the MFMA columns
+// (m in blocks of 16) and a v takes the three real products P1 = Re a Re v,
+// P2 = Im a Im v, P3 = (Re a + Im a)(Re v + Im v), so Re(a v) = P1 - P2 and
+// Im(a v) = P3 - P1 - P2: three MFMAs per 16 complex columns instead of four.
+// The second factor is packed once per call in the form's layout.
 //
 // Kernels:
 //   pencil_pack         packs V (pair layout, or bfloat16 split planes), U in the
@@ -66,9 +71,11 @@ constexpr int kPrefetchRows = 4 * kDepth;
 // instantiation supports: the accumulators of all fragments must fit the register
 // file next to the operand ring. 1 always; 2 up to 8 (FP32) or 5 (FP64) column
 // blocks; 4 up to 4 (FP32, split bfloat16: 2) or 2 (FP64) column blocks.
-constexpr bool rf_supported(size_t tsize, int nb, int rf, bool split = false) {
-    return rf == 1 || (rf == 2 && nb <= (tsize == 4 ? 8 : 5)) ||
-           (rf == 4 && nb <= (split ? 2 : (tsize == 4 ? 4 : 2)));
+// The three-product form keeps three accumulator blocks per column block.
+constexpr bool rf_supported(size_t tsize, int nb, int rf, bool split = false, bool gauss = false) {
+    const int na = gauss ? 3 * nb : nb;   // accumulator blocks per fragment
+    return rf == 1 || (rf == 2 && na <= (tsize == 4 ? 8 : (gauss ? 6 : 5))) ||
+           (rf == 4 && na <= (split ? 2 : (tsize == 4 ? 4 : 2)));
 }
 constexpr bool rf2_supported(size_t tsize, int nb) { return rf_supported(tsize, nb, 2); }
 
@@ -82,7 +89,9 @@ struct PencilPlan {
     int first_ell;  // 0 with S_0, else 1
     int C;          // complex columns of the result rows: ells * m (product: r)
     int CB;         // complex columns of the second operand V (or X): m
-    int nb;         // 16-wide blocks of the 2 CB real columns of the second operand
+    int gauss;      // 1: each complex product as three real ones (Re a Re v, Im a Im v,
+                    //    (Re a + Im a)(Re v + Im v)); nb then counts blocks of 16 complex columns
+    int nb;         // 16-wide blocks of the 2 CB real columns of the second operand (gauss: of its CB columns)
     int nrp;        // 16 * nb
     int mbi;        // 16-row blocks of the m output rows
     int NR;         // rows of the large product: (n+2)^d row-extended k' (product: N)
@@ -139,16 +148,18 @@ __device__ __forceinline__ void split3(float x, unsigned short& h, unsigned shor
 }
 
 // Pair values of the second operand at (row hx, real column j): .x multiplies
-// Re(a), .y multiplies Im(a); zero past the N rows and the CB columns.
+// Re(a), .y multiplies Im(a); zero past the N rows and the CB columns. In the
+// three-product form j is the complex column and the pair is (Re v, Im v).
 __device__ __forceinline__ double2 pair_of(const PencilPlan& P, const double2* __restrict__ V, int64_t v_rs,
                                            int64_t v_cs, int hx, int j) {
-    const int c = j >> 1;
+    const int c = P.gauss ? j : j >> 1;
     double vr = 0.0, vi = 0.0;
     if (hx < P.kb && c < P.CB) {
         const double2 v = V[hx * v_rs + c * v_cs];
         vr = v.x;
         vi = v.y;
     }
+    if (P.gauss) return make_double2(vr, vi);   // complex column c as it is
     return (j & 1) ? make_double2(vi, vr) : make_double2(vr, -vi);
 }
 
@@ -277,9 +288,14 @@ struct TilePtrs {
 // One workgroup tile: rows kRows rt_i .. +kRows-1 of the large product (row-extended
 // k' for the S-build, k of I_n for the product) against chunk sk_i of the indices h
 // of I_n, where L = sk_i * rt + rt_i. See the file comment for the formulation.
-template <typename T, int NB, int RF, int MODE, bool SPLIT = false>
+// GAUSS: the three-product form (S-build tiles, FP32/FP64 operands); NB then
+// counts blocks of 16 complex columns and every fragment keeps three
+// accumulator blocks per column block (P1, P2, P3 at cb, NB + cb, 2 NB + cb).
+template <typename T, int NB, int RF, int MODE, bool SPLIT = false, bool GAUSS = false>
 __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>& ptr, const int L) {
     static_assert(!SPLIT || sizeof(T) == 4, "the split operands accumulate in FP32");
+    static_assert(!GAUSS || (MODE == 0 && !SPLIT), "three-product form: S-build tiles, FP32/FP64 operands");
+    constexpr int NA = GAUSS ? 3 * NB : NB;       // accumulator blocks per fragment
     using T2 = pair_t<T>;
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
@@ -375,11 +391,11 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 #pragma unroll
     for (int f = 0; f < RF; ++f) gk[f] = row_offset(P, min(krow0 + kRowsPerWave * f, P.NR - 1)) + P.c0 - lo;
 
-    acc_t acc[RF][NB];
+    acc_t acc[RF][NA];
 #pragma unroll
     for (int f = 0; f < RF; ++f)
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[f][cb] = acc_t{0, 0, 0, 0};
+        for (int cb = 0; cb < NA; ++cb) acc[f][cb] = acc_t{0, 0, 0, 0};
 
     // K loop over this chunk, 4 h' per step (lane group g takes h' = 4 ks + g).
     // Operands rotate through kDepth register buffers: while the MFMAs of step
@@ -416,10 +432,30 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // slot ad, B step `bs` into slot bd), then the MFMAs of the current slot. With
     // many MFMAs per step (FP32, NB RF >= 12) the B prefetch goes between the Re and
     // Im halves, which measured 6-11 % faster there and 3 % slower for 5 x 2.
-    constexpr bool kSplitLoads = sizeof(T) == 4 && NB * RF >= 12;
+    constexpr bool kSplitLoads = sizeof(T) == 4 && NB * RF >= 12 && !GAUSS;
+    // Three-product form: P1 += Re a Re v, P2 += Im a Im v, P3 += (Re a + Im a)(Re v + Im v).
+    auto mma_g = [&](const T2* av, const T2* bv) {
+        T bsum[NB];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) bsum[cb] = bv[cb].x + bv[cb].y;
+#pragma unroll
+        for (int f = 0; f < RF; ++f) {
+            const T asum = av[f].x + av[f].y;
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                acc[f][cb] = M::fma(av[f].x, bv[cb].x, acc[f][cb]);
+                acc[f][NB + cb] = M::fma(av[f].y, bv[cb].y, acc[f][NB + cb]);
+                acc[f][2 * NB + cb] = M::fma(asum, bsum[cb], acc[f][2 * NB + cb]);
+            }
+        }
+    };
     auto ring_step = [&](T2* ad, int off, T2* bd, int bs, const T2* av, const T2* bv) {
         load_a(ad, off);
-        if constexpr (kSplitLoads) {
+        if constexpr (GAUSS) {
+            load_b(bd, bs);
+            __builtin_amdgcn_sched_barrier(0);
+            mma_g(av, bv);
+        } else if constexpr (kSplitLoads) {
             __builtin_amdgcn_sched_barrier(0);
             mma_x(av, bv);
             __builtin_amdgcn_sched_barrier(0);
@@ -601,6 +637,19 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         return;
     }
 
+    if constexpr (GAUSS) {
+        // Re Z = P1 - P2 at block cb and Im Z = P3 - P1 - P2 at block NB + cb
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const T p1 = acc[f][cb][r], p2 = acc[f][NB + cb][r], p3 = acc[f][2 * NB + cb][r];
+                    acc[f][cb][r] = p1 - p2;
+                    acc[f][NB + cb][r] = p3 - p1 - p2;
+                }
+    }
     // Rows past the last row of the product (padding of the last row tile) hold
     // copies of that row's sums; they must not meet the shifted U_l rows below.
     const int wrow0 = k_first + kRowsPerWave * RF * wave;
@@ -611,7 +660,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
             for (int r = 0; r < 4; ++r)
                 if (wrow0 + kRowsPerWave * f + M::row(g, r) >= P.NR)
 #pragma unroll
-                    for (int cb = 0; cb < NB; ++cb) acc[f][cb][r] = T(0);
+                    for (int cb = 0; cb < NA; ++cb) acc[f][cb][r] = T(0);
     }
 
     // Reductions with the shifted U_l over this wave's rows: for every 16-row block
@@ -649,10 +698,43 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     __syncthreads();   // the window is dead from here on; its bytes become the slabs
 
     // Every wave writes the blocks of slot q of a pass into its own slab
-    // (lane-major, conflict free): virtual 16-column blocks q NB + cb. A pass holds
-    // ipp items (nbp >= NB blocks per wave); after one barrier all threads add the
+    // (lane-major, conflict free): virtual 16-column blocks q SB + cb. A pass holds
+    // ipp items (nbp >= SB blocks per wave); after one barrier all threads add the
     // four slabs in wave order and store the partial pairs of the pass.
+    // Three-product form: conj(U) Z with the products Q1 = Ur Zr, Q2 = (-Ui) Zi,
+    // Q3 = (Ur - Ui)(Zr + Zi), so Re = Q1 - Q2 and Im = Q3 - Q1 - Q2; an item's
+    // slab blocks are (Re, Im) per column block.
+    constexpr int SB = GAUSS ? 2 * NB : NB;       // slab blocks per item
+    auto products_g = [&](const T2 (&u)[RF][4], int q) {
+        acc_t e1[NB], e2[NB], e3[NB];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) e1[cb] = e2[cb] = e3[cb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const T ur = u[f][r].x, ui = -u[f][r].y, us = ur + ui;
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb) {
+                    const T zr = acc[f][cb][r], zi = acc[f][NB + cb][r];
+                    e1[cb] = M::fma(ur, zr, e1[cb]);
+                    e2[cb] = M::fma(ui, zi, e2[cb]);
+                    e3[cb] = M::fma(us, zr + zi, e3[cb]);
+                }
+            }
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                slab[((wave * P.nbp + q * SB + 2 * cb) * 4 + r) * 64 + lane] = e1[cb][r] - e2[cb][r];
+                slab[((wave * P.nbp + q * SB + 2 * cb + 1) * 4 + r) * 64 + lane] = e3[cb][r] - e1[cb][r] - e2[cb][r];
+            }
+    };
     auto products = [&](const T2 (&u)[RF][4], int q) {
+        if constexpr (GAUSS) {
+            products_g(u, q);
+            return;
+        }
         acc_t e[NB];
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) e[cb] = acc_t{0, 0, 0, 0};
@@ -674,7 +756,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
             for (int r = 0; r < 4; ++r) slab[((wave * P.nbp + q * NB + cb) * 4 + r) * 64 + lane] = e[cb][r];
     };
     const T2* slab2 = reinterpret_cast<const T2*>(slab);
-    const int ipp = max(1, P.nbp / NB);
+    const int ipp = max(1, P.nbp / SB);
     T2* out = part + (size_t)L * P.m * P.C;
     for (int p0 = 0; p0 < items; p0 += ipp) {
         const int np = min(ipp, items - p0);
@@ -698,24 +780,35 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
             const int il = rem / P.m, c = rem - il * P.m;
             const int it = p0 + q, ib = it / P.ells, li = it - ib * P.ells;
             if (ib * 16 + il >= P.m) continue;
-            const int j = 2 * c;   // Re in column j, Im in column j + 1 (lane + 1)
-            const int s0 = ((q * NB + (j >> 4)) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 + (j & 15);
-            T2 sum = slab2[s0 >> 1];
-            for (int w = 1; w < kWaves; ++w) {
-                const T2 v = slab2[(s0 + w * P.nbp * 256) >> 1];
-                sum.x += v.x;
-                sum.y += v.y;
+            T2 sum;
+            if constexpr (GAUSS) {   // Re in block 2 (c / 16), Im in the next block, column c % 16
+                const int s0 = ((q * SB + 2 * (c >> 4)) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 +
+                               (c & 15);
+                sum = T2{slab[s0], slab[s0 + 256]};
+                for (int w = 1; w < kWaves; ++w) {
+                    sum.x += slab[s0 + w * P.nbp * 256];
+                    sum.y += slab[s0 + w * P.nbp * 256 + 256];
+                }
+            } else {
+                const int j = 2 * c;   // Re in column j, Im in column j + 1 (lane + 1)
+                const int s0 = ((q * NB + (j >> 4)) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 + (j & 15);
+                sum = slab2[s0 >> 1];
+                for (int w = 1; w < kWaves; ++w) {
+                    const T2 v = slab2[(s0 + w * P.nbp * 256) >> 1];
+                    sum.x += v.x;
+                    sum.y += v.y;
+                }
             }
             out[(size_t)(ib * 16 + il) * P.C + li * P.m + c] = sum;
         }
         if (p0 + np < items) __syncthreads();   // slabs are rewritten by the next pass
     }
 }
-template <typename T, int NB, int RF>
+template <typename T, int NB, int RF, bool GAUSS>
 __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, TilePtrs<T> ptr) {
     const int id = blockIdx.x;
     const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
-    tile_body<T, NB, RF, 0>(P, ptr, L);
+    tile_body<T, NB, RF, 0, false, GAUSS>(P, ptr, L);
 }
 
 // S-build tiles with split operands (FP32-accurate products on the bf16 MFMA).
@@ -853,8 +946,11 @@ int tuned_fragments(prony_handle_t h, int d, int n, int m, int prec, int batched
 // rf_req: 16-row fragments per wave; 0 picks 2 where the instantiation allows it
 // (and the product has more than one 64-row tile), 1, 2 or 4 ask for that count
 // (the default when not supported for the column count).
+// allow_gauss: single-instance S-builds may take the three-product form where it
+// needs fewer MFMAs (3 ceil(m/16) against 2 ceil(m/8) per fragment and K step).
 prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P,
-                         int target_wgs = 0, int rf_req = 0, int mode = 0, bool split = false) {
+                         int target_wgs = 0, int rf_req = 0, int mode = 0, bool split = false,
+                         bool allow_gauss = false) {
     P = PencilPlan{};
     P.d = d;
     P.n = n;
@@ -866,14 +962,16 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.first_ell = mode || with_s0 ? 0 : 1;
     P.C = P.ells * m;
     P.CB = m;
-    P.nb = (2 * P.CB + 15) / 16;
+    P.gauss = mode == 0 && !split && allow_gauss && 3 * ((m + 15) / 16) < 2 * ((2 * m + 15) / 16) ? 1 : 0;
+    P.nb = P.gauss ? (P.CB + 15) / 16 : (2 * P.CB + 15) / 16;
     P.nrp = 16 * P.nb;
     P.mbi = mode ? 0 : (m + 15) / 16;
     P.NR = mode ? P.N : (int)ipow(n + 2, d);
     P.ug = mode ? 0 : (int)ipow(n + 2, d - 1);
     P.kb = P.N;
-    P.rf = rf2_supported(tsize, P.nb) && P.NR > kRowsPerTile ? 2 : 1;
-    if ((rf_req == 1 || rf_req == 2 || rf_req == 4) && rf_supported(tsize, P.nb, rf_req, split)) P.rf = rf_req;
+    P.rf = rf_supported(tsize, P.nb, 2, split, P.gauss) && P.NR > kRowsPerTile ? 2 : 1;
+    if ((rf_req == 1 || rf_req == 2 || rf_req == 4) && rf_supported(tsize, P.nb, rf_req, split, P.gauss))
+        P.rf = rf_req;
     P.rows = kRowsPerTile * P.rf;
     P.rt = (P.NR + P.rows - 1) / P.rows;
     P.c0 = grid_center(d, n);
@@ -883,7 +981,8 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     // slabs hold nbp 16-column blocks per wave: whole items (NB blocks each), at
     // least one, at most all mbi * ells of them.
     size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
-    P.nbp = P.nb * std::max(1, std::min(P.mbi * P.ells, (int)(budget / (tsize * kWaves * 16 * 16)) / std::max(1, P.nb)));
+    const int sb = P.nb * (P.gauss ? 2 : 1);   // slab blocks per item (three-product form: Re and Im)
+    P.nbp = sb * std::max(1, std::min(P.mbi * P.ells, (int)(budget / (tsize * kWaves * 16 * 16)) / sb));
     P.bbufs = 2;
     const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
@@ -953,15 +1052,15 @@ __global__ __launch_bounds__(kFinishThreads) void pencil_finish_batched(const Ba
                 [&](int o, double re, double im) { store_s(e.P, e.ptr.sigma, e.ptr.S, o, re, im); });
 }
 
-template <typename T, int NB, int RF>
+template <typename T, int NB, int RF, bool GAUSS = false>
 prony_status_t launch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
     if (P.lds_bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, NB, RF>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, NB, RF, GAUSS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
         if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
     }
     ProfileScope prof(h, "pencil_tiles");
-    pencil_tiles<T, NB, RF><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
+    pencil_tiles<T, NB, RF, GAUSS><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
     return PRONY_OK;
 }
 
@@ -1040,6 +1139,22 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_queue(const BatchEntry<
 
 template <typename T>
 prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
+    if (P.gauss) {   // three-product form: 16-complex-column blocks, m <= 32
+        switch (P.nb) {
+#define PRONY_GCASE(NBV)                                                   \
+    case NBV:                                                              \
+        if constexpr (rf_supported(sizeof(T), NBV, 4, false, true))        \
+            if (P.rf == 4) return launch_tiles<T, NBV, 4, true>(h, P, ptr); \
+        if constexpr (rf_supported(sizeof(T), NBV, 2, false, true))        \
+            if (P.rf == 2) return launch_tiles<T, NBV, 2, true>(h, P, ptr); \
+        return launch_tiles<T, NBV, 1, true>(h, P, ptr);
+            PRONY_GCASE(1)
+            PRONY_GCASE(2)
+#undef PRONY_GCASE
+            default:
+                return fail(h, PRONY_ENOTSUP, "prony_build_S: too many columns");
+        }
+    }
     switch (P.nb) {
 #define PRONY_CASE(NBV)                                                    \
     case NBV:                                                              \
@@ -1210,7 +1325,7 @@ size_t pencil_workspace_bytes(prony_handle_t h, int d, int n, int m) {
             for (int tg : targets)
                 for (int rf : {1, 2, 4}) {
                     PencilPlan P;
-                    if (make_plan(h, d, n, m, s0 == 1, ts, P, tg, rf, 0, prec == PRONY_BF16X3) == PRONY_OK)
+                    if (make_plan(h, d, n, m, s0 == 1, ts, P, tg, rf, 0, prec == PRONY_BF16X3, true) == PRONY_OK)
                         best = std::max(best, P.ws_bytes);
                 }
     }
@@ -1275,7 +1390,7 @@ prony_status_t plan_build_S(prony_handle_t h, const char* who, int d, int n, int
     const bool s0 = (flags & PRONY_WITH_S0) != 0;
     const size_t ts = prec == PRONY_FP64 ? sizeof(double) : sizeof(float);
     return make_plan(h, d, n, m, s0, ts, P, tuned_target(h, d, n, m, prec, 0), tuned_fragments(h, d, n, m, prec, 0),
-                     0, prec == PRONY_BF16X3);
+                     0, prec == PRONY_BF16X3, true);
 }
 
 prony_status_t run_build_S(prony_handle_t h, const PencilPlan& P, unsigned char* ws, prony_prec_t prec,

@@ -216,11 +216,15 @@ def test_tile_entries_exact_and_bucket(vhandle):
     assert _plan(lib, h, 2, 63, 20, _lib.PRONY_FP32)[1] == 4
     assert lib.prony_tune_get_tile(h, 2, 63, 20, _lib.PRONY_FP32, 0, ctypes.byref(frag), ctypes.byref(tgt)) == 0
     assert (frag.value, tgt.value) == (4, 512)
-    # FP64 supports 4 fragments only up to 2 column blocks (m <= 16): falls back to 2
+    # FP64 supports 4 fragments only up to 2 accumulator blocks per fragment: the
+    # pair form with one column block (m <= 8); m = 9..16 takes the three-product
+    # form (3 blocks) and m = 20 the pair form with 3 blocks, which fall back to 2
     assert lib.prony_tune_set_tile(h, 2, 63, 20, _lib.PRONY_FP64, 0, 4, 0) == _lib.PRONY_OK
     assert _plan(lib, h, 2, 63, 20, _lib.PRONY_FP64)[1] == 2
     assert lib.prony_tune_set_tile(h, 2, 63, 16, _lib.PRONY_FP64, 0, 4, 0) == _lib.PRONY_OK
-    assert _plan(lib, h, 2, 63, 16, _lib.PRONY_FP64)[1] == 4
+    assert _plan(lib, h, 2, 63, 16, _lib.PRONY_FP64)[1] == 2
+    assert lib.prony_tune_set_tile(h, 2, 63, 8, _lib.PRONY_FP64, 0, 4, 0) == _lib.PRONY_OK
+    assert _plan(lib, h, 2, 63, 8, _lib.PRONY_FP64)[1] == 4
     # a bucket entry (same d, floor(log2 N), ceil(m/8)) applies to other shapes of the bucket ...
     assert lib.prony_tune_set_tile(h, 3, 19, 30, _lib.PRONY_FP32, _lib.PRONY_TUNE_BUCKET, 1, 0) == _lib.PRONY_OK
     assert _plan(lib, h, 3, 18, 29, _lib.PRONY_FP32)[1] == 1          # N = 6859: same bucket as 8000
