@@ -872,7 +872,7 @@ __global__ __launch_bounds__(256) void pencil_pack_batched(const BatchEntry<T>* 
 // decreasing work: workgroup `id` finds its instance by binary search over the
 // tile offsets (the hardware dispatches workgroups in id order, so the longest
 // tiles start first).
-template <typename T, int NB, int RF>
+template <typename T, int NB, int RF, bool GAUSS>
 __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntry<T>* __restrict__ entries,
                                                                  int count) {
     const int id = blockIdx.x;
@@ -885,7 +885,7 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntr
             hi = mid - 1;
     }
     const BatchEntry<T>& e = entries[lo];
-    tile_body<T, NB, RF, 0>(e.P, e.ptr, id - e.tile_begin);
+    tile_body<T, NB, RF, 0, false, GAUSS>(e.P, e.ptr, id - e.tile_begin);
 }
 
 size_t lds_bytes_for(int win, int kc, int nbp, size_t tsize, int split_nrp = 0, int bbufs = 2) {
@@ -1064,16 +1064,16 @@ prony_status_t launch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtr
     return PRONY_OK;
 }
 
-template <typename T, int NB, int RF>
+template <typename T, int NB, int RF, bool GAUSS = false>
 prony_status_t launch_batched(prony_handle_t h, const BatchEntry<T>* entries, int count, int tiles, size_t lds,
                               hipStream_t stream) {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles_batched<T, NB, RF>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles_batched<T, NB, RF, GAUSS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
     }
     ProfileScope prof(h, "pencil_tiles_batched", stream);
-    pencil_tiles_batched<T, NB, RF><<<tiles, kThreads, lds, stream>>>(entries, count);
+    pencil_tiles_batched<T, NB, RF, GAUSS><<<tiles, kThreads, lds, stream>>>(entries, count);
     return PRONY_OK;
 }
 
@@ -1103,7 +1103,7 @@ struct WorkItem {
 // instance's column blocks and row fragments.
 template <typename T>
 __device__ __forceinline__ void tile_of_class(const BatchEntry<T>& e, int L) {
-    switch (e.P.nb * 2 + e.P.rf - 1) {
+    switch (e.P.gauss * 16 + e.P.nb * 2 + e.P.rf - 1) {
 #define PRONY_QCASE(NBV)                                           \
     case NBV * 2:                                                  \
         tile_body<T, NBV, 1, 0>(e.P, e.ptr, L);                    \
@@ -1113,6 +1113,16 @@ __device__ __forceinline__ void tile_of_class(const BatchEntry<T>& e, int L) {
         break;
         PRONY_NB_CASES(PRONY_QCASE)
 #undef PRONY_QCASE
+#define PRONY_QGCASE(NBV)                                                          \
+    case 16 + NBV * 2:                                                             \
+        tile_body<T, NBV, 1, 0, false, true>(e.P, e.ptr, L);                       \
+        break;                                                                     \
+    case 16 + NBV * 2 + 1:                                                         \
+        if constexpr (rf_supported(sizeof(T), NBV, 2, false, true)) tile_body<T, NBV, 2, 0, false, true>(e.P, e.ptr, L); \
+        break;
+        PRONY_QGCASE(1)
+        PRONY_QGCASE(2)
+#undef PRONY_QGCASE
         default:
             break;
     }
@@ -1179,8 +1189,22 @@ prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TileP
 }
 
 template <typename T>
-prony_status_t dispatch_batched(prony_handle_t h, int nb, int rf, const BatchEntry<T>* entries, int count, int tiles,
-                                size_t lds, hipStream_t stream) {
+prony_status_t dispatch_batched(prony_handle_t h, int nb, int rf, int gauss, const BatchEntry<T>* entries, int count,
+                                int tiles, size_t lds, hipStream_t stream) {
+    if (gauss) {
+        switch (nb) {
+#define PRONY_GCASE(NBV)                                                                                 \
+    case NBV:                                                                                            \
+        if constexpr (rf_supported(sizeof(T), NBV, 2, false, true))                                      \
+            if (rf == 2) return launch_batched<T, NBV, 2, true>(h, entries, count, tiles, lds, stream);  \
+        return launch_batched<T, NBV, 1, true>(h, entries, count, tiles, lds, stream);
+            PRONY_GCASE(1)
+            PRONY_GCASE(2)
+#undef PRONY_GCASE
+            default:
+                return fail(h, PRONY_ENOTSUP, "prony_build_S_batched: too many columns");
+        }
+    }
     switch (nb) {
 #define PRONY_CASE(NBV)                                                                        \
     case NBV:                                                                                  \
@@ -1604,17 +1628,23 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         if (!x.f || !x.U || !x.sigma || !x.V || !x.S) return fail(h, PRONY_EINVAL, who + "null pointer");
         // batch members: split into the tuned number of chunks (default 1)
         const TuneEntry te = tuned(h, x.d, x.n, x.m, sizeof(T) == 4 ? PRONY_FP32 : PRONY_FP64, true);
-        const int64_t NR = ipow(x.n + 2, x.d);
-        int rf = rf2_supported(sizeof(T), (2 * x.m + 15) / 16) && NR > kRowsPerTile ? 2 : 1;
-        if (te.fragments == 1 || (te.fragments == 2 && rf2_supported(sizeof(T), (2 * x.m + 15) / 16))) rf = te.fragments;
-        const int rt = (int)((NR + kRowsPerTile * rf - 1) / (kRowsPerTile * rf));
-        prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], std::max(1, te.target) * rt, rf);
+        // fragments: the tuned 1 or 2 where supported, else the default (never 4:
+        // the queue kernel instantiates 1 and 2); a first plan gives the row tiles
+        // that the chunk count multiplies
+        const int rf_req = te.fragments == 1 || te.fragments == 2 ? te.fragments : 0;
+        PencilPlan probe;
+        prony_status_t st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), probe, 1, rf_req, 0, false, true);
+        if (st == PRONY_OK)
+            st = make_plan(h, x.d, x.n, x.m, false, sizeof(T), plans[i], std::max(1, te.target) * probe.rt, probe.rf,
+                           0, false, true);
         if (st != PRONY_OK) return fail(h, st, who + h->err);
     }
-    // classes by (column-block count, row fragments); inside a class, longest tiles first
+    // classes by (product form, column-block count, row fragments); inside a class,
+    // longest tiles first
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (plans[a].gauss != plans[b].gauss) return plans[a].gauss < plans[b].gauss;
         if (plans[a].nb != plans[b].nb) return plans[a].nb < plans[b].nb;
         if (plans[a].rf != plans[b].rf) return plans[a].rf < plans[b].rf;
         return (int64_t)plans[a].kc * plans[a].rf > (int64_t)plans[b].kc * plans[b].rf;
@@ -1661,9 +1691,10 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         E.ptr.S = reinterpret_cast<double2*>(x.S);
         E.U = reinterpret_cast<const double2*>(x.U);
         E.V = reinterpret_cast<const double2*>(x.V);
-        const bool new_class = pos == 0 || plans[order[pos - 1]].nb != P.nb || plans[order[pos - 1]].rf != P.rf;
+        const PencilPlan* prev = pos == 0 ? nullptr : &plans[order[pos - 1]];
+        const bool new_class = !prev || prev->gauss != P.gauss || prev->nb != P.nb || prev->rf != P.rf;
         if (new_class) {
-            B->launches.push_back({P.nb, P.rf, pos, 0, 0, 0, 0.0});
+            B->launches.push_back({P.nb, P.rf, P.gauss, pos, 0, 0, 0, 0.0});
             first = 0;
         }
         auto& cl = B->launches.back();
@@ -1672,7 +1703,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         cl.count += 1;
         cl.tiles = first;
         cl.lds = std::max(cl.lds, P.lds_bytes);
-        cl.work += (double)P.nwg * P.kc * P.rf * P.nb;
+        cl.work += (double)P.nwg * P.kc * P.rf * P.nb * (P.gauss ? 3 : 2);
         const int64_t big = std::max<int64_t>(((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp,
                                               ((int64_t)P.ug + (int64_t)P.rt * P.rows) * P.mbi * 16);
         largest = (int)std::max<int64_t>(largest, (big + 255) / 256);
@@ -1685,7 +1716,9 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     items.reserve(nitems);
     std::vector<int> by_cost(count);
     for (int pos = 0; pos < count; ++pos) by_cost[pos] = pos;
-    auto cost = [&](int pos) { return (int64_t)host[pos].P.kc * host[pos].P.rf * host[pos].P.nb; };
+    auto cost = [&](int pos) {
+        return (int64_t)host[pos].P.kc * host[pos].P.rf * host[pos].P.nb * (host[pos].P.gauss ? 3 : 2);
+    };
     std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return cost(a) > cost(b); });
     for (int pos : by_cost)
         for (int L = 0; L < host[pos].P.nwg; ++L) items.push_back({pos, L});
@@ -1695,7 +1728,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     B->queue_lds = 0;
     for (int pos = 0; pos < count; ++pos) B->queue_lds = std::max(B->queue_lds, host[pos].P.lds_bytes);
     // resident workgroups per CU: LDS (dynamic + the kernel's 16 static bytes), and
-    // at most 3 (the kernel's 134 registers allow 3 waves per SIMD)
+    // at most 3 (the kernel's 161 registers allow 3 waves per SIMD)
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(3, h->lds_per_block / (B->queue_lds + 16)));
     B->queue_grid = (int)std::min<size_t>(nitems, (size_t)per_cu * h->num_cus);
     // class launches by default: each class's own kernel keeps as many workgroups
@@ -1765,7 +1798,7 @@ prony_status_t batch_launch(prony_handle_t h, prony_batch_s* B) {
             if (load[l] < load[lane]) lane = l;
         load[lane] += cl.work;
         hipStream_t s = lane == 0 ? h->stream : h->aux[lane - 1];
-        st = dispatch_batched<T>(h, cl.nb, cl.rf, entries + cl.first, cl.count, cl.tiles, cl.lds, s);
+        st = dispatch_batched<T>(h, cl.nb, cl.rf, cl.gauss, entries + cl.first, cl.count, cl.tiles, cl.lds, s);
         if (st != PRONY_OK) return st;
         if ((st = check_launch(h, "pencil_tiles_batched")) != PRONY_OK) return st;
     }
