@@ -168,7 +168,7 @@ struct prony_batch_s {
     int pack_x = 1;               // pack blocks per (instance, section)
     int finish_x = 1;             // finishing workgroups per instance (largest instance)
     struct ClassLaunch {
-        int nb, rf, gauss, first, count, tiles;
+        int nb, rf, ng, first, count, tiles;
         size_t lds;
         double work;   // sum of nwg * kc over the class (MFMA work, up to a factor)
     };

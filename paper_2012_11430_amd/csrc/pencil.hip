@@ -9,15 +9,18 @@
 // (zero where k' - e_l leaves I_n; U_0 = U for S_0). The MFMA work of the large
 // product is that of one N x N by N x m product on (n+2)^d rows, not d of them;
 // the d shifted copies of U enter only the m-row reduction of each tile.
-// The complex product is run as a real one, in one of two forms chosen per shape
-// by the MFMA count. Pair form: every complex column q yields the real columns
-// (Re, Im) and every complex T entry a contributes two MFMAs, one with Re(a)
-// against (Re v, Im v) and one with Im(a) against (-Im v, Re v); 2m real columns
-// in blocks of 16. Three-product form: the complex columns are the MFMA columns
-// (m in blocks of 16) and a v takes the three real products P1 = Re a Re v,
-// P2 = Im a Im v, P3 = (Re a + Im a)(Re v + Im v), so Re(a v) = P1 - P2 and
-// Im(a v) = P3 - P1 - P2: three MFMAs per 16 complex columns instead of four.
-// The second factor is packed once per call in the form's layout.
+// The complex product is run as a real one, in two forms of 16-column blocks.
+// Pair form: every complex column q yields the real columns (Re, Im) and every
+// complex T entry a contributes two MFMAs, one with Re(a) against (Re v, Im v)
+// and one with Im(a) against (-Im v, Re v): two MFMAs per 8 complex columns.
+// Three-product form: the complex columns are the MFMA columns and a v takes the
+// three real products P1 = Re a Re v, P2 = Im a Im v, P3 = (Re a + Im a)(Re v +
+// Im v), so Re(a v) = P1 - P2 and Im(a v) = P3 - P1 - P2: three MFMAs per 16
+// complex columns. S-builds take ng three-product blocks for the first columns and
+// a pair block for a remainder of at most 8 columns (m = 20: 16 + 4 columns, five
+// MFMAs per K step and fragment instead of six), so that no shape needs more
+// MFMAs than in either form alone. The second factor is packed once per call in
+// that layout.
 //
 // Kernels:
 //   pencil_pack         packs V (pair layout, or bfloat16 split planes), U in the
@@ -72,9 +75,11 @@ constexpr int kPrefetchRows = 4 * kDepth;
 // file next to the operand ring. 1 always; 2 up to 8 (FP32) or 5 (FP64) column
 // blocks; 4 up to 4 (FP32, split bfloat16: 2) or 2 (FP64) column blocks.
 // The three-product form keeps three accumulator blocks per column block.
-constexpr bool rf_supported(size_t tsize, int nb, int rf, bool split = false, bool gauss = false) {
-    const int na = gauss ? 3 * nb : nb;   // accumulator blocks per fragment
-    return rf == 1 || (rf == 2 && na <= (tsize == 4 ? 8 : (gauss ? 6 : 5))) ||
+// ng of the nb column blocks in the three-product form keep three accumulator
+// blocks each.
+constexpr bool rf_supported(size_t tsize, int nb, int rf, bool split = false, int ng = 0) {
+    const int na = nb + 2 * ng;   // accumulator blocks per fragment
+    return rf == 1 || (rf == 2 && na <= (tsize == 4 ? 8 : 6)) ||
            (rf == 4 && na <= (split ? 2 : (tsize == 4 ? 4 : 2)));
 }
 constexpr bool rf2_supported(size_t tsize, int nb) { return rf_supported(tsize, nb, 2); }
@@ -89,9 +94,9 @@ struct PencilPlan {
     int first_ell;  // 0 with S_0, else 1
     int C;          // complex columns of the result rows: ells * m (product: r)
     int CB;         // complex columns of the second operand V (or X): m
-    int gauss;      // 1: each complex product as three real ones (Re a Re v, Im a Im v,
-                    //    (Re a + Im a)(Re v + Im v)); nb then counts blocks of 16 complex columns
-    int nb;         // 16-wide blocks of the 2 CB real columns of the second operand (gauss: of its CB columns)
+    int ng;         // leading column blocks in the three-product form (16 complex columns each)
+    int nb;         // 16-wide column blocks of the second operand: ng three-product blocks, then
+                    // pair blocks for the remaining columns (2 real columns per complex one)
     int nrp;        // 16 * nb
     int mbi;        // 16-row blocks of the m output rows
     int NR;         // rows of the large product: (n+2)^d row-extended k' (product: N)
@@ -149,18 +154,19 @@ __device__ __forceinline__ void split3(float x, unsigned short& h, unsigned shor
 
 // Pair values of the second operand at (row hx, real column j): .x multiplies
 // Re(a), .y multiplies Im(a); zero past the N rows and the CB columns. In the
-// three-product form j is the complex column and the pair is (Re v, Im v).
+// three-product blocks (j < 16 ng) j is the complex column and the pair is (Re v, Im v).
 __device__ __forceinline__ double2 pair_of(const PencilPlan& P, const double2* __restrict__ V, int64_t v_rs,
                                            int64_t v_cs, int hx, int j) {
-    const int c = P.gauss ? j : j >> 1;
+    const int g16 = 16 * P.ng;
+    const int c = j < g16 ? j : g16 + ((j - g16) >> 1);
     double vr = 0.0, vi = 0.0;
     if (hx < P.kb && c < P.CB) {
         const double2 v = V[hx * v_rs + c * v_cs];
         vr = v.x;
         vi = v.y;
     }
-    if (P.gauss) return make_double2(vr, vi);   // complex column c as it is
-    return (j & 1) ? make_double2(vi, vr) : make_double2(vr, -vi);
+    if (j < g16) return make_double2(vr, vi);   // three-product block: complex column c as it is
+    return ((j - g16) & 1) ? make_double2(vi, vr) : make_double2(vr, -vi);
 }
 
 // Split packing of the second operand: per K block of 32 h', per plane p (the
@@ -288,14 +294,16 @@ struct TilePtrs {
 // One workgroup tile: rows kRows rt_i .. +kRows-1 of the large product (row-extended
 // k' for the S-build, k of I_n for the product) against chunk sk_i of the indices h
 // of I_n, where L = sk_i * rt + rt_i. See the file comment for the formulation.
-// GAUSS: the three-product form (S-build tiles, FP32/FP64 operands); NB then
-// counts blocks of 16 complex columns and every fragment keeps three
-// accumulator blocks per column block (P1, P2, P3 at cb, NB + cb, 2 NB + cb).
-template <typename T, int NB, int RF, int MODE, bool SPLIT = false, bool GAUSS = false>
+// NG: the first NG of the NB column blocks are in the three-product form (S-build
+// tiles, FP32/FP64 operands); each keeps three accumulator blocks per fragment
+// (P1, P2, P3 at cb, NG + cb, 2 NG + cb) and pair block pb is at 3 NG + pb.
+template <typename T, int NB, int RF, int MODE, bool SPLIT = false, int NG = 0>
 __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>& ptr, const int L) {
     static_assert(!SPLIT || sizeof(T) == 4, "the split operands accumulate in FP32");
-    static_assert(!GAUSS || (MODE == 0 && !SPLIT), "three-product form: S-build tiles, FP32/FP64 operands");
-    constexpr int NA = GAUSS ? 3 * NB : NB;       // accumulator blocks per fragment
+    static_assert(NG == 0 || (MODE == 0 && !SPLIT), "three-product form: S-build tiles, FP32/FP64 operands");
+    static_assert(NG >= 0 && NG <= NB, "three-product blocks come first");
+    constexpr int NP = NB - NG;                   // pair blocks
+    constexpr int NA = 3 * NG + NP;               // accumulator blocks per fragment
     using T2 = pair_t<T>;
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
@@ -432,26 +440,38 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // slot ad, B step `bs` into slot bd), then the MFMAs of the current slot. With
     // many MFMAs per step (FP32, NB RF >= 12) the B prefetch goes between the Re and
     // Im halves, which measured 6-11 % faster there and 3 % slower for 5 x 2.
-    constexpr bool kSplitLoads = sizeof(T) == 4 && NB * RF >= 12 && !GAUSS;
-    // Three-product form: P1 += Re a Re v, P2 += Im a Im v, P3 += (Re a + Im a)(Re v + Im v).
+    constexpr bool kSplitLoads = sizeof(T) == 4 && NB * RF >= 12 && NG == 0;
+    // With three-product blocks: P1 += Re a Re v, P2 += Im a Im v, P3 += (Re a +
+    // Im a)(Re v + Im v) for those, the pair MFMAs for the rest; the Re-multiplier
+    // MFMAs of every block first, so that dependent MFMAs sit apart.
     auto mma_g = [&](const T2* av, const T2* bv) {
-        T bsum[NB];
+        T bsum[NG > 0 ? NG : 1];
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) bsum[cb] = bv[cb].x + bv[cb].y;
+        for (int cb = 0; cb < NG; ++cb) bsum[cb] = bv[cb].x + bv[cb].y;
+#pragma unroll
+        for (int f = 0; f < RF; ++f) {
+#pragma unroll
+            for (int cb = 0; cb < NG; ++cb) acc[f][cb] = M::fma(av[f].x, bv[cb].x, acc[f][cb]);
+#pragma unroll
+            for (int pb = 0; pb < NP; ++pb) acc[f][3 * NG + pb] = M::fma(av[f].x, bv[NG + pb].x, acc[f][3 * NG + pb]);
+        }
+#pragma unroll
+        for (int f = 0; f < RF; ++f) {
+#pragma unroll
+            for (int cb = 0; cb < NG; ++cb) acc[f][NG + cb] = M::fma(av[f].y, bv[cb].y, acc[f][NG + cb]);
+#pragma unroll
+            for (int pb = 0; pb < NP; ++pb) acc[f][3 * NG + pb] = M::fma(av[f].y, bv[NG + pb].y, acc[f][3 * NG + pb]);
+        }
 #pragma unroll
         for (int f = 0; f < RF; ++f) {
             const T asum = av[f].x + av[f].y;
 #pragma unroll
-            for (int cb = 0; cb < NB; ++cb) {
-                acc[f][cb] = M::fma(av[f].x, bv[cb].x, acc[f][cb]);
-                acc[f][NB + cb] = M::fma(av[f].y, bv[cb].y, acc[f][NB + cb]);
-                acc[f][2 * NB + cb] = M::fma(asum, bsum[cb], acc[f][2 * NB + cb]);
-            }
+            for (int cb = 0; cb < NG; ++cb) acc[f][2 * NG + cb] = M::fma(asum, bsum[cb], acc[f][2 * NG + cb]);
         }
     };
     auto ring_step = [&](T2* ad, int off, T2* bd, int bs, const T2* av, const T2* bv) {
         load_a(ad, off);
-        if constexpr (GAUSS) {
+        if constexpr (NG > 0) {
             load_b(bd, bs);
             __builtin_amdgcn_sched_barrier(0);
             mma_g(av, bv);
@@ -637,17 +657,17 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         return;
     }
 
-    if constexpr (GAUSS) {
-        // Re Z = P1 - P2 at block cb and Im Z = P3 - P1 - P2 at block NB + cb
+    if constexpr (NG > 0) {
+        // three-product blocks: Re Z = P1 - P2 at block cb, Im Z = P3 - P1 - P2 at NG + cb
 #pragma unroll
         for (int f = 0; f < RF; ++f)
 #pragma unroll
-            for (int cb = 0; cb < NB; ++cb)
+            for (int cb = 0; cb < NG; ++cb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const T p1 = acc[f][cb][r], p2 = acc[f][NB + cb][r], p3 = acc[f][2 * NB + cb][r];
+                    const T p1 = acc[f][cb][r], p2 = acc[f][NG + cb][r], p3 = acc[f][2 * NG + cb][r];
                     acc[f][cb][r] = p1 - p2;
-                    acc[f][NB + cb][r] = p3 - p1 - p2;
+                    acc[f][NG + cb][r] = p3 - p1 - p2;
                 }
     }
     // Rows past the last row of the product (padding of the last row tile) hold
@@ -698,62 +718,62 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     __syncthreads();   // the window is dead from here on; its bytes become the slabs
 
     // Every wave writes the blocks of slot q of a pass into its own slab
-    // (lane-major, conflict free): virtual 16-column blocks q SB + cb. A pass holds
+    // (lane-major, conflict free): virtual 16-column blocks q SB + b. A pass holds
     // ipp items (nbp >= SB blocks per wave); after one barrier all threads add the
     // four slabs in wave order and store the partial pairs of the pass.
-    // Three-product form: conj(U) Z with the products Q1 = Ur Zr, Q2 = (-Ui) Zi,
-    // Q3 = (Ur - Ui)(Zr + Zi), so Re = Q1 - Q2 and Im = Q3 - Q1 - Q2; an item's
-    // slab blocks are (Re, Im) per column block.
-    constexpr int SB = GAUSS ? 2 * NB : NB;       // slab blocks per item
-    auto products_g = [&](const T2 (&u)[RF][4], int q) {
-        acc_t e1[NB], e2[NB], e3[NB];
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) e1[cb] = e2[cb] = e3[cb] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int f = 0; f < RF; ++f)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const T ur = u[f][r].x, ui = -u[f][r].y, us = ur + ui;
-#pragma unroll
-                for (int cb = 0; cb < NB; ++cb) {
-                    const T zr = acc[f][cb][r], zi = acc[f][NB + cb][r];
-                    e1[cb] = M::fma(ur, zr, e1[cb]);
-                    e2[cb] = M::fma(ui, zi, e2[cb]);
-                    e3[cb] = M::fma(us, zr + zi, e3[cb]);
-                }
-            }
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                slab[((wave * P.nbp + q * SB + 2 * cb) * 4 + r) * 64 + lane] = e1[cb][r] - e2[cb][r];
-                slab[((wave * P.nbp + q * SB + 2 * cb + 1) * 4 + r) * 64 + lane] = e3[cb][r] - e1[cb][r] - e2[cb][r];
-            }
-    };
+    // Three-product blocks: conj(U) Z with the products Q1 = Ur Zr, Q2 = (-Ui) Zi,
+    // Q3 = (Ur - Ui)(Zr + Zi), so Re = Q1 - Q2 and Im = Q3 - Q1 - Q2, stored as a
+    // Re block and an Im block; pair blocks as one block of (Re, Im) columns.
+    constexpr int SB = 2 * NG + NP;               // slab blocks per item
     auto products = [&](const T2 (&u)[RF][4], int q) {
-        if constexpr (GAUSS) {
-            products_g(u, q);
-            return;
-        }
-        acc_t e[NB];
+        if constexpr (NG > 0) {
+            acc_t e1[NG], e2[NG], e3[NG];
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) e[cb] = acc_t{0, 0, 0, 0};
+            for (int cb = 0; cb < NG; ++cb) e1[cb] = e2[cb] = e3[cb] = acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int f = 0; f < RF; ++f)
+            for (int f = 0; f < RF; ++f)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+                for (int r = 0; r < 4; ++r) {
+                    const T ur = u[f][r].x, ui = -u[f][r].y, us = ur + ui;
 #pragma unroll
-                for (int cb = 0; cb < NB; ++cb) {
-                    const T y = acc[f][cb][r];
-                    const T ys = swap_lane_pair(y);
-                    e[cb] = M::fma(u[f][r].x, y, e[cb]);
-                    e[cb] = M::fma(u[f][r].y, odd ? -ys : ys, e[cb]);
+                    for (int cb = 0; cb < NG; ++cb) {
+                        const T zr = acc[f][cb][r], zi = acc[f][NG + cb][r];
+                        e1[cb] = M::fma(ur, zr, e1[cb]);
+                        e2[cb] = M::fma(ui, zi, e2[cb]);
+                        e3[cb] = M::fma(us, zr + zi, e3[cb]);
+                    }
                 }
-            }
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
+            for (int cb = 0; cb < NG; ++cb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) slab[((wave * P.nbp + q * NB + cb) * 4 + r) * 64 + lane] = e[cb][r];
+                for (int r = 0; r < 4; ++r) {
+                    slab[((wave * P.nbp + q * SB + 2 * cb) * 4 + r) * 64 + lane] = e1[cb][r] - e2[cb][r];
+                    slab[((wave * P.nbp + q * SB + 2 * cb + 1) * 4 + r) * 64 + lane] =
+                        e3[cb][r] - e1[cb][r] - e2[cb][r];
+                }
+        }
+        if constexpr (NP > 0) {
+            acc_t e[NP];
+#pragma unroll
+            for (int pb = 0; pb < NP; ++pb) e[pb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int f = 0; f < RF; ++f)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                    for (int pb = 0; pb < NP; ++pb) {
+                        const T y = acc[f][3 * NG + pb][r];
+                        const T ys = swap_lane_pair(y);
+                        e[pb] = M::fma(u[f][r].x, y, e[pb]);
+                        e[pb] = M::fma(u[f][r].y, odd ? -ys : ys, e[pb]);
+                    }
+                }
+#pragma unroll
+            for (int pb = 0; pb < NP; ++pb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    slab[((wave * P.nbp + q * SB + 2 * NG + pb) * 4 + r) * 64 + lane] = e[pb][r];
+        }
     };
     const T2* slab2 = reinterpret_cast<const T2*>(slab);
     const int ipp = max(1, P.nbp / SB);
@@ -781,7 +801,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
             const int it = p0 + q, ib = it / P.ells, li = it - ib * P.ells;
             if (ib * 16 + il >= P.m) continue;
             T2 sum;
-            if constexpr (GAUSS) {   // Re in block 2 (c / 16), Im in the next block, column c % 16
+            if (c < 16 * NG) {   // Re in block 2 (c / 16), Im in the next block, column c % 16
                 const int s0 = ((q * SB + 2 * (c >> 4)) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 +
                                (c & 15);
                 sum = T2{slab[s0], slab[s0 + 256]};
@@ -790,8 +810,9 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                     sum.y += slab[s0 + w * P.nbp * 256 + 256];
                 }
             } else {
-                const int j = 2 * c;   // Re in column j, Im in column j + 1 (lane + 1)
-                const int s0 = ((q * NB + (j >> 4)) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 + (j & 15);
+                const int j = 2 * (c - 16 * NG);   // Re in pair column j, Im in j + 1 (lane + 1)
+                const int s0 = ((q * SB + 2 * NG + (j >> 4)) * 4 + M::elem_of_row(il)) * 64 +
+                               M::group_of_row(il) * 16 + (j & 15);
                 sum = slab2[s0 >> 1];
                 for (int w = 1; w < kWaves; ++w) {
                     const T2 v = slab2[(s0 + w * P.nbp * 256) >> 1];
@@ -804,11 +825,11 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         if (p0 + np < items) __syncthreads();   // slabs are rewritten by the next pass
     }
 }
-template <typename T, int NB, int RF, bool GAUSS>
+template <typename T, int NB, int RF, int NG>
 __global__ __launch_bounds__(kThreads) void pencil_tiles(PencilPlan P, TilePtrs<T> ptr) {
     const int id = blockIdx.x;
     const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
-    tile_body<T, NB, RF, 0, false, GAUSS>(P, ptr, L);
+    tile_body<T, NB, RF, 0, false, NG>(P, ptr, L);
 }
 
 // S-build tiles with split operands (FP32-accurate products on the bf16 MFMA).
@@ -872,7 +893,7 @@ __global__ __launch_bounds__(256) void pencil_pack_batched(const BatchEntry<T>* 
 // decreasing work: workgroup `id` finds its instance by binary search over the
 // tile offsets (the hardware dispatches workgroups in id order, so the longest
 // tiles start first).
-template <typename T, int NB, int RF, bool GAUSS>
+template <typename T, int NB, int RF, int NG>
 __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntry<T>* __restrict__ entries,
                                                                  int count) {
     const int id = blockIdx.x;
@@ -885,7 +906,7 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntr
             hi = mid - 1;
     }
     const BatchEntry<T>& e = entries[lo];
-    tile_body<T, NB, RF, 0, false, GAUSS>(e.P, e.ptr, id - e.tile_begin);
+    tile_body<T, NB, RF, 0, false, NG>(e.P, e.ptr, id - e.tile_begin);
 }
 
 size_t lds_bytes_for(int win, int kc, int nbp, size_t tsize, int split_nrp = 0, int bbufs = 2) {
@@ -946,8 +967,10 @@ int tuned_fragments(prony_handle_t h, int d, int n, int m, int prec, int batched
 // rf_req: 16-row fragments per wave; 0 picks 2 where the instantiation allows it
 // (and the product has more than one 64-row tile), 1, 2 or 4 ask for that count
 // (the default when not supported for the column count).
-// allow_gauss: single-instance S-builds may take the three-product form where it
-// needs fewer MFMAs (3 ceil(m/16) against 2 ceil(m/8) per fragment and K step).
+// allow_gauss: S-builds take three-product blocks of 16 complex columns while more
+// than 8 columns remain, then one pair block for the rest (per fragment and K step
+// 3 MFMAs per three-product block and 2 per pair block: never more than either
+// form alone, e.g. 5 instead of 6 at m = 20 and 6 instead of 8 at m = 30).
 prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P,
                          int target_wgs = 0, int rf_req = 0, int mode = 0, bool split = false,
                          bool allow_gauss = false) {
@@ -962,15 +985,19 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.first_ell = mode || with_s0 ? 0 : 1;
     P.C = P.ells * m;
     P.CB = m;
-    P.gauss = mode == 0 && !split && allow_gauss && 3 * ((m + 15) / 16) < 2 * ((2 * m + 15) / 16) ? 1 : 0;
-    P.nb = P.gauss ? (P.CB + 15) / 16 : (2 * P.CB + 15) / 16;
+    P.ng = 0;
+    if (mode == 0 && !split && allow_gauss) {
+        P.ng = m / 16;
+        if (m - 16 * P.ng > 8) ++P.ng;
+    }
+    P.nb = P.ng + (2 * std::max(0, P.CB - 16 * P.ng) + 15) / 16;
     P.nrp = 16 * P.nb;
     P.mbi = mode ? 0 : (m + 15) / 16;
     P.NR = mode ? P.N : (int)ipow(n + 2, d);
     P.ug = mode ? 0 : (int)ipow(n + 2, d - 1);
     P.kb = P.N;
-    P.rf = rf_supported(tsize, P.nb, 2, split, P.gauss) && P.NR > kRowsPerTile ? 2 : 1;
-    if ((rf_req == 1 || rf_req == 2 || rf_req == 4) && rf_supported(tsize, P.nb, rf_req, split, P.gauss))
+    P.rf = rf_supported(tsize, P.nb, 2, split, P.ng) && P.NR > kRowsPerTile ? 2 : 1;
+    if ((rf_req == 1 || rf_req == 2 || rf_req == 4) && rf_supported(tsize, P.nb, rf_req, split, P.ng))
         P.rf = rf_req;
     P.rows = kRowsPerTile * P.rf;
     P.rt = (P.NR + P.rows - 1) / P.rows;
@@ -981,7 +1008,7 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     // slabs hold nbp 16-column blocks per wave: whole items (NB blocks each), at
     // least one, at most all mbi * ells of them.
     size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
-    const int sb = P.nb * (P.gauss ? 2 : 1);   // slab blocks per item (three-product form: Re and Im)
+    const int sb = P.nb + P.ng;   // slab blocks per item (three-product blocks: Re and Im)
     P.nbp = sb * std::max(1, std::min(P.mbi * P.ells, (int)(budget / (tsize * kWaves * 16 * 16)) / sb));
     P.bbufs = 2;
     const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
@@ -1052,28 +1079,28 @@ __global__ __launch_bounds__(kFinishThreads) void pencil_finish_batched(const Ba
                 [&](int o, double re, double im) { store_s(e.P, e.ptr.sigma, e.ptr.S, o, re, im); });
 }
 
-template <typename T, int NB, int RF, bool GAUSS = false>
+template <typename T, int NB, int RF, int NG = 0>
 prony_status_t launch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
     if (P.lds_bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, NB, RF, GAUSS>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles<T, NB, RF, NG>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
         if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
     }
     ProfileScope prof(h, "pencil_tiles");
-    pencil_tiles<T, NB, RF, GAUSS><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
+    pencil_tiles<T, NB, RF, NG><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
     return PRONY_OK;
 }
 
-template <typename T, int NB, int RF, bool GAUSS = false>
+template <typename T, int NB, int RF, int NG = 0>
 prony_status_t launch_batched(prony_handle_t h, const BatchEntry<T>* entries, int count, int tiles, size_t lds,
                               hipStream_t stream) {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles_batched<T, NB, RF, GAUSS>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pencil_tiles_batched<T, NB, RF, NG>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
     }
     ProfileScope prof(h, "pencil_tiles_batched", stream);
-    pencil_tiles_batched<T, NB, RF, GAUSS><<<tiles, kThreads, lds, stream>>>(entries, count);
+    pencil_tiles_batched<T, NB, RF, NG><<<tiles, kThreads, lds, stream>>>(entries, count);
     return PRONY_OK;
 }
 
@@ -1091,6 +1118,9 @@ prony_status_t launch_tiles_split(prony_handle_t h, const PencilPlan& P, const T
 
 // Column blocks of the S-build's second operand: 2m <= 64 real columns.
 #define PRONY_NB_CASES(X) X(1) X(2) X(3) X(4)
+// (blocks, three-product blocks) of the S-builds with three-product blocks, m <= 32:
+// m = 9..16, 17..24, 25..32
+#define PRONY_MIXED_CASES(X) X(1, 1) X(2, 1) X(2, 2)
 
 // Work item of the queue schedule: a tile L of the instance at position `entry`
 // of the batch's entry table.
@@ -1103,7 +1133,7 @@ struct WorkItem {
 // instance's column blocks and row fragments.
 template <typename T>
 __device__ __forceinline__ void tile_of_class(const BatchEntry<T>& e, int L) {
-    switch (e.P.gauss * 16 + e.P.nb * 2 + e.P.rf - 1) {
+    switch (e.P.ng * 16 + e.P.nb * 2 + e.P.rf - 1) {
 #define PRONY_QCASE(NBV)                                           \
     case NBV * 2:                                                  \
         tile_body<T, NBV, 1, 0>(e.P, e.ptr, L);                    \
@@ -1113,15 +1143,14 @@ __device__ __forceinline__ void tile_of_class(const BatchEntry<T>& e, int L) {
         break;
         PRONY_NB_CASES(PRONY_QCASE)
 #undef PRONY_QCASE
-#define PRONY_QGCASE(NBV)                                                          \
-    case 16 + NBV * 2:                                                             \
-        tile_body<T, NBV, 1, 0, false, true>(e.P, e.ptr, L);                       \
+#define PRONY_QGCASE(NBV, NGV)                                                     \
+    case NGV * 16 + NBV * 2:                                                       \
+        tile_body<T, NBV, 1, 0, false, NGV>(e.P, e.ptr, L);                        \
         break;                                                                     \
-    case 16 + NBV * 2 + 1:                                                         \
-        if constexpr (rf_supported(sizeof(T), NBV, 2, false, true)) tile_body<T, NBV, 2, 0, false, true>(e.P, e.ptr, L); \
+    case NGV * 16 + NBV * 2 + 1:                                                   \
+        if constexpr (rf_supported(sizeof(T), NBV, 2, false, NGV)) tile_body<T, NBV, 2, 0, false, NGV>(e.P, e.ptr, L); \
         break;
-        PRONY_QGCASE(1)
-        PRONY_QGCASE(2)
+        PRONY_MIXED_CASES(PRONY_QGCASE)
 #undef PRONY_QGCASE
         default:
             break;
@@ -1149,17 +1178,16 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_queue(const BatchEntry<
 
 template <typename T>
 prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
-    if (P.gauss) {   // three-product form: 16-complex-column blocks, m <= 32
-        switch (P.nb) {
-#define PRONY_GCASE(NBV)                                                   \
-    case NBV:                                                              \
-        if constexpr (rf_supported(sizeof(T), NBV, 4, false, true))        \
-            if (P.rf == 4) return launch_tiles<T, NBV, 4, true>(h, P, ptr); \
-        if constexpr (rf_supported(sizeof(T), NBV, 2, false, true))        \
-            if (P.rf == 2) return launch_tiles<T, NBV, 2, true>(h, P, ptr); \
-        return launch_tiles<T, NBV, 1, true>(h, P, ptr);
-            PRONY_GCASE(1)
-            PRONY_GCASE(2)
+    if (P.ng) {   // three-product blocks (and a pair block), m <= 32
+        switch (P.ng * 16 + P.nb) {
+#define PRONY_GCASE(NBV, NGV)                                                   \
+    case NGV * 16 + NBV:                                                        \
+        if constexpr (rf_supported(sizeof(T), NBV, 4, false, NGV))              \
+            if (P.rf == 4) return launch_tiles<T, NBV, 4, NGV>(h, P, ptr);      \
+        if constexpr (rf_supported(sizeof(T), NBV, 2, false, NGV))              \
+            if (P.rf == 2) return launch_tiles<T, NBV, 2, NGV>(h, P, ptr);      \
+        return launch_tiles<T, NBV, 1, NGV>(h, P, ptr);
+            PRONY_MIXED_CASES(PRONY_GCASE)
 #undef PRONY_GCASE
             default:
                 return fail(h, PRONY_ENOTSUP, "prony_build_S: too many columns");
@@ -1189,17 +1217,16 @@ prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TileP
 }
 
 template <typename T>
-prony_status_t dispatch_batched(prony_handle_t h, int nb, int rf, int gauss, const BatchEntry<T>* entries, int count,
+prony_status_t dispatch_batched(prony_handle_t h, int nb, int rf, int ng, const BatchEntry<T>* entries, int count,
                                 int tiles, size_t lds, hipStream_t stream) {
-    if (gauss) {
-        switch (nb) {
-#define PRONY_GCASE(NBV)                                                                                 \
-    case NBV:                                                                                            \
-        if constexpr (rf_supported(sizeof(T), NBV, 2, false, true))                                      \
-            if (rf == 2) return launch_batched<T, NBV, 2, true>(h, entries, count, tiles, lds, stream);  \
-        return launch_batched<T, NBV, 1, true>(h, entries, count, tiles, lds, stream);
-            PRONY_GCASE(1)
-            PRONY_GCASE(2)
+    if (ng) {
+        switch (ng * 16 + nb) {
+#define PRONY_GCASE(NBV, NGV)                                                                           \
+    case NGV * 16 + NBV:                                                                                \
+        if constexpr (rf_supported(sizeof(T), NBV, 2, false, NGV))                                      \
+            if (rf == 2) return launch_batched<T, NBV, 2, NGV>(h, entries, count, tiles, lds, stream);  \
+        return launch_batched<T, NBV, 1, NGV>(h, entries, count, tiles, lds, stream);
+            PRONY_MIXED_CASES(PRONY_GCASE)
 #undef PRONY_GCASE
             default:
                 return fail(h, PRONY_ENOTSUP, "prony_build_S_batched: too many columns");
@@ -1644,7 +1671,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (plans[a].gauss != plans[b].gauss) return plans[a].gauss < plans[b].gauss;
+        if (plans[a].ng != plans[b].ng) return plans[a].ng < plans[b].ng;
         if (plans[a].nb != plans[b].nb) return plans[a].nb < plans[b].nb;
         if (plans[a].rf != plans[b].rf) return plans[a].rf < plans[b].rf;
         return (int64_t)plans[a].kc * plans[a].rf > (int64_t)plans[b].kc * plans[b].rf;
@@ -1692,9 +1719,9 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         E.U = reinterpret_cast<const double2*>(x.U);
         E.V = reinterpret_cast<const double2*>(x.V);
         const PencilPlan* prev = pos == 0 ? nullptr : &plans[order[pos - 1]];
-        const bool new_class = !prev || prev->gauss != P.gauss || prev->nb != P.nb || prev->rf != P.rf;
+        const bool new_class = !prev || prev->ng != P.ng || prev->nb != P.nb || prev->rf != P.rf;
         if (new_class) {
-            B->launches.push_back({P.nb, P.rf, P.gauss, pos, 0, 0, 0, 0.0});
+            B->launches.push_back({P.nb, P.rf, P.ng, pos, 0, 0, 0, 0.0});
             first = 0;
         }
         auto& cl = B->launches.back();
@@ -1703,7 +1730,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
         cl.count += 1;
         cl.tiles = first;
         cl.lds = std::max(cl.lds, P.lds_bytes);
-        cl.work += (double)P.nwg * P.kc * P.rf * P.nb * (P.gauss ? 3 : 2);
+        cl.work += (double)P.nwg * P.kc * P.rf * (2 * P.nb + P.ng);   // MFMAs per K step and fragment
         const int64_t big = std::max<int64_t>(((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp,
                                               ((int64_t)P.ug + (int64_t)P.rt * P.rows) * P.mbi * 16);
         largest = (int)std::max<int64_t>(largest, (big + 255) / 256);
@@ -1717,7 +1744,7 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     std::vector<int> by_cost(count);
     for (int pos = 0; pos < count; ++pos) by_cost[pos] = pos;
     auto cost = [&](int pos) {
-        return (int64_t)host[pos].P.kc * host[pos].P.rf * host[pos].P.nb * (host[pos].P.gauss ? 3 : 2);
+        return (int64_t)host[pos].P.kc * host[pos].P.rf * (2 * host[pos].P.nb + host[pos].P.ng);
     };
     std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return cost(a) > cost(b); });
     for (int pos : by_cost)
@@ -1798,7 +1825,7 @@ prony_status_t batch_launch(prony_handle_t h, prony_batch_s* B) {
             if (load[l] < load[lane]) lane = l;
         load[lane] += cl.work;
         hipStream_t s = lane == 0 ? h->stream : h->aux[lane - 1];
-        st = dispatch_batched<T>(h, cl.nb, cl.rf, cl.gauss, entries + cl.first, cl.count, cl.tiles, cl.lds, s);
+        st = dispatch_batched<T>(h, cl.nb, cl.rf, cl.ng, entries + cl.first, cl.count, cl.tiles, cl.lds, s);
         if (st != PRONY_OK) return st;
         if ((st = check_launch(h, "pencil_tiles_batched")) != PRONY_OK) return st;
     }
