@@ -11,10 +11,12 @@
 // i.e. the (n+2)^d x N product (inner dimension m) is summed along its Toeplitz
 // diagonals.
 //
-// adjoint_pack   forms Z (FP64, stored in T), packs W in the MFMA pair layout,
+// adjoint_pack   forms Z (FP64, stored in T), packs W as (Re, Im) pairs,
 //                writes the G(h) table and zeroes the gradient;
 // adjoint_tiles  one workgroup = 64 rows k' x one chunk of h: for every block of
-//                16 h the tile of Z W^T is formed on MFMA (K = m), and each
+//                16 h the tile of Z W^T is formed on MFMA (K = m; three real
+//                products per complex one: Re z Re w, Im z Im w and
+//                (Re z + Im z)(Re w + Im w)), and each
 //                entry is added (LDS atomics, accumulation in FP64) to the bin of
 //                its diagonal in an LDS copy of the workgroup's grid window; the
 //                window is then added to the gradient in FP64 (device atomics).
@@ -96,19 +98,17 @@ __device__ __forceinline__ void adj_pack_body(const AdjPlan& P, const double2* _
             zp[e] = T2{(T)re, (T)im};
         }
     } else if (section == 1) {
-        // W pairs, row q, column j = 2 h + part: (Re Z) multiplies .x, (Im Z) .y
-        const int row = 2 * kbp;
-        const int nw = P.cp * row;
+        // W = conj(V) as (Re, Im) pairs, row q, column h
+        const int nw = P.cp * kbp;
         for (int e = first; e < nw; e += stride) {
-            const int q = e / row, j = e - (e / row) * row;
-            const int hx = j >> 1;
+            const int q = e / kbp, hx = e - (e / kbp) * kbp;
             double wr = 0.0, wi = 0.0;
             if (hx < P.kb && q < P.m) {
                 const double2 v = V[hx * v_rs + q * v_cs];
                 wr = v.x;
                 wi = -v.y;   // conj
             }
-            wp[e] = (j & 1) ? T2{(T)wi, (T)wr} : T2{(T)wr, (T)(-wi)};
+            wp[e] = T2{(T)wr, (T)wi};
         }
     } else {
         for (int hx = first; hx < kbp; hx += stride)
@@ -141,7 +141,7 @@ struct AdjPtrs {
 // LDS: diagonal bins (2 win_cap doubles: LDS FP64 atomics measured several
 // times faster than FP32 ones here, and the bins then add in FP64 for both
 // precisions) | h' offsets (kc ints) | two staging
-// buffers of one W block (cp rows x 32 pairs each).
+// buffers of one W block (cp rows x 16 pairs each).
 __host__ __device__ inline size_t adj_bins_bytes(int win_cap) { return align_up(2 * sizeof(double) * (size_t)win_cap, 16); }
 __host__ __device__ inline size_t adj_gt_bytes(int kc) { return align_up(4 * (size_t)kc, 16); }
 
@@ -152,7 +152,9 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
     using acc_t = typename M::acc_t;
     constexpr int kTileRows = kRows * RF;
     constexpr int cp = 4 * KS;              // padded complex K
-    constexpr int kStg = cp * 32 / kThreads;   // staged pairs per thread and block
+    constexpr int kPairs = cp * kHBlock;          // W pairs of one h block
+    constexpr int kBuf = kPairs + 1;              // staging buffer stride: the block and one spare slot
+    constexpr int kStg = (kPairs + kThreads - 1) / kThreads;   // staged pairs per thread and block
     extern __shared__ __align__(16) unsigned char smem[];
     double* bins = reinterpret_cast<double*>(smem);
     int* gt = reinterpret_cast<int*>(smem + adj_bins_bytes(P.win_cap));
@@ -169,16 +171,27 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
     const int lo = rowext_offset(k_first, P.d, P.n) - grid_offset_of_index(h_last, P.d, P.n) + P.c0;
     const int hi = rowext_offset(k_last, P.d, P.n) - grid_offset_of_index(h_first, P.d, P.n) + P.c0;
     const int W = hi - lo + 1;
-    const int rowlen = 2 * P.sk * P.kc;
+    const int rowlen = P.sk * P.kc;
     const int nblk = P.kc / kHBlock;
 
-    // W block hb: rows c < cp, 32 pairs from column 2 (h_first + 16 hb); thread
-    // tid moves pairs e = tid + 256 u (row e / 32, pair e % 32)
-    const T2* wsrc = ptr.wp + (size_t)(tid >> 5) * rowlen + (tid & 31) + 2 * h_first;
-    constexpr int kRowStep = kThreads / 32;   // rows advanced per u
-    T2 stg[kStg];
-#pragma unroll
-    for (int u = 0; u < kStg; ++u) stg[u] = wsrc[(size_t)u * kRowStep * rowlen];
+    // W block hb: rows q < cp, 16 pairs from column h_first + 16 hb; thread tid
+    // moves pairs e = tid + 256 u < cp 16 (row e / 16, pair e % 16). When the
+    // block is not a whole number of rounds, the last round's other threads load
+    // the block's last pair again (the loads stay unconditional, so the staging
+    // registers stay registers) and write nothing.
+    auto wsrc = [&](int u, int blk) {
+        const int e = min(tid + u * kThreads, kPairs - 1);
+        return ptr.wp + (size_t)(e >> 4) * rowlen + (e & 15) + h_first + kHBlock * blk;
+    };
+    constexpr int kTail = kPairs % kThreads;
+    const bool tail_ok = kTail == 0 || tid < kTail;
+    // LDS slot of staged pair u: its place in the block, or the buffer's spare slot
+    // for the last round's idle threads (every thread writes: no branch)
+    auto slot = [&](int u) { return u + 1 < kStg || tail_ok ? tid + u * kThreads : kPairs; };
+    static_assert(kStg <= 2, "m <= 32: at most two staged pairs per thread");
+    // two named registers rather than an array, which the compiler kept in scratch
+    T2 stg0 = *wsrc(0, 0), stg1{};
+    if constexpr (kStg > 1) stg1 = *wsrc(1, 0);
     for (int i = tid; i < 2 * W; i += kThreads) bins[i] = 0.0;
     for (int i = tid; i < P.kc; i += kThreads) gt[i] = ptr.gtab[min(h_first + i, h_last)];
 
@@ -197,49 +210,47 @@ __device__ __forceinline__ void adjoint_body(const AdjPlan& P, const AdjPtrs<T>&
         for (int r = 0; r < 4; ++r)
             gk[f][r] = rowext_offset(min(k_first + 16 * RF * wave + 16 * f + M::row(g, r), P.NR - 1), P.d, P.n) +
                        P.c0 - lo;
-#pragma unroll
-    for (int u = 0; u < kStg; ++u) wst[tid + u * kThreads] = stg[u];
+    wst[slot(0)] = stg0;
+    if constexpr (kStg > 1) wst[slot(1)] = stg1;
     __syncthreads();
 
     for (int hb = 0; hb < nblk; ++hb) {
         // next block's W (the last block fetches itself again) lands while the MFMAs run
         const int nxt = min(hb + 1, nblk - 1);
+        stg0 = *wsrc(0, nxt);
+        if constexpr (kStg > 1) stg1 = *wsrc(1, nxt);
+        // three real products per complex product: P1 = Re z Re w, P2 = Im z Im w,
+        // P3 = (Re z + Im z)(Re w + Im w); Re = P1 - P2, Im = P3 - P1 - P2
+        const T2* wb = wst + (hb & 1) * kBuf + g * kHBlock + col;
+        acc_t acc[RF][3];
 #pragma unroll
-        for (int u = 0; u < kStg; ++u) stg[u] = wsrc[(size_t)u * kRowStep * rowlen + 2 * kHBlock * nxt];
-        const T2* wb = wst + (hb & 1) * cp * 32 + g * 32 + col;
-        acc_t acc[RF][2];
-#pragma unroll
-        for (int f = 0; f < RF; ++f) acc[f][0] = acc[f][1] = acc_t{0, 0, 0, 0};
+        for (int f = 0; f < RF; ++f) acc[f][0] = acc[f][1] = acc[f][2] = acc_t{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const T2 b0 = wb[4 * s * 32];
-            const T2 b1 = wb[4 * s * 32 + 16];
+            const T2 b = wb[4 * s * kHBlock];
+            const T bsum = b.x + b.y;
 #pragma unroll
-            for (int f = 0; f < RF; ++f) {
-                acc[f][0] = M::fma(a[f][s].x, b0.x, acc[f][0]);
-                acc[f][1] = M::fma(a[f][s].x, b1.x, acc[f][1]);
-            }
+            for (int f = 0; f < RF; ++f) acc[f][0] = M::fma(a[f][s].x, b.x, acc[f][0]);
 #pragma unroll
-            for (int f = 0; f < RF; ++f) {
-                acc[f][0] = M::fma(a[f][s].y, b0.y, acc[f][0]);
-                acc[f][1] = M::fma(a[f][s].y, b1.y, acc[f][1]);
-            }
+            for (int f = 0; f < RF; ++f) acc[f][1] = M::fma(a[f][s].y, b.y, acc[f][1]);
+#pragma unroll
+            for (int f = 0; f < RF; ++f) acc[f][2] = M::fma(a[f][s].x + a[f][s].y, bsum, acc[f][2]);
         }
-        // element r of lane (g, col) in block cb of fragment f: row 16 f + row(g,r),
-        // real column j = 16 cb + col, i.e. h = 16 hb + j/2 and part j&1 (rows past
-        // the last row of Z are zero rows: they add zeros)
+        // element r of lane (g, col) of fragment f: row 16 f + row(g,r), column
+        // h = 16 hb + col (rows past the last row of Z are zero rows: they add zeros)
+        const int gh = gt[hb * kHBlock + col];
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-            const int j = cb * 16 + col;
-            const int gh = gt[hb * kHBlock + (j >> 1)];
+        for (int f = 0; f < RF; ++f)
 #pragma unroll
-            for (int f = 0; f < RF; ++f)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) atomicAdd(&bins[2 * (gk[f][r] - gh) + (j & 1)], (double)acc[f][cb][r]);
-        }
+            for (int r = 0; r < 4; ++r) {
+                const T p1 = acc[f][0][r], p2 = acc[f][1][r], p3 = acc[f][2][r];
+                double* bin = &bins[2 * (gk[f][r] - gh)];
+                atomicAdd(bin, (double)(p1 - p2));
+                atomicAdd(bin + 1, (double)(p3 - p1 - p2));
+            }
         // the other buffer was last read before the previous barrier
-#pragma unroll
-        for (int u = 0; u < kStg; ++u) wst[((hb + 1) & 1) * cp * 32 + tid + u * kThreads] = stg[u];
+        wst[((hb + 1) & 1) * kBuf + slot(0)] = stg0;
+        if constexpr (kStg > 1) wst[((hb + 1) & 1) * kBuf + slot(1)] = stg1;
         __syncthreads();
     }
     double* out = reinterpret_cast<double*>(ptr.gf + lo);
@@ -315,7 +326,7 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
     P.rt = (P.NR + P.rows - 1) / P.rows;
     P.c0 = grid_center(d, n);
     P.gsize = (int)ipow(2 * n + 2, d);
-    const size_t staging = 2 * (2 * tsize) * (size_t)P.cp * 32;
+    const size_t staging = 2 * (2 * tsize) * ((size_t)P.cp * kHBlock + 1);
     const size_t budget = std::min<size_t>(h->lds_per_block, staging + 64 * 1024);
     const int target = batched ? P.rt * std::max(1, P.kb / 256) : 2 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
@@ -347,13 +358,13 @@ prony_status_t make_adj_plan(prony_handle_t h, int d, int n, int m, size_t tsize
     }
     P.nwg = P.rt * P.sk;
     const size_t t2 = 2 * tsize;
-    if ((int64_t)P.cp * 2 * P.sk * P.kc >= (int64_t(1) << 31))
+    if ((int64_t)P.cp * P.sk * P.kc >= (int64_t(1) << 31))
         return fail(h, PRONY_ENOTSUP, "prony_build_S_adjoint: problem too large");
     size_t off = 0;
     P.off_z = off;
     off = align_up(off + t2 * (size_t)P.rt * P.rows * P.cp, 256);
     P.off_w = off;
-    off = align_up(off + t2 * (size_t)P.cp * 2 * P.sk * P.kc, 256);
+    off = align_up(off + t2 * (size_t)P.cp * P.sk * P.kc, 256);
     P.off_g = off;
     off = align_up(off + 4 * (size_t)P.sk * P.kc, 256);
     P.ws_bytes = off;
@@ -390,7 +401,7 @@ prony_status_t launch_adjoint(prony_handle_t h, const AdjPlan& P, const double* 
     T2* zp = reinterpret_cast<T2*>(ws + P.off_z);
     T2* wp = reinterpret_cast<T2*>(ws + P.off_w);
     int* gt = reinterpret_cast<int*>(ws + P.off_g);
-    const int64_t largest = std::max<int64_t>({(int64_t)P.rt * P.rows * P.cp, (int64_t)P.cp * 2 * P.sk * P.kc,
+    const int64_t largest = std::max<int64_t>({(int64_t)P.rt * P.rows * P.cp, (int64_t)P.cp * P.sk * P.kc,
                                                (int64_t)P.gsize});
     const int blocks = (int)std::min<int64_t>((largest + 255) / 256, 2 * (int64_t)h->num_cus);
     {
@@ -531,7 +542,7 @@ prony_status_t adj_batch_build(prony_handle_t h, const prony_batch_s* B, AdjBatc
         cl.count += 1;
         cl.tiles = first;
         cl.lds = std::max(cl.lds, P.lds_bytes);
-        largest = std::max<int64_t>({largest, (int64_t)P.rt * P.rows * P.cp, (int64_t)P.cp * 2 * P.sk * P.kc,
+        largest = std::max<int64_t>({largest, (int64_t)P.rt * P.rows * P.cp, (int64_t)P.cp * P.sk * P.kc,
                                      (int64_t)P.gsize});
     }
     A->count = count;
