@@ -82,7 +82,6 @@ constexpr bool rf_supported(size_t tsize, int nb, int rf, bool split = false, in
     return rf == 1 || (rf == 2 && na <= (tsize == 4 ? 8 : 6)) ||
            (rf == 4 && na <= (split ? 2 : (tsize == 4 ? 4 : 2)));
 }
-constexpr bool rf2_supported(size_t tsize, int nb) { return rf_supported(tsize, nb, 2); }
 
 struct PencilPlan {
     int d, n, N, m;
@@ -98,6 +97,7 @@ struct PencilPlan {
     int nb;         // 16-wide column blocks of the second operand: ng three-product blocks, then
                     // pair blocks for the remaining columns (2 real columns per complex one)
     int nrp;        // 16 * nb
+    int nrr;        // real columns of a product row: 32 per three-product block, 16 per pair block
     int mbi;        // 16-row blocks of the m output rows
     int NR;         // rows of the large product: (n+2)^d row-extended k' (product: N)
     int ug;         // zero guard rows in front of the packed U: (n+2)^(d-1), the largest shift
@@ -300,7 +300,7 @@ struct TilePtrs {
 template <typename T, int NB, int RF, int MODE, bool SPLIT = false, int NG = 0>
 __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>& ptr, const int L) {
     static_assert(!SPLIT || sizeof(T) == 4, "the split operands accumulate in FP32");
-    static_assert(NG == 0 || (MODE == 0 && !SPLIT), "three-product form: S-build tiles, FP32/FP64 operands");
+    static_assert(NG == 0 || !SPLIT, "three-product form: FP32/FP64 operands");
     static_assert(NG >= 0 && NG <= NB, "three-product blocks come first");
     constexpr int NP = NB - NG;                   // pair blocks
     constexpr int NA = 3 * NG + NP;               // accumulator blocks per fragment
@@ -642,21 +642,6 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     }
     }
 
-    if constexpr (MODE == 1) {
-        // Product: this chunk's part of Y = T X for the wave's rows, real column
-        // 16 cb + col of row 16 (RF wave + f) + row(g, r), summed over chunks by
-        // the finishing launch. No barrier: the window is not reused.
-        T* yp = reinterpret_cast<T*>(part) + ((size_t)sk_i * P.rt * P.rows + k_first + kRowsPerWave * RF * wave) * P.nrp + col;
-#pragma unroll
-        for (int f = 0; f < RF; ++f)
-#pragma unroll
-            for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    yp[(size_t)(kRowsPerWave * f + M::row(g, r)) * P.nrp + 16 * cb] = acc[f][cb][r];
-        return;
-    }
-
     if constexpr (NG > 0) {
         // three-product blocks: Re Z = P1 - P2 at block cb, Im Z = P3 - P1 - P2 at NG + cb
 #pragma unroll
@@ -670,6 +655,29 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                     acc[f][NG + cb][r] = p3 - p1 - p2;
                 }
     }
+    if constexpr (MODE == 1) {
+        // Product: this chunk's part of Y = T X for the wave's rows, summed over
+        // chunks by the finishing launch, as rows of nrr real columns with complex
+        // column c at (2c, 2c + 1): a three-product block's lane col holds column
+        // 16 cb + col (Re and Im from two blocks), a pair block's lane col real
+        // column 32 NG + 16 pb + col. No barrier: the window is not reused.
+        T* yp = reinterpret_cast<T*>(part) + ((size_t)sk_i * P.rt * P.rows + k_first + kRowsPerWave * RF * wave) * P.nrr;
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T* yr = yp + (size_t)(kRowsPerWave * f + M::row(g, r)) * P.nrr;
+#pragma unroll
+                for (int cb = 0; cb < NG; ++cb) {
+                    yr[2 * (16 * cb + col)] = acc[f][cb][r];
+                    yr[2 * (16 * cb + col) + 1] = acc[f][NG + cb][r];
+                }
+#pragma unroll
+                for (int pb = 0; pb < NP; ++pb) yr[32 * NG + 16 * pb + col] = acc[f][3 * NG + pb][r];
+            }
+        return;
+    }
+
     // Rows past the last row of the product (padding of the last row tile) hold
     // copies of that row's sums; they must not meet the shifted U_l rows below.
     const int wrow0 = k_first + kRowsPerWave * RF * wave;
@@ -842,11 +850,11 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_split(PencilPlan P, Til
 
 // Y = T X (or T^* X) for a block of columns: tiles of the product, partial
 // over the K chunks (summed by toeplitz_mm_finish).
-template <typename T, int NB, int RF>
+template <typename T, int NB, int RF, int NG>
 __global__ __launch_bounds__(kThreads) void toeplitz_mm_tiles(PencilPlan P, TilePtrs<T> ptr) {
     const int id = blockIdx.x;
     const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
-    tile_body<T, NB, RF, 1>(P, ptr, L);
+    tile_body<T, NB, RF, 1, false, NG>(P, ptr, L);
 }
 
 // Y[k, c] = sum over chunks s (in order) of the partial real columns 2c, 2c+1, FP64.
@@ -856,8 +864,8 @@ __global__ __launch_bounds__(256) void toeplitz_mm_finish(PencilPlan P, const T*
     const int o = blockIdx.x * 256 + threadIdx.x;
     if (o >= P.N * P.C) return;
     const int k = o / P.C, c = o - (o / P.C) * P.C;
-    const size_t slab = (size_t)P.rt * P.rows * P.nrp;
-    const T* src = part + (size_t)k * P.nrp + 2 * c;
+    const size_t slab = (size_t)P.rt * P.rows * P.nrr;
+    const T* src = part + (size_t)k * P.nrr + 2 * c;
     double re = 0.0, im = 0.0;
     for (int s2 = 0; s2 < P.sk; ++s2) {
         re += (double)src[s2 * slab];
@@ -945,7 +953,7 @@ PlanBytes plan_bytes(const PencilPlan& P, size_t tsize) {
     b.u = align_up(t2 * ((size_t)P.ug + (size_t)P.rt * P.rows) * P.mbi * 16, 256);
     b.g = align_up(4 * ((size_t)P.sk * P.kc + kPrefetchRows), 256);
     if (P.mode)   // partial Y rows of every chunk, real columns
-        b.p = align_up(tsize * (size_t)P.sk * P.rt * P.rows * P.nrp, 256);
+        b.p = align_up(tsize * (size_t)P.sk * P.rt * P.rows * P.nrr, 256);
     else
         b.p = align_up(t2 * (size_t)P.nwg * P.m * P.C, 256);
     return b;
@@ -986,12 +994,13 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.C = P.ells * m;
     P.CB = m;
     P.ng = 0;
-    if (mode == 0 && !split && allow_gauss) {
+    if (!split && allow_gauss) {
         P.ng = m / 16;
         if (m - 16 * P.ng > 8) ++P.ng;
     }
     P.nb = P.ng + (2 * std::max(0, P.CB - 16 * P.ng) + 15) / 16;
     P.nrp = 16 * P.nb;
+    P.nrr = 32 * P.ng + 16 * (P.nb - P.ng);
     P.mbi = mode ? 0 : (m + 15) / 16;
     P.NR = mode ? P.N : (int)ipow(n + 2, d);
     P.ug = mode ? 0 : (int)ipow(n + 2, d - 1);
@@ -1049,7 +1058,7 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     if (((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp >= (int64_t(1) << 31) ||
         (int64_t)P.nwg * P.m * P.C >= (int64_t(1) << 31) ||
         ((int64_t)P.ug + (int64_t)P.rt * P.rows) * P.mbi * 16 >= (int64_t(1) << 31) ||
-        (int64_t)P.sk * P.rt * P.rows * P.nrp >= (int64_t(1) << 31))
+        (int64_t)P.sk * P.rt * P.rows * P.nrr >= (int64_t(1) << 31))
         return fail(h, PRONY_ENOTSUP, "prony_build_S: problem too large for 32-bit tile indexing");
     const PlanBytes b = plan_bytes(P, tsize);
     P.off_v = 0;
@@ -1134,15 +1143,12 @@ struct WorkItem {
 template <typename T>
 __device__ __forceinline__ void tile_of_class(const BatchEntry<T>& e, int L) {
     switch (e.P.ng * 16 + e.P.nb * 2 + e.P.rf - 1) {
-#define PRONY_QCASE(NBV)                                           \
-    case NBV * 2:                                                  \
-        tile_body<T, NBV, 1, 0>(e.P, e.ptr, L);                    \
-        break;                                                     \
-    case NBV * 2 + 1:                                              \
-        if constexpr (rf2_supported(sizeof(T), NBV)) tile_body<T, NBV, 2, 0>(e.P, e.ptr, L); \
-        break;
-        PRONY_NB_CASES(PRONY_QCASE)
-#undef PRONY_QCASE
+        case 2:   // one pair block (m <= 8)
+            tile_body<T, 1, 1, 0>(e.P, e.ptr, L);
+            break;
+        case 3:
+            tile_body<T, 1, 2, 0>(e.P, e.ptr, L);
+            break;
 #define PRONY_QGCASE(NBV, NGV)                                                     \
     case NGV * 16 + NBV * 2:                                                       \
         tile_body<T, NBV, 1, 0, false, NGV>(e.P, e.ptr, L);                        \
@@ -1193,27 +1199,27 @@ prony_status_t dispatch_tiles(prony_handle_t h, const PencilPlan& P, const TileP
                 return fail(h, PRONY_ENOTSUP, "prony_build_S: too many columns");
         }
     }
-    switch (P.nb) {
+    if constexpr (sizeof(T) == 4)
+        if (P.split) {   // pair blocks only
+            switch (P.nb) {
 #define PRONY_CASE(NBV)                                                    \
     case NBV:                                                              \
-        if constexpr (sizeof(T) == 4)                                      \
-            if (P.split) {                                                 \
-                if constexpr (rf_supported(4, NBV, 4, true))               \
-                    if (P.rf == 4) return launch_tiles_split<NBV, 4>(h, P, ptr); \
-                if constexpr (rf_supported(4, NBV, 2, true))               \
-                    if (P.rf == 2) return launch_tiles_split<NBV, 2>(h, P, ptr); \
-                return launch_tiles_split<NBV, 1>(h, P, ptr);              \
-            }                                                              \
-        if constexpr (rf_supported(sizeof(T), NBV, 4))                     \
-            if (P.rf == 4) return launch_tiles<T, NBV, 4>(h, P, ptr);      \
-        if constexpr (rf2_supported(sizeof(T), NBV))                       \
-            if (P.rf == 2) return launch_tiles<T, NBV, 2>(h, P, ptr);      \
-        return launch_tiles<T, NBV, 1>(h, P, ptr);
-        PRONY_NB_CASES(PRONY_CASE)
+        if constexpr (rf_supported(4, NBV, 4, true))                       \
+            if (P.rf == 4) return launch_tiles_split<NBV, 4>(h, P, ptr);   \
+        if constexpr (rf_supported(4, NBV, 2, true))                       \
+            if (P.rf == 2) return launch_tiles_split<NBV, 2>(h, P, ptr);   \
+        return launch_tiles_split<NBV, 1>(h, P, ptr);
+                PRONY_NB_CASES(PRONY_CASE)
 #undef PRONY_CASE
-        default:
-            return fail(h, PRONY_ENOTSUP, "prony_build_S: too many columns");
-    }
+                default:
+                    return fail(h, PRONY_ENOTSUP, "prony_build_S: too many columns");
+            }
+        }
+    // without three-product blocks: one pair block (m <= 8)
+    if (P.nb != 1) return fail(h, PRONY_ENOTSUP, "prony_build_S: unexpected column blocks");
+    if (P.rf == 4) return launch_tiles<T, 1, 4>(h, P, ptr);
+    if (P.rf == 2) return launch_tiles<T, 1, 2>(h, P, ptr);
+    return launch_tiles<T, 1, 1>(h, P, ptr);
 }
 
 template <typename T>
@@ -1232,17 +1238,10 @@ prony_status_t dispatch_batched(prony_handle_t h, int nb, int rf, int ng, const 
                 return fail(h, PRONY_ENOTSUP, "prony_build_S_batched: too many columns");
         }
     }
-    switch (nb) {
-#define PRONY_CASE(NBV)                                                                        \
-    case NBV:                                                                                  \
-        if constexpr (rf2_supported(sizeof(T), NBV))                                           \
-            if (rf == 2) return launch_batched<T, NBV, 2>(h, entries, count, tiles, lds, stream); \
-        return launch_batched<T, NBV, 1>(h, entries, count, tiles, lds, stream);
-        PRONY_NB_CASES(PRONY_CASE)
-#undef PRONY_CASE
-        default:
-            return fail(h, PRONY_ENOTSUP, "prony_build_S_batched: too many columns");
-    }
+    // without three-product blocks: one pair block (m <= 8)
+    if (nb != 1) return fail(h, PRONY_ENOTSUP, "prony_build_S_batched: unexpected column blocks");
+    if (rf == 2) return launch_batched<T, 1, 2>(h, entries, count, tiles, lds, stream);
+    return launch_batched<T, 1, 1>(h, entries, count, tiles, lds, stream);
 }
 
 // The three launches of one S-build with the packed operands and partial sums in
@@ -1299,33 +1298,41 @@ prony_status_t launch_pencil(prony_handle_t h, const PencilPlan& P, unsigned cha
     return launch_tiles_finish<T>(h, P, ws, ws + P.off_p, f, sigma, S);
 }
 
-template <typename T, int NB, int RF>
+template <typename T, int NB, int RF, int NG = 0>
 prony_status_t launch_mm_tiles(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
     if (P.lds_bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&toeplitz_mm_tiles<T, NB, RF>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&toeplitz_mm_tiles<T, NB, RF, NG>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
         if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
     }
     ProfileScope prof(h, "toeplitz_mm_tiles");
-    toeplitz_mm_tiles<T, NB, RF><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
+    toeplitz_mm_tiles<T, NB, RF, NG><<<P.nwg, kThreads, P.lds_bytes, h->stream>>>(P, ptr);
     return PRONY_OK;
 }
 
-#define PRONY_MM_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+
+// (blocks, three-product blocks) of the products with three-product blocks, r <= 64
+#define PRONY_MM_MIXED_CASES(X) X(1, 1) X(2, 1) X(2, 2) X(3, 2) X(3, 3) X(4, 3) X(4, 4)
 
 template <typename T>
 prony_status_t dispatch_mm(prony_handle_t h, const PencilPlan& P, const TilePtrs<T>& ptr) {
-    switch (P.nb) {
-#define PRONY_CASE(NBV)                                               \
-    case NBV:                                                         \
-        if constexpr (rf2_supported(sizeof(T), NBV))                  \
-            if (P.rf == 2) return launch_mm_tiles<T, NBV, 2>(h, P, ptr); \
-        return launch_mm_tiles<T, NBV, 1>(h, P, ptr);
-        PRONY_MM_NB_CASES(PRONY_CASE)
-#undef PRONY_CASE
-        default:
-            return fail(h, PRONY_ENOTSUP, "prony_toeplitz_mm: too many columns");
+    if (P.ng) {
+        switch (P.ng * 16 + P.nb) {
+#define PRONY_GCASE(NBV, NGV)                                                    \
+    case NGV * 16 + NBV:                                                         \
+        if constexpr (rf_supported(sizeof(T), NBV, 2, false, NGV))               \
+            if (P.rf == 2) return launch_mm_tiles<T, NBV, 2, NGV>(h, P, ptr);    \
+        return launch_mm_tiles<T, NBV, 1, NGV>(h, P, ptr);
+            PRONY_MM_MIXED_CASES(PRONY_GCASE)
+#undef PRONY_GCASE
+            default:
+                return fail(h, PRONY_ENOTSUP, "prony_toeplitz_mm: too many columns");
+        }
     }
+    // without three-product blocks: one pair block (r <= 8)
+    if (P.nb != 1) return fail(h, PRONY_ENOTSUP, "prony_toeplitz_mm: unexpected column blocks");
+    if (P.rf == 2) return launch_mm_tiles<T, 1, 2>(h, P, ptr);
+    return launch_mm_tiles<T, 1, 1>(h, P, ptr);
 }
 
 template <typename T>
@@ -2056,7 +2063,7 @@ extern "C" prony_status_t prony_toeplitz_mm(prony_handle_t h, int d, int n, int 
     if (!g.ok) return fail(h, PRONY_EHIP, "hipSetDevice failed");
     PencilPlan P;
     const size_t ts = prec == PRONY_FP32 ? sizeof(float) : sizeof(double);
-    if ((st = make_plan(h, d, n, r, false, ts, P, 0, 0, 1)) != PRONY_OK) return st;
+    if ((st = make_plan(h, d, n, r, false, ts, P, 0, 0, 1, false, true)) != PRONY_OK) return st;
     P.conj_grid = adjoint;
     return prec == PRONY_FP32 ? launch_toeplitz_mm<float>(h, P, f, X, ldx, Y, ldy)
                               : launch_toeplitz_mm<double>(h, P, f, X, ldx, Y, ldy);
