@@ -107,7 +107,6 @@ struct PencilPlan {
     int rf;         // 16-row fragments per wave (1 or 2)
     int rows;       // rows k' per tile: 64 rf
     int rt;         // row tiles
-    int nbp;        // 16-column blocks per pass of the cross-wave sum
     int nwg;        // rt * sk workgroups
     int win_cap;    // window capacity (complex elements)
     int c0;         // grid offset of the origin shift
@@ -316,14 +315,14 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 
     extern __shared__ __align__(16) unsigned char smem[];
     // Phase 1 (K loop): grid window + h' offsets. Phase 2 (U^* reduction): the
-    // same bytes hold one slab of results per wave.
+    // same bytes hold the tile's rows of Z (S-build).
     // window entries: complex<T>, or for split operands 16 bytes
     // (Re h | Im h, Re m | Im m, Re l | Im l, 0) as bfloat16 pairs
     constexpr size_t kEntry = SPLIT ? 16 : sizeof(T2);
     T2* win = reinterpret_cast<T2*>(smem);
     u32x4* win16 = reinterpret_cast<u32x4*>(smem);
     int* gt = reinterpret_cast<int*>(smem + align_up(kEntry * (size_t)P.win_cap, 16));
-    T* slab = reinterpret_cast<T*>(smem);
+    T* zpl = reinterpret_cast<T*>(smem);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -344,8 +343,9 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 
     // Stage the window (converted to T) and the h' offsets, kStage loads per
     // thread in flight. The offsets are stored transposed per lane group:
-    // gt[g * stride + s] = G(h' = h_first + 4 s + g), so one 16-byte LDS read
-    // gives a lane the offsets of four consecutive K steps.
+    // gt[g * stride + s] = G(h' = h_first + 4 s + g) (in bytes of a window entry,
+    // except for split operands), so one 16-byte LDS read gives a lane the offsets
+    // of four consecutive K steps.
     constexpr int kStage = 8;
     const int ngt = SPLIT ? P.kc : P.kc + kPrefetchRows;
     const int gstride = ngt >> 2;
@@ -372,7 +372,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                 if (w < ngt) gt[(w & ~31) | ((w & 3) << 3) | ((w & 31) >> 2)] = o[j];
             } else {
                 if (w < W) win[w] = T2{(T)v[j].x, reflect ? -(T)v[j].y : (T)v[j].y};
-                if (w < ngt) gt[(w & 3) * gstride + (w >> 2)] = o[j];
+                if (w < ngt) gt[(w & 3) * gstride + (w >> 2)] = o[j] * (int)sizeof(T2);   // bytes
             }
         }
     }
@@ -395,9 +395,18 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // Rows of this wave: k_first + 16 (RF wave + f) + col for fragment f (rows past
     // the last read the last row's offsets; their results are discarded).
     const int krow0 = k_first + kRowsPerWave * RF * wave + col;
+    // window offsets of the fragments' rows (split operands: entries; otherwise LDS
+    // byte addresses, with the staged h' offsets in bytes, so that an A address is
+    // one subtraction)
+    typedef T vec2_t __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const vec2_t lds_t2;
+    const int lds_base = (int)(size_t)(__attribute__((address_space(3))) unsigned char*)smem;
     int gk[RF];
 #pragma unroll
-    for (int f = 0; f < RF; ++f) gk[f] = row_offset(P, min(krow0 + kRowsPerWave * f, P.NR - 1)) + P.c0 - lo;
+    for (int f = 0; f < RF; ++f) {
+        gk[f] = row_offset(P, min(krow0 + kRowsPerWave * f, P.NR - 1)) + P.c0 - lo;
+        if constexpr (!SPLIT) gk[f] = gk[f] * (int)sizeof(T2) + lds_base;
+    }
 
     acc_t acc[RF][NA];
 #pragma unroll
@@ -417,7 +426,10 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     T2 b[kDepth][NB];
     auto load_a = [&](T2* dst, int off) {
 #pragma unroll
-        for (int f = 0; f < RF; ++f) dst[f] = win[gk[f] - off];
+        for (int f = 0; f < RF; ++f) {
+            const vec2_t e = *(lds_t2*)(size_t)(unsigned)(gk[f] - off);
+            dst[f] = T2{e.x, e.y};
+        }
     };
     auto load_b = [&](T2* dst, int step) {
         const T2* src = vrow + (size_t)step * kstride;
@@ -445,9 +457,14 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // Im a)(Re v + Im v) for those, the pair MFMAs for the rest; the Re-multiplier
     // MFMAs of every block first, so that dependent MFMAs sit apart.
     auto mma_g = [&](const T2* av, const T2* bv) {
-        T bsum[NG > 0 ? NG : 1];
+        // the operand sums first, as one group: a VALU operation between this wave's
+        // MFMAs leaves the matrix core idle for about its latency (measured)
+        T bsum[NG > 0 ? NG : 1], asum[RF];
 #pragma unroll
         for (int cb = 0; cb < NG; ++cb) bsum[cb] = bv[cb].x + bv[cb].y;
+#pragma unroll
+        for (int f = 0; f < RF; ++f) asum[f] = av[f].x + av[f].y;
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int f = 0; f < RF; ++f) {
 #pragma unroll
@@ -464,9 +481,8 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         }
 #pragma unroll
         for (int f = 0; f < RF; ++f) {
-            const T asum = av[f].x + av[f].y;
 #pragma unroll
-            for (int cb = 0; cb < NG; ++cb) acc[f][2 * NG + cb] = M::fma(asum, bsum[cb], acc[f][2 * NG + cb]);
+            for (int cb = 0; cb < NG; ++cb) acc[f][2 * NG + cb] = M::fma(asum[f], bsum[cb], acc[f][2 * NG + cb]);
         }
     };
     auto ring_step = [&](T2* ad, int off, T2* bd, int bs, const T2* av, const T2* bv) {
@@ -691,146 +707,204 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                     for (int cb = 0; cb < NA; ++cb) acc[f][cb][r] = T(0);
     }
 
-    // Reductions with the shifted U_l over this wave's rows: for every 16-row block
-    // ib of U_l^* and every stored matrix l, e = U_l[rows]^* Z[rows], with
-    // U_l[k'] = packed U row ug + k' - shift(e_l). The accumulators are the second
-    // MFMA operand directly: element r of lane (g, col) of fragment f is
-    // Z[16 f + row(g,r)][16cb+col] (rows relative to the wave's first row).
-    // Output column 2c gets Re(U_l^* Z)_c and 2c+1 gets Im: with the partner lane's
-    // value y' (column j^1), Re = Ur.Yr + Ui.Yi and Im = Ur.Yi - Ui.Yr.
-    // Items are the (block, matrix) pairs in block-major order. The U pairs of the
-    // first item are requested before the barrier, so their latency overlaps the
-    // other waves' K loops; later ones one item ahead, into the other of two
-    // register sets. A pass covers as many items as the slabs hold; within it the
-    // loads are unconditional (a pass's last item requests a pair set it does not
-    // use) and the sets alternate in a loop unrolled by two whose body holds no
-    // other memory operation: every path to an item's products then has the same
-    // loads in flight, and the wait counters make it wait for its own pairs only.
+    // Reductions with the shifted U_l. Item (ib, l) is the 16 x m block
+    // e(i, c) = sum over the tile's rows k' of conj(U_l[k'][16 ib + i]) Z[k'][c], with
+    // U_l[k'] = packed U row ug + k' - shift(e_l); items are numbered block-major.
+    // The waves first store their rows of Z in LDS (the window is dead by then) as
+    // two planes, Re and Im, of one 16-column slot per column block, laid out as the
+    // MFMA's second operand: [K step s][slot][row 4 s + k][column], so that a read
+    // is 64 consecutive elements. Then each wave takes whole units (wave, wave + 4,
+    // ...) and runs their MFMAs itself. A unit is an item over all kRows / 4 K steps
+    // of the tile when there are 3 or more items; with 1 or 2 items it is one of rs =
+    // 4 / items parts of an item's K steps (at most one per group of steps), so that
+    // no wave idles, and the parts are added in part order through LDS before the
+    // store.
+    // The first operand (lane (k, i) of step s: U_l[4 s + k][16 ib + i]) comes in
+    // groups of GS steps, two groups in flight in two register sets. The loads are
+    // unconditional (clamped to the wave's last group and to the last item) and the
+    // first two are issued before the barrier, so that their latency overlaps the
+    // other waves' K loops and every path to a group's MFMAs has the same loads in
+    // flight. Three-product blocks: conj(U) Z as Q1 = Ur Zr, Q2 = (-Ui) Zi,
+    // Q3 = (Ur - Ui)(Zr + Zi), Re = Q1 - Q2, Im = Q3 - Q1 - Q2. Pair blocks: lane
+    // column n is complex column n / 2 of the block, real part for even n and
+    // imaginary part for odd n, from Ur [Zr | Zi] + Ui [Zi | -Zr].
+    constexpr int KS = kRows / 4;                                   // K steps over the tile's rows
+    constexpr int kGroup = (int)(128 / sizeof(T2));                 // 128 bytes of operands per lane
+    constexpr int GS = KS / 2 < kGroup ? KS / 2 : kGroup;           // steps per group
+    constexpr int NGR = KS / GS;                                    // groups per item (2, 4 or 8)
+    static_assert(MODE == 1 || 2 * kRows * 16 * NB * sizeof(T) <= 65536, "Z planes above 64 KiB");
+    T* const zre = zpl;
+    T* const zim = zpl + KS * NB * 64;
     const int mup = P.mbi * 16;
-    const T2* ubase = up + (size_t)(P.ug + wrow0) * mup + col;
     const int items = P.mbi * P.ells;
-    auto load_u = [&](T2 (&u)[RF][4], int it) {
-        it = min(it, items - 1);
+    constexpr int kLgr = __builtin_ctz(NGR);
+    const int lrs = items >= 3 ? 0 : min(items == 2 ? 1 : 2, kLgr);   // log2 of the parts per item
+    const int lgpu = kLgr - lrs;                                    // log2 of the groups per unit
+    const int units = items << lrs;
+    const int total = (units > wave ? (units - wave + kWaves - 1) / kWaves : 0) << lgpu;
+    const int xlast = max(total, 1) - 1;
+    const T2* ubase = up + (size_t)(P.ug + k_first + g) * mup + col;
+    // unit u = wave + 4 j of the wave's x-th group: item u >> lrs, part u & (rs - 1)
+    auto unit_of = [&](int x) { return wave + kWaves * (x >> lgpu); };
+    auto load_g = [&](T2 (&u)[GS], int x) {
+        x = min(x, xlast);
+        const int un = min(unit_of(x), units - 1);
+        const int it = un >> lrs, grp = ((un & ((1 << lrs) - 1)) << lgpu) | (x & ((1 << lgpu) - 1));
         const int ib = it / P.ells, li = it - ib * P.ells;
-        const T2* src = ubase - (size_t)rowext_shift(P, li + P.first_ell) * mup + ib * 16;
+        const T2* src = ubase + (ptrdiff_t)(4 * GS * grp - rowext_shift(P, li + P.first_ell)) * mup + ib * 16;
 #pragma unroll
-        for (int f = 0; f < RF; ++f)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) u[f][r] = src[(size_t)(kRowsPerWave * f + M::row(g, r)) * mup];
+        for (int s = 0; s < GS; ++s) u[s] = src[(size_t)(4 * s) * mup];
     };
-    T2 ua[RF][4], ub[RF][4];
+    T2 ua[GS], ub[GS];
     // the K loop's last steps prefetched operands nobody reads; let them land
-    // before the pair registers are written (same reason as at the pass end)
+    // before these registers are written
     __builtin_amdgcn_s_waitcnt(0x0F70);
-    load_u(ua, 0);
-    __syncthreads();   // the window is dead from here on; its bytes become the slabs
-
-    // Every wave writes the blocks of slot q of a pass into its own slab
-    // (lane-major, conflict free): virtual 16-column blocks q SB + b. A pass holds
-    // ipp items (nbp >= SB blocks per wave); after one barrier all threads add the
-    // four slabs in wave order and store the partial pairs of the pass.
-    // Three-product blocks: conj(U) Z with the products Q1 = Ur Zr, Q2 = (-Ui) Zi,
-    // Q3 = (Ur - Ui)(Zr + Zi), so Re = Q1 - Q2 and Im = Q3 - Q1 - Q2, stored as a
-    // Re block and an Im block; pair blocks as one block of (Re, Im) columns.
-    constexpr int SB = 2 * NG + NP;               // slab blocks per item
-    auto products = [&](const T2 (&u)[RF][4], int q) {
-        if constexpr (NG > 0) {
-            acc_t e1[NG], e2[NG], e3[NG];
+    load_g(ua, 0);
+    load_g(ub, 1);
+    __syncthreads();   // the window is dead from here on; its bytes become the Z planes
 #pragma unroll
-            for (int cb = 0; cb < NG; ++cb) e1[cb] = e2[cb] = e3[cb] = acc_t{0, 0, 0, 0};
+    for (int f = 0; f < RF; ++f)
 #pragma unroll
-            for (int f = 0; f < RF; ++f)
+        for (int r = 0; r < 4; ++r) {
+            const int t = kRowsPerWave * (RF * wave + f) + M::row(g, r);   // row of the tile
+            const int zo = (t >> 2) * NB * 64 + (t & 3) * 16;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const T ur = u[f][r].x, ui = -u[f][r].y, us = ur + ui;
+            for (int cb = 0; cb < NG; ++cb) {
+                zre[zo + cb * 64 + col] = acc[f][cb][r];
+                zim[zo + cb * 64 + col] = acc[f][NG + cb][r];
+            }
 #pragma unroll
-                    for (int cb = 0; cb < NG; ++cb) {
-                        const T zr = acc[f][cb][r], zi = acc[f][NG + cb][r];
-                        e1[cb] = M::fma(ur, zr, e1[cb]);
-                        e2[cb] = M::fma(ui, zi, e2[cb]);
-                        e3[cb] = M::fma(us, zr + zi, e3[cb]);
-                    }
-                }
-#pragma unroll
-            for (int cb = 0; cb < NG; ++cb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    slab[((wave * P.nbp + q * SB + 2 * cb) * 4 + r) * 64 + lane] = e1[cb][r] - e2[cb][r];
-                    slab[((wave * P.nbp + q * SB + 2 * cb + 1) * 4 + r) * 64 + lane] =
-                        e3[cb][r] - e1[cb][r] - e2[cb][r];
-                }
+            for (int pb = 0; pb < NP; ++pb) (odd ? zim : zre)[zo + (NG + pb) * 64 + (col >> 1)] = acc[f][3 * NG + pb][r];
         }
-        if constexpr (NP > 0) {
-            acc_t e[NP];
+    __syncthreads();
+
+    // Accumulators in two sets, [0] for even and [1] for odd K steps, and the two
+    // products of a pair block in two of them, so that the MFMAs issued back to back
+    // are independent (a single 16-row block per item has no fragments to alternate).
+    constexpr int NGa = NG > 0 ? NG : 1, NPa = NP > 0 ? NP : 1;
+    constexpr int NV = 8 * NG + 4 * NP;   // result values of a unit per lane
+    acc_t e1[2][NGa], e2[2][NGa], e3[2][NGa], epr[2][NPa], epi[2][NPa];
+    T res[NV];   // unit result: (Re, Im) of the three-product blocks' rows, then the pair values
+    T* const out = reinterpret_cast<T*>(part + (size_t)L * P.m * P.C);
+    // output row 16 ib + row(g, r), lane column col
+    auto store_item = [&](int it) {
+        const int ib = it / P.ells, li = it - ib * P.ells;
 #pragma unroll
-            for (int pb = 0; pb < NP; ++pb) e[pb] = acc_t{0, 0, 0, 0};
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * ib + M::row(g, r);
+            if (i >= P.m) continue;
+            T* orow = out + 2 * ((size_t)i * P.C + li * P.m);
 #pragma unroll
-            for (int f = 0; f < RF; ++f)
+            for (int cb = 0; cb < NG; ++cb) {
+                const int c = 16 * cb + col;
+                if (c < P.m) reinterpret_cast<T2*>(orow)[c] = T2{res[8 * cb + 2 * r], res[8 * cb + 2 * r + 1]};
+            }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-#pragma unroll
-                    for (int pb = 0; pb < NP; ++pb) {
-                        const T y = acc[f][3 * NG + pb][r];
-                        const T ys = swap_lane_pair(y);
-                        e[pb] = M::fma(u[f][r].x, y, e[pb]);
-                        e[pb] = M::fma(u[f][r].y, odd ? -ys : ys, e[pb]);
-                    }
-                }
-#pragma unroll
-            for (int pb = 0; pb < NP; ++pb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    slab[((wave * P.nbp + q * SB + 2 * NG + pb) * 4 + r) * 64 + lane] = e[pb][r];
+            for (int pb = 0; pb < NP; ++pb) {
+                const int c = 16 * NG + 8 * pb + (col >> 1);
+                if (c < P.m) orow[2 * c + (col & 1)] = res[8 * NG + 4 * pb + r];
+            }
         }
     };
-    const T2* slab2 = reinterpret_cast<const T2*>(slab);
-    const int ipp = max(1, P.nbp / SB);
-    T2* out = part + (size_t)L * P.m * P.C;
-    for (int p0 = 0; p0 < items; p0 += ipp) {
-        const int np = min(ipp, items - p0);
-        if (p0 > 0) load_u(ua, p0);
-        for (int q = 0; q < np; q += 2) {
-            load_u(ub, p0 + q + 1);
-            __builtin_amdgcn_sched_barrier(0);
-            products(ua, q);
-            if (q + 1 == np) break;
-            load_u(ua, p0 + q + 2);
-            __builtin_amdgcn_sched_barrier(0);
-            products(ub, q + 1);
-        }
-        // the pass's last item requested a set it does not use: wait for it here
-        // (vmcnt 0, other counters free), so that no load into those registers is
-        // in flight on the next pass's paths and their wait counters stay exact
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        __syncthreads();
-        for (int o = tid; o < np * 16 * P.m; o += kThreads) {
-            const int q = o / (16 * P.m), rem = o - q * (16 * P.m);
-            const int il = rem / P.m, c = rem - il * P.m;
-            const int it = p0 + q, ib = it / P.ells, li = it - ib * P.ells;
-            if (ib * 16 + il >= P.m) continue;
-            T2 sum;
-            if (c < 16 * NG) {   // Re in block 2 (c / 16), Im in the next block, column c % 16
-                const int s0 = ((q * SB + 2 * (c >> 4)) * 4 + M::elem_of_row(il)) * 64 + M::group_of_row(il) * 16 +
-                               (c & 15);
-                sum = T2{slab[s0], slab[s0 + 256]};
-                for (int w = 1; w < kWaves; ++w) {
-                    sum.x += slab[s0 + w * P.nbp * 256];
-                    sum.y += slab[s0 + w * P.nbp * 256 + 256];
-                }
-            } else {
-                const int j = 2 * (c - 16 * NG);   // Re in pair column j, Im in j + 1 (lane + 1)
-                const int s0 = ((q * SB + 2 * NG + (j >> 4)) * 4 + M::elem_of_row(il)) * 64 +
-                               M::group_of_row(il) * 16 + (j & 15);
-                sum = slab2[s0 >> 1];
-                for (int w = 1; w < kWaves; ++w) {
-                    const T2 v = slab2[(s0 + w * P.nbp * 256) >> 1];
-                    sum.x += v.x;
-                    sum.y += v.y;
-                }
+    auto group = [&](const T2 (&u)[GS], int x) {
+        const int un = unit_of(x), gi = x & ((1 << lgpu) - 1);
+        const int grp = ((un & ((1 << lrs) - 1)) << lgpu) | gi;
+        if (gi == 0) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int cb = 0; cb < NG; ++cb) e1[h][cb] = e2[h][cb] = e3[h][cb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+                for (int pb = 0; pb < NP; ++pb) epr[h][pb] = epi[h][pb] = acc_t{0, 0, 0, 0};
             }
-            out[(size_t)(ib * 16 + il) * P.C + li * P.m + c] = sum;
         }
-        if (p0 + np < items) __syncthreads();   // slabs are rewritten by the next pass
+        // second operands of step s (three-product blocks: Zr, Zi of lane column;
+        // pair blocks: Zr, Zi of complex column col / 2), read one step ahead
+        auto zread = [&](int s, T (&zr)[NB], T (&zi)[NB]) {
+            const int zs = (GS * grp + s) * NB * 64;
+#pragma unroll
+            for (int cb = 0; cb < NG; ++cb) {
+                zr[cb] = zre[zs + cb * 64 + lane];
+                zi[cb] = zim[zs + cb * 64 + lane];
+            }
+#pragma unroll
+            for (int pb = 0; pb < NP; ++pb) {
+                const int zp = zs + (NG + pb) * 64 + g * 16 + (col >> 1);
+                zr[NG + pb] = zre[zp];
+                zi[NG + pb] = zim[zp];
+            }
+        };
+        auto step = [&](int s, const T (&zr)[NB], const T (&zi)[NB]) {
+            const T ur = u[s].x, ui = u[s].y;
+            const int h = s & 1;
+#pragma unroll
+            for (int cb = 0; cb < NG; ++cb) {
+                e1[h][cb] = M::fma(ur, zr[cb], e1[h][cb]);
+                e2[h][cb] = M::fma(-ui, zi[cb], e2[h][cb]);
+                e3[h][cb] = M::fma(ur - ui, zr[cb] + zi[cb], e3[h][cb]);
+            }
+#pragma unroll
+            for (int pb = 0; pb < NP; ++pb) {
+                const T zr_ = zr[NG + pb], zi_ = zi[NG + pb];
+                epr[h][pb] = M::fma(ur, odd ? zi_ : zr_, epr[h][pb]);
+                epi[h][pb] = M::fma(ui, odd ? -zr_ : zi_, epi[h][pb]);
+            }
+        };
+        T zra[NB], zia[NB], zrb[NB], zib[NB];
+        // (the scheduling barriers keep the reads ahead of the previous step's MFMAs)
+        zread(0, zra, zia);
+#pragma unroll
+        for (int s = 0; s < GS; s += 2) {   // GS is even
+            zread(s + 1, zrb, zib);
+            __builtin_amdgcn_sched_barrier(0);
+            step(s, zra, zia);
+            if (s + 2 < GS) zread(s + 2, zra, zia);
+            __builtin_amdgcn_sched_barrier(0);
+            step(s + 1, zrb, zib);
+        }
+        if (gi == (1 << lgpu) - 1) {   // the unit is complete
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                for (int cb = 0; cb < NG; ++cb) {
+                    const T q1 = e1[0][cb][r] + e1[1][cb][r], q2 = e2[0][cb][r] + e2[1][cb][r];
+                    const T q3 = e3[0][cb][r] + e3[1][cb][r];
+                    res[8 * cb + 2 * r] = q1 - q2;
+                    res[8 * cb + 2 * r + 1] = q3 - q1 - q2;
+                }
+#pragma unroll
+                for (int pb = 0; pb < NP; ++pb)
+                    res[8 * NG + 4 * pb + r] = (epr[0][pb][r] + epr[1][pb][r]) + (epi[0][pb][r] + epi[1][pb][r]);
+            }
+            if (lrs == 0) store_item(un);
+        }
+    };
+    for (int x = 0; x < total; x += 2) {
+        group(ua, x);
+        load_g(ua, x + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        if (x + 1 == total) break;
+        group(ub, x + 1);
+        load_g(ub, x + 3);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (lrs > 0) {
+        // at most one unit per wave: part wave & (rs - 1) of item wave >> lrs; parts
+        // 1.. go through LDS (the Z planes are free once every wave is past its
+        // MFMAs) and part 0 adds them in part order and stores the item
+        const int pt = wave & ((1 << lrs) - 1);
+        __syncthreads();
+        if (pt > 0 && wave < units) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) zpl[((wave - 1) * NV + v) * 64 + lane] = res[v];
+        }
+        __syncthreads();
+        if (pt == 0 && wave < units) {
+            for (int q = 1; q < (1 << lrs); ++q)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) res[v] += zpl[((wave + q - 1) * NV + v) * 64 + lane];
+            store_item(wave >> lrs);
+        }
     }
 }
 template <typename T, int NB, int RF, int NG>
@@ -917,11 +991,10 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntr
     tile_body<T, NB, RF, 0, false, NG>(e.P, e.ptr, id - e.tile_begin);
 }
 
-size_t lds_bytes_for(int win, int kc, int nbp, size_t tsize, int split_nrp = 0, int bbufs = 2) {
+size_t lds_bytes_for(int win, int kc, size_t epi, size_t tsize, int split_nrp = 0, int bbufs = 2) {
     const size_t entry = split_nrp ? 16 : 2 * tsize;
     const size_t loop = align_up(entry * (size_t)win, 16) + align_up(4 * ((size_t)kc + kPrefetchRows + 16), 16) +
                         (split_nrp ? (size_t)bbufs * kSplitPlanes * split_nrp * 64 : 0);
-    const size_t epi = tsize * (size_t)kWaves * 16 * 16 * nbp;   // one 16 x 16nbp slab per wave
     return align_up(std::max(loop, epi), 16);
 }
 
@@ -1013,12 +1086,11 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.c0 = grid_center(d, n);
 
     // two workgroups per CU; the split kernel, which also stages B planes, may
-    // take the whole LDS when its window does not fit otherwise. The epilogue's
-    // slabs hold nbp 16-column blocks per wave: whole items (NB blocks each), at
-    // least one, at most all mbi * ells of them.
+    // take the whole LDS when its window does not fit otherwise. The S-build's
+    // epilogue holds the tile's rows of Z as two planes of one 16-column slot per
+    // column block, at most 64 KiB for every instantiated shape.
     size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
-    const int sb = P.nb + P.ng;   // slab blocks per item (three-product blocks: Re and Im)
-    P.nbp = sb * std::max(1, std::min(P.mbi * P.ells, (int)(budget / (tsize * kWaves * 16 * 16)) / sb));
+    const size_t epi = mode ? 0 : 2 * (size_t)P.rows * 16 * P.nb * tsize;
     P.bbufs = 2;
     const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
@@ -1030,10 +1102,10 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     for (;;) {
         const int colspan = max_span(P.kb, kc, d, n, false);
         const int win = rowspan + colspan + 1;
-        size_t lds = lds_bytes_for(win, kc, mode ? 0 : P.nbp, tsize, split ? P.nrp : 0, 2);
+        size_t lds = lds_bytes_for(win, kc, epi, tsize, split ? P.nrp : 0, 2);
         if (split && lds > budget) {   // one B buffer (two barriers per K block) before smaller chunks
             P.bbufs = 1;
-            lds = lds_bytes_for(win, kc, mode ? 0 : P.nbp, tsize, P.nrp, 1);
+            lds = lds_bytes_for(win, kc, epi, tsize, P.nrp, 1);
         }
         if (lds <= budget) {
             P.kc = kc;
