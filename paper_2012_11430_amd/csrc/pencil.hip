@@ -83,6 +83,12 @@ constexpr bool rf_supported(size_t tsize, int nb, int rf, bool split = false, in
            (rf == 4 && na <= (split ? 2 : (tsize == 4 ? 4 : 2)));
 }
 
+// Whether the S-build epilogue stores Zr + Zi of its three-product blocks as a third
+// LDS plane (when all planes of a tile of `rows` rows fit in 64 KiB).
+__host__ __device__ constexpr bool z_sum_plane(size_t tsize, int nb, int ng, int rows) {
+    return ng > 0 && (size_t)(2 * nb + ng) * rows * 16 * tsize <= 65536;
+}
+
 struct PencilPlan {
     int d, n, N, m;
     int mode;       // 0: S-build (row-extended k', shifted U^* epilogue); 1: product Y = T X
@@ -711,9 +717,12 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // e(i, c) = sum over the tile's rows k' of conj(U_l[k'][16 ib + i]) Z[k'][c], with
     // U_l[k'] = packed U row ug + k' - shift(e_l); items are numbered block-major.
     // The waves first store their rows of Z in LDS (the window is dead by then) as
-    // two planes, Re and Im, of one 16-column slot per column block, laid out as the
-    // MFMA's second operand: [K step s][slot][row 4 s + k][column], so that a read
-    // is 64 consecutive elements. Then each wave takes whole units (wave, wave + 4,
+    // the MFMA's second operands, in planes of one 16-column slot per column block
+    // laid out as [K step s][slot][row 4 s + k][column], so that a read is 64
+    // consecutive elements: three-product blocks as Zr, Zi and (where the LDS
+    // allows) Zr + Zi; pair blocks lane-ready, [Zr | Zi] and [Zi | -Zr] (lane column
+    // n is complex column n / 2 of the block, real part for even n, imaginary part
+    // for odd n). Then each wave takes whole units (wave, wave + 4,
     // ...) and runs their MFMAs itself. A unit is an item over all kRows / 4 K steps
     // of the tile when there are 3 or more items; with 1 or 2 items it is one of rs =
     // 4 / items parts of an item's K steps (at most one per group of steps), so that
@@ -724,17 +733,18 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // unconditional (clamped to the wave's last group and to the last item) and the
     // first two are issued before the barrier, so that their latency overlaps the
     // other waves' K loops and every path to a group's MFMAs has the same loads in
-    // flight. Three-product blocks: conj(U) Z as Q1 = Ur Zr, Q2 = (-Ui) Zi,
-    // Q3 = (Ur - Ui)(Zr + Zi), Re = Q1 - Q2, Im = Q3 - Q1 - Q2. Pair blocks: lane
-    // column n is complex column n / 2 of the block, real part for even n and
-    // imaginary part for odd n, from Ur [Zr | Zi] + Ui [Zi | -Zr].
+    // flight. Three-product blocks: conj(U) Z as Q1 = Ur Zr, Q2 = Ui Zi,
+    // Q3 = (Ur - Ui)(Zr + Zi), Re = Q1 + Q2, Im = Q3 - Q1 + Q2. Pair blocks:
+    // Ur [Zr | Zi] + Ui [Zi | -Zr].
     constexpr int KS = kRows / 4;                                   // K steps over the tile's rows
     constexpr int kGroup = (int)(128 / sizeof(T2));                 // 128 bytes of operands per lane
     constexpr int GS = KS / 2 < kGroup ? KS / 2 : kGroup;           // steps per group
     constexpr int NGR = KS / GS;                                    // groups per item (2, 4 or 8)
     static_assert(MODE == 1 || 2 * kRows * 16 * NB * sizeof(T) <= 65536, "Z planes above 64 KiB");
+    constexpr bool kZs = z_sum_plane(sizeof(T), NB, NG, kRows);   // Zr + Zi stored
     T* const zre = zpl;
     T* const zim = zpl + KS * NB * 64;
+    T* const zsm = zpl + 2 * KS * NB * 64;   // [s][three-product block][k][column]
     const int mup = P.mbi * 16;
     const int items = P.mbi * P.ells;
     constexpr int kLgr = __builtin_ctz(NGR);
@@ -772,9 +782,14 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
             for (int cb = 0; cb < NG; ++cb) {
                 zre[zo + cb * 64 + col] = acc[f][cb][r];
                 zim[zo + cb * 64 + col] = acc[f][NG + cb][r];
+                if constexpr (kZs) zsm[(t >> 2) * NG * 64 + (t & 3) * 16 + cb * 64 + col] = acc[f][cb][r] + acc[f][NG + cb][r];
             }
 #pragma unroll
-            for (int pb = 0; pb < NP; ++pb) (odd ? zim : zre)[zo + (NG + pb) * 64 + (col >> 1)] = acc[f][3 * NG + pb][r];
+            for (int pb = 0; pb < NP; ++pb) {
+                const T y = acc[f][3 * NG + pb][r];   // Zr (even col) or Zi (odd col) of complex column col / 2
+                zre[zo + (NG + pb) * 64 + col] = y;
+                zim[zo + (NG + pb) * 64 + (col ^ 1)] = odd ? y : -y;
+            }
         }
     __syncthreads();
 
@@ -818,49 +833,45 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                 for (int pb = 0; pb < NP; ++pb) epr[h][pb] = epi[h][pb] = acc_t{0, 0, 0, 0};
             }
         }
-        // second operands of step s (three-product blocks: Zr, Zi of lane column;
-        // pair blocks: Zr, Zi of complex column col / 2), read one step ahead
-        auto zread = [&](int s, T (&zr)[NB], T (&zi)[NB]) {
-            const int zs = (GS * grp + s) * NB * 64;
+        // second operands of step s (plane 0, plane 1 and, three-product blocks,
+        // the sum), read one step ahead
+        constexpr int NGa2 = NG > 0 ? NG : 1;
+        auto zread = [&](int s, T (&zr)[NB], T (&zi)[NB], T (&zz)[NGa2]) {
+            const int zs = (GS * grp + s) * NB * 64 + lane;
 #pragma unroll
-            for (int cb = 0; cb < NG; ++cb) {
-                zr[cb] = zre[zs + cb * 64 + lane];
-                zi[cb] = zim[zs + cb * 64 + lane];
+            for (int cb = 0; cb < NB; ++cb) {
+                zr[cb] = zre[zs + cb * 64];
+                zi[cb] = zim[zs + cb * 64];
             }
 #pragma unroll
-            for (int pb = 0; pb < NP; ++pb) {
-                const int zp = zs + (NG + pb) * 64 + g * 16 + (col >> 1);
-                zr[NG + pb] = zre[zp];
-                zi[NG + pb] = zim[zp];
-            }
+            for (int cb = 0; cb < NG; ++cb) zz[cb] = kZs ? zsm[(GS * grp + s) * NG * 64 + lane + cb * 64] : T(0);
         };
-        auto step = [&](int s, const T (&zr)[NB], const T (&zi)[NB]) {
+        auto step = [&](int s, const T (&zr)[NB], const T (&zi)[NB], const T (&zz)[NGa2]) {
             const T ur = u[s].x, ui = u[s].y;
             const int h = s & 1;
 #pragma unroll
             for (int cb = 0; cb < NG; ++cb) {
                 e1[h][cb] = M::fma(ur, zr[cb], e1[h][cb]);
-                e2[h][cb] = M::fma(-ui, zi[cb], e2[h][cb]);
-                e3[h][cb] = M::fma(ur - ui, zr[cb] + zi[cb], e3[h][cb]);
+                e2[h][cb] = M::fma(ui, zi[cb], e2[h][cb]);
+                e3[h][cb] = M::fma(ur - ui, kZs ? zz[cb] : zr[cb] + zi[cb], e3[h][cb]);
             }
 #pragma unroll
             for (int pb = 0; pb < NP; ++pb) {
-                const T zr_ = zr[NG + pb], zi_ = zi[NG + pb];
-                epr[h][pb] = M::fma(ur, odd ? zi_ : zr_, epr[h][pb]);
-                epi[h][pb] = M::fma(ui, odd ? -zr_ : zi_, epi[h][pb]);
+                epr[h][pb] = M::fma(ur, zr[NG + pb], epr[h][pb]);
+                epi[h][pb] = M::fma(ui, zi[NG + pb], epi[h][pb]);
             }
         };
-        T zra[NB], zia[NB], zrb[NB], zib[NB];
+        T zra[NB], zia[NB], zza[NGa2], zrb[NB], zib[NB], zzb[NGa2];
         // (the scheduling barriers keep the reads ahead of the previous step's MFMAs)
-        zread(0, zra, zia);
+        zread(0, zra, zia, zza);
 #pragma unroll
         for (int s = 0; s < GS; s += 2) {   // GS is even
-            zread(s + 1, zrb, zib);
+            zread(s + 1, zrb, zib, zzb);
             __builtin_amdgcn_sched_barrier(0);
-            step(s, zra, zia);
-            if (s + 2 < GS) zread(s + 2, zra, zia);
+            step(s, zra, zia, zza);
+            if (s + 2 < GS) zread(s + 2, zra, zia, zza);
             __builtin_amdgcn_sched_barrier(0);
-            step(s + 1, zrb, zib);
+            step(s + 1, zrb, zib, zzb);
         }
         if (gi == (1 << lgpu) - 1) {   // the unit is complete
 #pragma unroll
@@ -869,8 +880,8 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                 for (int cb = 0; cb < NG; ++cb) {
                     const T q1 = e1[0][cb][r] + e1[1][cb][r], q2 = e2[0][cb][r] + e2[1][cb][r];
                     const T q3 = e3[0][cb][r] + e3[1][cb][r];
-                    res[8 * cb + 2 * r] = q1 - q2;
-                    res[8 * cb + 2 * r + 1] = q3 - q1 - q2;
+                    res[8 * cb + 2 * r] = q1 + q2;
+                    res[8 * cb + 2 * r + 1] = q3 - q1 + q2;
                 }
 #pragma unroll
                 for (int pb = 0; pb < NP; ++pb)
@@ -1090,7 +1101,9 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     // epilogue holds the tile's rows of Z as two planes of one 16-column slot per
     // column block, at most 64 KiB for every instantiated shape.
     size_t budget = std::min<size_t>(h->lds_per_block, 80 * 1024);
-    const size_t epi = mode ? 0 : 2 * (size_t)P.rows * 16 * P.nb * tsize;
+    const size_t epi = mode ? 0
+                            : (size_t)(2 * P.nb + (z_sum_plane(tsize, P.nb, P.ng, P.rows) ? P.ng : 0)) * P.rows * 16 *
+                                  tsize;
     P.bbufs = 2;
     const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
