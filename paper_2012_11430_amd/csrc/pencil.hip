@@ -115,6 +115,7 @@ struct PencilPlan {
     int rt;         // row tiles
     int nwg;        // rt * sk workgroups
     int win_cap;    // window capacity (complex elements)
+    int wsum;       // three-product blocks: window entries (Re, Im, Re + Im, 0) instead of (Re, Im)
     int c0;         // grid offset of the origin shift
     size_t lds_bytes;
     // workspace offsets (bytes)
@@ -322,12 +323,16 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     extern __shared__ __align__(16) unsigned char smem[];
     // Phase 1 (K loop): grid window + h' offsets. Phase 2 (U^* reduction): the
     // same bytes hold the tile's rows of Z (S-build).
-    // window entries: complex<T>, or for split operands 16 bytes
-    // (Re h | Im h, Re m | Im m, Re l | Im l, 0) as bfloat16 pairs
-    constexpr size_t kEntry = SPLIT ? 16 : sizeof(T2);
+    // window entries: complex<T>, with three-product blocks and P.wsum (Re, Im,
+    // Re + Im, 0), or for split operands 16 bytes (Re h | Im h, Re m | Im m,
+    // Re l | Im l, 0) as bfloat16 pairs
+    typedef T vec4_t __attribute__((ext_vector_type(4)));
+    const bool wide = !SPLIT && NG > 0 && P.wsum;
+    const int entry = SPLIT ? 16 : (wide ? (int)sizeof(vec4_t) : (int)sizeof(T2));
     T2* win = reinterpret_cast<T2*>(smem);
+    vec4_t* win4 = reinterpret_cast<vec4_t*>(smem);
     u32x4* win16 = reinterpret_cast<u32x4*>(smem);
-    int* gt = reinterpret_cast<int*>(smem + align_up(kEntry * (size_t)P.win_cap, 16));
+    int* gt = reinterpret_cast<int*>(smem + align_up((size_t)entry * P.win_cap, 16));
     T* zpl = reinterpret_cast<T*>(smem);
 
     const int tid = threadIdx.x;
@@ -377,8 +382,14 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                 // per K block, h' = 4 t + g at 8 g + t: a lane reads its 8 offsets as two int4
                 if (w < ngt) gt[(w & ~31) | ((w & 3) << 3) | ((w & 31) >> 2)] = o[j];
             } else {
-                if (w < W) win[w] = T2{(T)v[j].x, reflect ? -(T)v[j].y : (T)v[j].y};
-                if (w < ngt) gt[(w & 3) * gstride + (w >> 2)] = o[j] * (int)sizeof(T2);   // bytes
+                if (w < W) {
+                    const T x = (T)v[j].x, y = reflect ? -(T)v[j].y : (T)v[j].y;
+                    if (wide)
+                        win4[w] = vec4_t{x, y, x + y, T(0)};
+                    else
+                        win[w] = T2{x, y};
+                }
+                if (w < ngt) gt[(w & 3) * gstride + (w >> 2)] = o[j] * entry;   // bytes
             }
         }
     }
@@ -386,7 +397,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // (two buffers, or one); the four 16-byte units of a column are XOR-swizzled by
     // bits 1..2 of the column, the pattern under which a ds_read_b128 of 16 columns
     // x 4 lane groups runs without bank conflicts on gfx950 (measured).
-    u32x4* bst = reinterpret_cast<u32x4*>(smem + align_up(kEntry * (size_t)P.win_cap, 16) +
+    u32x4* bst = reinterpret_cast<u32x4*>(smem + align_up((size_t)entry * P.win_cap, 16) +
                                           align_up(4 * ((size_t)P.kc + kPrefetchRows + 16), 16));
     const int bunits = kSplitPlanes * P.nrp * 4;  // 16-byte units of one K block
     const u32x4* bsrc = reinterpret_cast<const u32x4*>(vp) + (size_t)(h_first / kSplitK) * bunits;
@@ -411,7 +422,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 #pragma unroll
     for (int f = 0; f < RF; ++f) {
         gk[f] = row_offset(P, min(krow0 + kRowsPerWave * f, P.NR - 1)) + P.c0 - lo;
-        if constexpr (!SPLIT) gk[f] = gk[f] * (int)sizeof(T2) + lds_base;
+        if constexpr (!SPLIT) gk[f] = gk[f] * entry + lds_base;
     }
 
     acc_t acc[RF][NA];
@@ -429,12 +440,21 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     const int nks = P.kc >> 2;
     const int4* gq = reinterpret_cast<const int4*>(gt + g * gstride);
     T2 a[kDepth][RF];
+    T as4[kDepth][RF];   // Re + Im of the A entries (wide window entries)
     T2 b[kDepth][NB];
-    auto load_a = [&](T2* dst, int off) {
+    typedef __attribute__((address_space(3))) const vec4_t lds_t4;
+    // wc: std::integral_constant<bool, wide window entries>
+    auto load_a = [&](auto wc, T2* dst, T* sdst, int off) {
 #pragma unroll
         for (int f = 0; f < RF; ++f) {
-            const vec2_t e = *(lds_t2*)(size_t)(unsigned)(gk[f] - off);
-            dst[f] = T2{e.x, e.y};
+            if constexpr (decltype(wc)::value) {
+                const vec4_t e = *(lds_t4*)(size_t)(unsigned)(gk[f] - off);
+                dst[f] = T2{e.x, e.y};
+                sdst[f] = e.z;
+            } else {
+                const vec2_t e = *(lds_t2*)(size_t)(unsigned)(gk[f] - off);
+                dst[f] = T2{e.x, e.y};
+            }
         }
     };
     auto load_b = [&](T2* dst, int step) {
@@ -462,14 +482,15 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // With three-product blocks: P1 += Re a Re v, P2 += Im a Im v, P3 += (Re a +
     // Im a)(Re v + Im v) for those, the pair MFMAs for the rest; the Re-multiplier
     // MFMAs of every block first, so that dependent MFMAs sit apart.
-    auto mma_g = [&](const T2* av, const T2* bv) {
+    auto mma_g = [&](auto wc, const T2* av, const T* avs, const T2* bv) {
         // the operand sums first, as one group: a VALU operation between this wave's
-        // MFMAs leaves the matrix core idle for about its latency (measured)
+        // MFMAs leaves the matrix core idle for about its latency (measured); the A
+        // sums come with the window entries where they are staged
         T bsum[NG > 0 ? NG : 1], asum[RF];
 #pragma unroll
         for (int cb = 0; cb < NG; ++cb) bsum[cb] = bv[cb].x + bv[cb].y;
 #pragma unroll
-        for (int f = 0; f < RF; ++f) asum[f] = av[f].x + av[f].y;
+        for (int f = 0; f < RF; ++f) asum[f] = decltype(wc)::value ? avs[f] : av[f].x + av[f].y;
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int f = 0; f < RF; ++f) {
@@ -491,12 +512,13 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
             for (int cb = 0; cb < NG; ++cb) acc[f][2 * NG + cb] = M::fma(asum[f], bsum[cb], acc[f][2 * NG + cb]);
         }
     };
-    auto ring_step = [&](T2* ad, int off, T2* bd, int bs, const T2* av, const T2* bv) {
-        load_a(ad, off);
+    auto ring_step = [&](auto wc, T2* ad, T* asd, int off, T2* bd, int bs, const T2* av, const T* avs,
+                         const T2* bv) {
+        load_a(wc, ad, asd, off);
         if constexpr (NG > 0) {
             load_b(bd, bs);
             __builtin_amdgcn_sched_barrier(0);
-            mma_g(av, bv);
+            mma_g(wc, av, avs, bv);
         } else if constexpr (kSplitLoads) {
             __builtin_amdgcn_sched_barrier(0);
             mma_x(av, bv);
@@ -643,24 +665,35 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // counters of the loop header merge this path with the back edge, and an
     // order that differs there makes the header wait for every load in flight
     // instead of the oldest step's.
+    // one copy of the loop per window entry form (a uniform branch before it)
+    auto kloop_pairs = [&](auto wc) {
     int4 gc = gq[0];
-    load_a(a[0], gc.x);
+    load_a(wc, a[0], as4[0], gc.x);
     load_b(b[0], 0);
     __builtin_amdgcn_sched_barrier(0);
-    load_a(a[1], gc.y);
+    load_a(wc, a[1], as4[1], gc.y);
     load_b(b[1], 1);
     __builtin_amdgcn_sched_barrier(0);
-    load_a(a[2], gc.z);
+    load_a(wc, a[2], as4[2], gc.z);
     load_b(b[2], 2);
     __builtin_amdgcn_sched_barrier(0);
     // sched_barrier keeps the compiler from sinking the prefetches next to their use.
     for (int ks = 0; ks < nks; ks += kDepth) {
         const int4 gn = gq[(ks >> 2) + 1];
-        ring_step(a[3], gc.w, b[3], ks + 3, a[0], b[0]);
-        ring_step(a[0], gn.x, b[0], ks + 4, a[1], b[1]);
-        ring_step(a[1], gn.y, b[1], ks + 5, a[2], b[2]);
-        ring_step(a[2], gn.z, b[2], ks + 6, a[3], b[3]);
+        ring_step(wc, a[3], as4[3], gc.w, b[3], ks + 3, a[0], as4[0], b[0]);
+        ring_step(wc, a[0], as4[0], gn.x, b[0], ks + 4, a[1], as4[1], b[1]);
+        ring_step(wc, a[1], as4[1], gn.y, b[1], ks + 5, a[2], as4[2], b[2]);
+        ring_step(wc, a[2], as4[2], gn.z, b[2], ks + 6, a[3], as4[3], b[3]);
         gc = gn;
+    }
+    };
+    if constexpr (NG > 0) {
+        if (wide)
+            kloop_pairs(std::integral_constant<bool, true>{});
+        else
+            kloop_pairs(std::integral_constant<bool, false>{});
+    } else {
+        kloop_pairs(std::integral_constant<bool, false>{});
     }
     }
 
@@ -1002,8 +1035,8 @@ __global__ __launch_bounds__(kThreads) void pencil_tiles_batched(const BatchEntr
     tile_body<T, NB, RF, 0, false, NG>(e.P, e.ptr, id - e.tile_begin);
 }
 
-size_t lds_bytes_for(int win, int kc, size_t epi, size_t tsize, int split_nrp = 0, int bbufs = 2) {
-    const size_t entry = split_nrp ? 16 : 2 * tsize;
+size_t lds_bytes_for(int win, int kc, size_t epi, size_t tsize, int split_nrp = 0, int bbufs = 2, bool wide = false) {
+    const size_t entry = split_nrp ? 16 : (wide ? 4 : 2) * tsize;
     const size_t loop = align_up(entry * (size_t)win, 16) + align_up(4 * ((size_t)kc + kPrefetchRows + 16), 16) +
                         (split_nrp ? (size_t)bbufs * kSplitPlanes * split_nrp * 64 : 0);
     return align_up(std::max(loop, epi), 16);
@@ -1138,6 +1171,17 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
         }
         kc = (int)align_up((size_t)(kc / 2), kal);
         P.bbufs = 2;
+    }
+    // FP32 three-product blocks: the sums Re + Im of the window entries staged with
+    // them when the wider entries fit at this chunk size (one VALU operation less
+    // per fragment and K step in the MFMA stream; with FP64 the 32-byte entries
+    // cost more in LDS reads than the sums, measured)
+    if (!split && P.ng > 0 && tsize == 4) {
+        const size_t lw = lds_bytes_for(P.win_cap, P.kc, epi, tsize, 0, 2, true);
+        if (lw <= budget) {
+            P.wsum = 1;
+            P.lds_bytes = lw;
+        }
     }
     P.nwg = P.rt * P.sk;
     if (((int64_t)P.sk * P.kc + kPrefetchRows) * P.nrp >= (int64_t(1) << 31) ||
