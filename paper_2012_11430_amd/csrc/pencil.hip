@@ -755,12 +755,11 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // consecutive elements: three-product blocks as Zr, Zi and (where the LDS
     // allows) Zr + Zi; pair blocks lane-ready, [Zr | Zi] and [Zi | -Zr] (lane column
     // n is complex column n / 2 of the block, real part for even n, imaginary part
-    // for odd n). Then each wave takes whole units (wave, wave + 4,
-    // ...) and runs their MFMAs itself. A unit is an item over all kRows / 4 K steps
-    // of the tile when there are 3 or more items; with 1 or 2 items it is one of rs =
-    // 4 / items parts of an item's K steps (at most one per group of steps), so that
-    // no wave idles, and the parts are added in part order through LDS before the
-    // store.
+    // for odd n). Then each wave runs the MFMAs of its units: the items wave,
+    // wave + 4, ... over all kRows / 4 K steps of the tile, and, when 1 or 2 items
+    // are left over after the multiples of 4, one of the rs = 4 / (items mod 4)
+    // parts of a left-over item's K steps (at most one per group of steps), so that
+    // no wave idles; the parts are added in part order through LDS before the store.
     // The first operand (lane (k, i) of step s: U_l[4 s + k][16 ib + i]) comes in
     // groups of GS steps, two groups in flight in two register sets. The loads are
     // unconditional (clamped to the wave's last group and to the last item) and the
@@ -781,18 +780,31 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     const int mup = P.mbi * 16;
     const int items = P.mbi * P.ells;
     constexpr int kLgr = __builtin_ctz(NGR);
-    const int lrs = items >= 3 ? 0 : min(items == 2 ? 1 : 2, kLgr);   // log2 of the parts per item
-    const int lgpu = kLgr - lrs;                                    // log2 of the groups per unit
-    const int units = items << lrs;
-    const int total = (units > wave ? (units - wave + kWaves - 1) / kWaves : 0) << lgpu;
+    const int rem = items & 3;
+    const int lrs = rem == 1 || rem == 2 ? min(rem == 2 ? 1 : 2, kLgr) : 0;   // log2 of the parts per tail item
+    const int lgpu = kLgr - lrs;                                              // log2 of the groups per part
+    const int nfull = lrs ? items - rem : items;                              // items taken whole
+    const int nwhole = nfull > wave ? (nfull - wave + kWaves - 1) / kWaves : 0;
+    const bool has_part = lrs > 0 && wave < (rem << lrs);
+    const int total = (nwhole << kLgr) + (has_part ? 1 << lgpu : 0);
     const int xlast = max(total, 1) - 1;
     const T2* ubase = up + (size_t)(P.ug + k_first + g) * mup + col;
-    // unit u = wave + 4 j of the wave's x-th group: item u >> lrs, part u & (rs - 1)
-    auto unit_of = [&](int x) { return wave + kWaves * (x >> lgpu); };
+    // The wave's x-th group: whole items wave, wave + 4, ... first, then part
+    // wave & (rs - 1) of tail item nfull + (wave >> lrs).
+    auto unit_at = [&](int x, int& it, int& grp) {
+        const int xw = x - (nwhole << kLgr);
+        if (xw < 0) {
+            it = wave + kWaves * (x >> kLgr);
+            grp = x & (NGR - 1);
+        } else {
+            it = nfull + (wave >> lrs);
+            grp = ((wave & ((1 << lrs) - 1)) << lgpu) | xw;
+        }
+    };
     auto load_g = [&](T2 (&u)[GS], int x) {
-        x = min(x, xlast);
-        const int un = min(unit_of(x), units - 1);
-        const int it = un >> lrs, grp = ((un & ((1 << lrs) - 1)) << lgpu) | (x & ((1 << lgpu) - 1));
+        int it, grp;
+        unit_at(min(x, xlast), it, grp);
+        it = min(it, items - 1);
         const int ib = it / P.ells, li = it - ib * P.ells;
         const T2* src = ubase + (ptrdiff_t)(4 * GS * grp - rowext_shift(P, li + P.first_ell)) * mup + ib * 16;
 #pragma unroll
@@ -855,8 +867,11 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         }
     };
     auto group = [&](const T2 (&u)[GS], int x) {
-        const int un = unit_of(x), gi = x & ((1 << lgpu) - 1);
-        const int grp = ((un & ((1 << lrs) - 1)) << lgpu) | gi;
+        int it, grp;
+        unit_at(x, it, grp);
+        const bool whole = x < (nwhole << kLgr);
+        const int lg = whole ? kLgr : lgpu;   // log2 of the unit's groups
+        const int gi = grp & ((1 << lg) - 1);
         if (gi == 0) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -906,7 +921,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
             __builtin_amdgcn_sched_barrier(0);
             step(s + 1, zrb, zib, zzb);
         }
-        if (gi == (1 << lgpu) - 1) {   // the unit is complete
+        if (gi == (1 << lg) - 1) {   // the unit is complete
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
 #pragma unroll
@@ -920,7 +935,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                 for (int pb = 0; pb < NP; ++pb)
                     res[8 * NG + 4 * pb + r] = (epr[0][pb][r] + epr[1][pb][r]) + (epi[0][pb][r] + epi[1][pb][r]);
             }
-            if (lrs == 0) store_item(un);
+            if (whole) store_item(it);
         }
     };
     for (int x = 0; x < total; x += 2) {
@@ -933,21 +948,20 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         __builtin_amdgcn_sched_barrier(0);
     }
     if (lrs > 0) {
-        // at most one unit per wave: part wave & (rs - 1) of item wave >> lrs; parts
-        // 1.. go through LDS (the Z planes are free once every wave is past its
-        // MFMAs) and part 0 adds them in part order and stores the item
+        // tail items: parts 1.. go through LDS (the Z planes are free once every
+        // wave is past its MFMAs) and part 0 adds them in part order and stores
         const int pt = wave & ((1 << lrs) - 1);
         __syncthreads();
-        if (pt > 0 && wave < units) {
+        if (pt > 0 && has_part) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) zpl[((wave - 1) * NV + v) * 64 + lane] = res[v];
         }
         __syncthreads();
-        if (pt == 0 && wave < units) {
+        if (pt == 0 && has_part) {
             for (int q = 1; q < (1 << lrs); ++q)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) res[v] += zpl[((wave + q - 1) * NV + v) * 64 + lane];
-            store_item(wave >> lrs);
+            store_item(nfull + (wave >> lrs));
         }
     }
 }
