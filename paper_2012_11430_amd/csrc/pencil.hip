@@ -1308,9 +1308,10 @@ __device__ __forceinline__ void tile_of_class(const BatchEntry<T>& e, int L) {
 
 // Queue schedule of a batch: one persistent launch of as many workgroups as fit
 // the device at once; each takes the next work item (all tiles of all
-// instances, longest first) from a counter until the queue is empty.
+// instances, longest first) from a counter until the queue is empty. Bounded to
+// two workgroups per CU: the union of the tile classes would take more registers.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void pencil_tiles_queue(const BatchEntry<T>* __restrict__ entries,
+__global__ __launch_bounds__(kThreads, 2) void pencil_tiles_queue(const BatchEntry<T>* __restrict__ entries,
                                                                const WorkItem* __restrict__ items, int nitems,
                                                                int* __restrict__ counter) {
     __shared__ int next;
@@ -1905,8 +1906,8 @@ prony_status_t batch_build(prony_handle_t h, int count, const prony_instance_t* 
     B->queue_lds = 0;
     for (int pos = 0; pos < count; ++pos) B->queue_lds = std::max(B->queue_lds, host[pos].P.lds_bytes);
     // resident workgroups per CU: LDS (dynamic + the kernel's 16 static bytes), and
-    // at most 3 (the kernel's 161 registers allow 3 waves per SIMD)
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(3, h->lds_per_block / (B->queue_lds + 16)));
+    // at most 2 (the kernel is bounded to 256 registers, 2 waves per SIMD)
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, h->lds_per_block / (B->queue_lds + 16)));
     B->queue_grid = (int)std::min<size_t>(nitems, (size_t)per_cu * h->num_cus);
     // class launches by default: each class's own kernel keeps as many workgroups
     // resident as its registers and LDS allow, and the lanes overlap the classes'
