@@ -354,9 +354,9 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 
     // Stage the window (converted to T) and the h' offsets, kStage loads per
     // thread in flight. The offsets are stored transposed per lane group:
-    // gt[g * stride + s] = G(h' = h_first + 4 s + g) (in bytes of a window entry,
-    // except for split operands), so one 16-byte LDS read gives a lane the offsets
-    // of four consecutive K steps.
+    // gt[g * stride + s] = G(h' = h_first + 4 s + g) (in bytes: G times the window
+    // entry size), so one 16-byte LDS read gives a lane the offsets of four
+    // consecutive K steps.
     constexpr int kStage = 8;
     const int ngt = SPLIT ? P.kc : P.kc + kPrefetchRows;
     const int gstride = ngt >> 2;
@@ -380,7 +380,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                     win16[w] = u32x4{rh | ((unsigned)ih << 16), rm | ((unsigned)im << 16), rl | ((unsigned)il << 16), 0u};
                 }
                 // per K block, h' = 4 t + g at 8 g + t: a lane reads its 8 offsets as two int4
-                if (w < ngt) gt[(w & ~31) | ((w & 3) << 3) | ((w & 31) >> 2)] = o[j];
+                if (w < ngt) gt[(w & ~31) | ((w & 3) << 3) | ((w & 31) >> 2)] = o[j] * entry;   // bytes
             } else {
                 if (w < W) {
                     const T x = (T)v[j].x, y = reflect ? -(T)v[j].y : (T)v[j].y;
@@ -412,9 +412,8 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // Rows of this wave: k_first + 16 (RF wave + f) + col for fragment f (rows past
     // the last read the last row's offsets; their results are discarded).
     const int krow0 = k_first + kRowsPerWave * RF * wave + col;
-    // window offsets of the fragments' rows (split operands: entries; otherwise LDS
-    // byte addresses, with the staged h' offsets in bytes, so that an A address is
-    // one subtraction)
+    // window offsets of the fragments' rows as LDS byte addresses, with the staged
+    // h' offsets in bytes, so that an A address is one subtraction
     typedef T vec2_t __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) const vec2_t lds_t2;
     const int lds_base = (int)(size_t)(__attribute__((address_space(3))) unsigned char*)smem;
@@ -422,7 +421,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 #pragma unroll
     for (int f = 0; f < RF; ++f) {
         gk[f] = row_offset(P, min(krow0 + kRowsPerWave * f, P.NR - 1)) + P.c0 - lo;
-        if constexpr (!SPLIT) gk[f] = gk[f] * entry + lds_base;
+        gk[f] = gk[f] * entry + lds_base;
     }
 
     acc_t acc[RF][NA];
@@ -552,6 +551,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         };
         const int nkb = P.kc / kSplitK;
         const int swz = (col >> 1) & 3;
+        typedef __attribute__((address_space(3))) const u32x4 lds_u4;
         auto mfma = [](const bf16x8& x, const bf16x8& y, acc_t c) {
             return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
         };
@@ -574,7 +574,7 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
             for (int f = 0; f < RF; ++f) {
                 u32x4 e[8];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) e[t] = win16[gk[f] - offs[t]];
+                for (int t = 0; t < 8; ++t) e[t] = *(lds_u4*)(size_t)(unsigned)(gk[f] - offs[t]);
                 unsigned re[3][4], im[3][4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
