@@ -1186,11 +1186,11 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
         kc = (int)align_up((size_t)(kc / 2), kal);
         P.bbufs = 2;
     }
-    // FP32 three-product blocks: the sums Re + Im of the window entries staged with
-    // them when the wider entries fit at this chunk size (one VALU operation less
-    // per fragment and K step in the MFMA stream; with FP64 the 32-byte entries
-    // cost more in LDS reads than the sums, measured)
-    if (!split && P.ng > 0 && tsize == 4) {
+    // FP32 three-product S-build blocks: the sums Re + Im of the window entries
+    // staged with them when the wider entries fit at this chunk size (one VALU
+    // operation less per fragment and K step in the MFMA stream; measured slower
+    // with FP64's 32-byte entries and in the product mode)
+    if (!split && P.ng > 0 && tsize == 4 && !mode) {
         const size_t lw = lds_bytes_for(P.win_cap, P.kc, epi, tsize, 0, 2, true);
         if (lw <= budget) {
             P.wsum = 1;
