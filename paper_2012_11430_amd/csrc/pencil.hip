@@ -72,15 +72,14 @@ constexpr int kPrefetchRows = 4 * kDepth;
 
 // 16-row fragments per wave (each B operand feeds RF times the MFMAs) that an
 // instantiation supports: the accumulators of all fragments must fit the register
-// file next to the operand ring. 1 always; 2 up to 8 (FP32) or 5 (FP64) column
-// blocks; 4 up to 4 (FP32, split bfloat16: 2) or 2 (FP64) column blocks.
-// The three-product form keeps three accumulator blocks per column block.
+// file next to the operand ring. 1 always; 2 up to 8 (FP32) or 6 (FP64)
+// accumulator blocks; 4 up to 4 (FP32, split bfloat16: 1 column block) or 2 (FP64).
 // ng of the nb column blocks in the three-product form keep three accumulator
-// blocks each.
+// blocks each; split tiles keep two per column block (Re a and Im a products).
 constexpr bool rf_supported(size_t tsize, int nb, int rf, bool split = false, int ng = 0) {
-    const int na = nb + 2 * ng;   // accumulator blocks per fragment
+    const int na = nb + 2 * ng;   // accumulator blocks per fragment (split: x 2)
     return rf == 1 || (rf == 2 && na <= (tsize == 4 ? 8 : 6)) ||
-           (rf == 4 && na <= (split ? 2 : (tsize == 4 ? 4 : 2)));
+           (rf == 4 && na <= (split ? 1 : (tsize == 4 ? 4 : 2)));
 }
 
 // Whether the S-build epilogue stores Zr + Zi of its three-product blocks as a third
@@ -425,10 +424,16 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     }
 
     acc_t acc[RF][NA];
+    // split operands: the Im(a) products against the same (Re-multiplier) B planes,
+    // combined with acc through a lane-pair swap after the K loop
+    acc_t acc2[RF][SPLIT ? NB : 1];
 #pragma unroll
-    for (int f = 0; f < RF; ++f)
+    for (int f = 0; f < RF; ++f) {
 #pragma unroll
         for (int cb = 0; cb < NA; ++cb) acc[f][cb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int cb = 0; cb < (SPLIT ? NB : 1); ++cb) acc2[f][cb] = acc_t{0, 0, 0, 0};
+    }
 
     // K loop over this chunk, 4 h' per step (lane group g takes h' = 4 ks + g).
     // Operands rotate through kDepth register buffers: while the MFMAs of step
@@ -535,20 +540,6 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     };
     if constexpr (SPLIT) {
         constexpr int kVecB = (kSplitPlanes * 16 * NB * 4 + kThreads - 1) / kThreads;
-        // Im-multiplier from the Re-multiplier of the neighbouring column (lane col ^ 1):
-        // negated (sign bits of both bfloat16 halves) on even columns. Every lane of
-        // the quad permutation has a source, so the update form (old value 0, bound
-        // control on) equals a plain move and lets the XOR take the DPP operand
-        // directly (one v_xor_b32_dpp per dword).
-        const unsigned neg = (col & 1) ? 0u : 0x80008000u;
-        auto im_of = [neg](const u32x4& x) {
-            u32x4 y;
-            y.x = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x.x, 0xB1, 0xF, 0xF, true) ^ neg;
-            y.y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x.y, 0xB1, 0xF, 0xF, true) ^ neg;
-            y.z = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x.z, 0xB1, 0xF, 0xF, true) ^ neg;
-            y.w = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x.w, 0xB1, 0xF, 0xF, true) ^ neg;
-            return y;
-        };
         const int nkb = P.kc / kSplitK;
         const int swz = (col >> 1) & 3;
         typedef __attribute__((address_space(3))) const u32x4 lds_u4;
@@ -616,30 +607,28 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 #pragma unroll
                     for (int pl = 0; pl < kSplitPlanes; ++pl) xb[pl] = bb[((pl * P.nrp + 16 * cb + col) << 2) | (g ^ swz)];
                 }
-                bf16x8 b[2 * kSplitPlanes];
+                bf16x8 b[kSplitPlanes];
 #pragma unroll
-                for (int pl = 0; pl < kSplitPlanes; ++pl) {
-                    const u32x4 x = xb[pl];
-                    b[pl] = __builtin_bit_cast(bf16x8, x);
-                    b[kSplitPlanes + pl] = __builtin_bit_cast(bf16x8, im_of(x));
-                }
-                // the six products of the three-term splits above 2^-24 (h h, h m, m h, h l, l h, m m)
+                for (int pl = 0; pl < kSplitPlanes; ++pl) b[pl] = __builtin_bit_cast(bf16x8, xb[pl]);
+                // the six products of the three-term splits above 2^-24 (h h, h m, m h, h l, l h,
+                // m m), of Re a into acc and of Im a into acc2, alternating
 #pragma unroll
                 for (int f = 0; f < RF; ++f) {
-                    acc_t c = acc[f][cb];
+                    acc_t c = acc[f][cb], c2 = acc2[f][cb];
                     c = mfma(ar[f][2], b[0], c);
+                    c2 = mfma(ai[f][2], b[0], c2);
                     c = mfma(ar[f][0], b[2], c);
+                    c2 = mfma(ai[f][0], b[2], c2);
                     c = mfma(ar[f][1], b[1], c);
+                    c2 = mfma(ai[f][1], b[1], c2);
                     c = mfma(ar[f][1], b[0], c);
+                    c2 = mfma(ai[f][1], b[0], c2);
                     c = mfma(ar[f][0], b[1], c);
+                    c2 = mfma(ai[f][0], b[1], c2);
                     c = mfma(ar[f][0], b[0], c);
-                    c = mfma(ai[f][2], b[3], c);
-                    c = mfma(ai[f][0], b[5], c);
-                    c = mfma(ai[f][1], b[4], c);
-                    c = mfma(ai[f][1], b[3], c);
-                    c = mfma(ai[f][0], b[4], c);
-                    c = mfma(ai[f][0], b[3], c);
+                    c2 = mfma(ai[f][0], b[0], c2);
                     acc[f][cb] = c;
+                    acc2[f][cb] = c2;
                 }
                 if constexpr (kPrefetchB) {
 #pragma unroll
@@ -659,6 +648,19 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
             kloop(std::integral_constant<bool, true>{});
         else
             kloop(std::integral_constant<bool, false>{});
+        // The B planes hold the Re-multipliers only (lane column j: Re v for even j,
+        // Im v for odd j, of complex column j / 2): acc2 holds Im a times them, so the
+        // pair result is Re = acc - acc2 of the odd neighbour (Im a Im v) on even
+        // lanes and Im = acc + acc2 of the even neighbour (Im a Re v) on odd lanes.
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const T y = swap_lane_pair(acc2[f][cb][r]);
+                    acc[f][cb][r] += odd ? y : -y;
+                }
     } else {
     // The prologue issues the ring's first three steps in the order the loop body
     // issues them (step by step, A then B), pinned by sched_barrier: the wait
