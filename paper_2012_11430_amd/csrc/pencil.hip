@@ -181,7 +181,8 @@ __device__ __forceinline__ double2 pair_of(const PencilPlan& P, const double2* _
 // then read neighbouring window entries, which keeps the LDS reads free of bank
 // conflicts); a thread makes the eight rows of one lane group (16 bytes per plane).
 // The Im-multiplier is not stored: .y of column j is -.x of column j + 1 (j even)
-// or .x of column j - 1 (j odd), which the tile kernel forms in registers.
+// or .x of column j - 1 (j odd); the tile kernel multiplies Im a by the .x planes
+// into a second accumulator and applies that lane exchange once after its K loop.
 __device__ __forceinline__ void pack_split(const PencilPlan& P, const double2* __restrict__ V, int64_t v_rs,
                                            int64_t v_cs, u32x4* __restrict__ vp16, int first, int stride) {
     const int nunits = (P.sk * P.kc / kSplitK) * P.nrp * 4;
