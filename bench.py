@@ -424,7 +424,9 @@ def _match_errors(t_est, c_est, t_true, c_true):
 def noise_sweep_c2(dev, args, per_call_ms):
     """c2 (d=3, n=19, N=8000, m=30) over its noise levels: the SVD by Algorithm 3
     with GPU block products (T is never formed), S in FP64, FP32-MFMA and split
-    bfloat16, and the recovered t_j, c_j of each against the truth; the S-build
+    bfloat16, the recovered t_j, c_j of each against the truth, and per level the
+    operational accuracy estimates of Sec. 5 (detected rank, sigma_m / sigma_{m+1},
+    relative LS residual of each precision); the S-build
     of each precision timed as the median of per-call HIP events, with the tile
     kernel's launch time and its fraction of the MFMA peak on its own work."""
     import numpy as np
@@ -447,17 +449,28 @@ def noise_sweep_c2(dev, args, per_call_ms):
         noise = torch.from_numpy(inst.noise(level)).to(dev) if level > 0 else None
         f = api.samples(t_d, c_d, n, noise=noise)
         tol = max(N * np.finfo(float).eps, level)
-        U, s, V, _, sweeps = host.power_svd(host.GpuToeplitz(f, d, n), blocks[0], blocks[1], tol, rank=m)
+        info = {}
+        U, s, V, detected, sweeps = host.power_svd(host.GpuToeplitz(f, d, n), blocks[0], blocks[1], tol, rank=m,
+                                                   info=info)
         Ud, sd, Vd = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (U, s, V))
-        row = {"noise": level, "svd_sweeps": sweeps}
+        # the operational accuracy estimates of Sec. 5: the rank the SVD step detects at
+        # tolerance max(N eps, noise), sigma_m / sigma_{m+1} (sigma_{m+1} from the first
+        # sweep's estimates) and the relative LS residual ||A^T c - f_I|| / ||f_I||
+        est = info.get("first_sweep_sigma")
+        row = {"noise": level, "svd_sweeps": sweeps, "detected_rank": int(detected),
+               "sigma_m_over_sigma_m_plus_1": (float(f"{s[m - 1] / est[m]:.3e}")
+                                               if est is not None and est.size > m and est[m] > 0 else None)}
+        fI = host.samples_on_index_set(f.cpu().numpy(), d, n)
         S = {}
         for prec in ("fp64", "fp32", "bf16x3"):
             S[prec] = api.build_S(f, d, n, Ud, sd, Vd, prec=prec)
             z_p, t_p = host.nodes(S[prec].cpu().numpy(), inst.mu)
-            gram, rhs = api.coeffs(torch.from_numpy(z_p).to(dev), f, d, n)
+            gram, rhs, AT = api.coeffs(torch.from_numpy(z_p).to(dev), f, d, n, want_AT=True)
             c_p = host.solve_normal_equations(gram.cpu().numpy(), rhs.cpu().numpy())
             dt, dc = _match_errors(t_p, c_p, inst.t, inst.c)
-            row[prec] = {"max_dt_vs_truth": float(f"{dt:.3e}"), "rel_dc_vs_truth": float(f"{dc:.3e}")}
+            res = float(np.linalg.norm(AT.cpu().numpy() @ c_p - fI) / np.linalg.norm(fI))
+            row[prec] = {"max_dt_vs_truth": float(f"{dt:.3e}"), "rel_dc_vs_truth": float(f"{dc:.3e}"),
+                         "ls_rel_residual": float(f"{res:.3e}")}
         for p in ("fp32", "bf16x3"):
             row[f"s_rel_diff_{p}_vs_fp64"] = float(f"{float(torch.linalg.norm(S[p] - S['fp64']) / torch.linalg.norm(S['fp64'])):.3e}")
         rows.append(row)
