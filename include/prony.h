@@ -328,6 +328,13 @@ prony_status_t prony_toeplitz_mm(prony_handle_t handle, int d, int n, int adjoin
 
 /* ---- many instances: one planned launch sequence, graph capture ------------- */
 
+/* The batched S-build and its graph capture take a plan object rather than the
+   descriptor array on every call: prony_batch_create validates, plans and uploads
+   the descriptors once and owns the batch's workspace, so that
+   prony_build_S_batched and prony_graph_capture only enqueue launches — no
+   allocation, host-to-device copy or memset per call, which graph capture and
+   replay require. Descriptors therefore live on the host, and prony_reserve does
+   not size batches (each batch brings its own workspace). */
 typedef struct prony_batch_s* prony_batch_t;
 
 /* One S-build of a batch (Sec. 1, eq. generateSl, per instance). Pointers are
@@ -344,7 +351,8 @@ typedef struct {
 
 /* Plan the S-build of `count` (1..65535) instances (host array of descriptors, copied):
    validates every descriptor, chooses tiles per instance, groups the instances
-   by column-block count, orders them by decreasing work, builds the queue of all
+   by tile class (three-product blocks, column blocks, row fragments), orders them
+   by decreasing work, builds the queue of all
    tiles (longest first), allocates the batch's own device workspace and uploads
    its work tables (synchronously on the handle's stream). Errors name the
    offending instance. */
@@ -360,8 +368,9 @@ prony_status_t prony_batch_destroy(prony_batch_t batch);
                             device at once) that takes (instance, tile) work items,
                             longest first, from a counter the packing launch resets.
                             FP32 batches only.
-   PRONY_SCHEDULE_CLASSES — one launch per class of instances with the same
-                            column-block count and row fragments, spread over the
+   PRONY_SCHEDULE_CLASSES — one launch per class of instances with the same tile
+                            instantiation (three-product blocks, column blocks,
+                            row fragments), spread over the
                             handle's stream and three auxiliary streams (forked after
                             the packing launch, joined before the finishing launch).
                             The default: each class's kernel keeps as many workgroups
