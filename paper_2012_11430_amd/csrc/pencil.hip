@@ -441,7 +441,10 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     // ks run, the loads of steps ks+1 .. ks+kDepth-1 are in flight. Every B
     // operand feeds the RF fragments of the wave.
     const T2* vrow = vp + (size_t)(h_first + g) * P.nrp + col;
-    const size_t kstride = (size_t)4 * P.nrp;
+    // 4 packed rows per K step; the row length is 16 NB pairs for every FP32/FP64
+    // tile (a compile-time stride lets the steps of a loop iteration share one
+    // address with immediate offsets)
+    constexpr size_t kstride = (size_t)4 * 16 * NB;
     const int nks = P.kc >> 2;
     const int4* gq = reinterpret_cast<const int4*>(gt + g * gstride);
     T2 a[kDepth][RF];
