@@ -783,7 +783,9 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
     T* const zre = zpl;
     T* const zim = zpl + KS * NB * 64;
     T* const zsm = zpl + 2 * KS * NB * 64;   // [s][three-product block][k][column]
-    const int mup = P.mbi * 16;
+    // packed U row length: 16 mbi pairs (mbi = NB for FP32/FP64 S-builds, checked by
+    // the planner; a compile-time stride lets the U loads use immediate offsets)
+    const int mup = SPLIT ? P.mbi * 16 : 16 * NB;
     const int items = P.mbi * P.ells;
     constexpr int kLgr = __builtin_ctz(NGR);
     const int rem = items & 3;
@@ -1139,6 +1141,8 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.nrp = 16 * P.nb;
     P.nrr = 32 * P.ng + 16 * (P.nb - P.ng);
     P.mbi = mode ? 0 : (m + 15) / 16;
+    // the FP32/FP64 S-build tiles take the packed U row length as 16 nb
+    if (!mode && !split && P.mbi != P.nb) return fail(h, PRONY_ENOTSUP, "prony_build_S: unexpected column blocks");
     P.NR = mode ? P.N : (int)ipow(n + 2, d);
     P.ug = mode ? 0 : (int)ipow(n + 2, d - 1);
     P.kb = P.N;
