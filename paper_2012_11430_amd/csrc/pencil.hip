@@ -550,21 +550,19 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
         auto mfma = [](const bf16x8& x, const bf16x8& y, acc_t c) {
             return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
         };
-        // the buffer count is a compile-time constant of each loop copy: a
-        // barrier under a run-time condition sends the staging registers to scratch
-        auto kloop = [&](auto two_buffers) {
-        constexpr bool kTwo = decltype(two_buffers)::value;
-        for (int kb = 0; kb < nkb; ++kb) {
-            const int nxt = min(kb + 1, nkb - 1);
-            u32x4 stg[kVecB];
-#pragma unroll
-            for (int u = 0; u < kVecB; ++u) stg[u] = bsrc[(size_t)nxt * bunits + min(tid + u * kThreads, bunits - 1)];
-            __builtin_amdgcn_sched_barrier(0);   // issue the next block's loads before this block's MFMAs
+        // A terms of block kb for every fragment: element t of lane group g is
+        // h' = 32 kb + 4 t + g. The window and the offsets stay in LDS for the whole
+        // chunk, so with one fragment per wave the next block's terms are read and
+        // assembled while this block's MFMAs run (two register sets, swapped by
+        // unrolling the block loop by two; measured 3 % faster on c1 at the same
+        // register count). With two or more fragments the second set would take the
+        // kernel past 256 registers and halve the waves per SIMD (c2: 1.5x slower).
+        constexpr bool kPipeA = RF == 1;
+        typedef bf16x8 aterms_t[RF][3];
+        auto load_split_a = [&](int kb, aterms_t& ar, aterms_t& ai) {
             const int4 o0 = *reinterpret_cast<const int4*>(gt + kSplitK * kb + 8 * g);
             const int4 o1 = *reinterpret_cast<const int4*>(gt + kSplitK * kb + 8 * g + 4);
             const int offs[8] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
-            // A terms of each fragment: element t of lane group g is h' = 32 kb + 4 t + g
-            bf16x8 ar[RF][3], ai[RF][3];
 #pragma unroll
             for (int f = 0; f < RF; ++f) {
                 u32x4 e[8];
@@ -588,6 +586,19 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                     ai[f][q] = __builtin_bit_cast(bf16x8, u32x4{im[q][0], im[q][1], im[q][2], im[q][3]});
                 }
             }
+        };
+        // One K block with the A terms (ar, ai); with kPipeA loads the next block's
+        // into (nar, nai), else its own into (ar, ai) first.
+        // The buffer count is a compile-time constant of each loop copy: a barrier
+        // under a run-time condition sends the staging registers to scratch.
+        auto kblock = [&](auto two_buffers, int kb, aterms_t& ar, aterms_t& ai, aterms_t& nar, aterms_t& nai) {
+            constexpr bool kTwo = decltype(two_buffers)::value;
+            const int nxt = min(kb + 1, nkb - 1);
+            u32x4 stg[kVecB];
+#pragma unroll
+            for (int u = 0; u < kVecB; ++u) stg[u] = bsrc[(size_t)nxt * bunits + min(tid + u * kThreads, bunits - 1)];
+            __builtin_amdgcn_sched_barrier(0);   // issue the next block's loads before this block's MFMAs
+            if constexpr (!kPipeA) load_split_a(kb, ar, ai);
             const u32x4* bb = bst + (kTwo ? (kb & 1) * bunits : 0);
             // With 4 or more column blocks the B planes of block cb + 1 are read before
             // the MFMAs of block cb (measured 3-6 % faster on 8 and 12 blocks, neutral
@@ -634,6 +645,10 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
                     acc[f][cb] = c;
                     acc2[f][cb] = c2;
                 }
+                // the next block's A terms behind the first column block's MFMAs
+                if constexpr (kPipeA) {
+                    if (cb == 0) load_split_a(nxt, nar, nai);
+                }
                 if constexpr (kPrefetchB) {
 #pragma unroll
                     for (int pl = 0; pl < kSplitPlanes; ++pl) xb[pl] = xn[pl];
@@ -646,7 +661,20 @@ __device__ __forceinline__ void tile_body(const PencilPlan& P, const TilePtrs<T>
 #pragma unroll
             for (int u = 0; u < kVecB; ++u) wb[bslot(min(tid + u * kThreads, bunits - 1))] = stg[u];
             __syncthreads();
-        }
+        };
+        auto kloop = [&](auto two_buffers) {
+            aterms_t a0r, a0i, a1r, a1i;
+            if constexpr (kPipeA) {
+                load_split_a(0, a0r, a0i);
+                int kb = 0;
+                for (; kb + 1 < nkb; kb += 2) {
+                    kblock(two_buffers, kb, a0r, a0i, a1r, a1i);
+                    kblock(two_buffers, kb + 1, a1r, a1i, a0r, a0i);
+                }
+                if (kb < nkb) kblock(two_buffers, kb, a0r, a0i, a1r, a1i);
+            } else {
+                for (int kb = 0; kb < nkb; ++kb) kblock(two_buffers, kb, a0r, a0i, a1r, a1i);
+            }
         };
         if (P.bbufs == 2)
             kloop(std::integral_constant<bool, true>{});
