@@ -39,6 +39,7 @@
 //                       order and applies Sigma^{-1} in FP64;
 //   toeplitz_mm_tiles / toeplitz_mm_finish
 //                       the product mode Y = T X or T^* X (h over I_n, no U^*);
+//   toeplitz_mv         the same product with one column, on vector FMAs;
 //   pencil_pack_batched / pencil_tiles_batched / pencil_tiles_queue /
 //   pencil_finish_batched
 //                       many instances: one launch per tile class, or one
@@ -1042,6 +1043,87 @@ __global__ __launch_bounds__(256) void toeplitz_mm_finish(PencilPlan P, const T*
     Y[(size_t)k * ldy + c] = make_double2(re, im);
 }
 
+// Product with one column, y = T x or T^* x (Lanczos steps): vector FMAs instead of
+// the MFMA tiles, which would use 2 of their 16 columns. Same plan, packing and
+// partial-row layout as toeplitz_mm_tiles: a workgroup stages its tile's window and
+// its chunk's h offsets and x values in LDS; thread t accumulates row t mod R of the
+// tile (R = 64 rf rows) over every S-th h of the chunk (S = 256 / R), the S shares
+// are added in order through LDS, and toeplitz_mm_finish sums the chunks.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void toeplitz_mv(PencilPlan P, TilePtrs<T> ptr) {
+    using T2 = pair_t<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int id = blockIdx.x;
+    const int L = (P.nwg & 7) == 0 ? (id & 7) * (P.nwg >> 3) + (id >> 3) : id;
+    const int sk_i = L / P.rt, rt_i = L - (L / P.rt) * P.rt;
+    const int k_first = rt_i * P.rows;
+    const int k_last = min(k_first + P.rows - 1, P.NR - 1);
+    const int h_first = sk_i * P.kc;
+    const int h_last = min(h_first + P.kc, P.kb) - 1;
+    const int nh = h_last - h_first + 1;
+    const int lo = row_offset(P, k_first) - h_offset(P, h_last) + P.c0;
+    const int hi = row_offset(P, k_last) - h_offset(P, h_first) + P.c0;
+    const int W = hi - lo + 1;
+    // T^* multiplies by the Toeplitz matrix of conj(f(-p)): offsets reflected about c0
+    const bool reflect = P.conj_grid;
+    T2* win = reinterpret_cast<T2*>(smem);
+    int* go = reinterpret_cast<int*>(smem + align_up(sizeof(T2) * (size_t)P.win_cap, 16));
+    T2* xs = reinterpret_cast<T2*>(smem + align_up(sizeof(T2) * (size_t)P.win_cap, 16) + align_up(4 * (size_t)P.kc, 16));
+    T2* red = xs + P.kc;   // one partial sum per thread
+    const int tid = threadIdx.x;
+    // kStage loads per thread in flight
+    constexpr int kStage = 8;
+    for (int base = 0; base < max(W, nh); base += kStage * kThreads) {
+        double2 v[kStage];
+        int o[kStage];
+        T2 p[kStage];
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) {
+            const int w = base + j * kThreads + tid;
+            if (w < W) v[j] = ptr.grid[reflect ? 2 * P.c0 - (lo + w) : lo + w];
+            if (w < nh) {
+                o[j] = ptr.gtab[h_first + w];
+                p[j] = ptr.vp[(size_t)(h_first + w) * P.nrp];   // pair column 0: (Re x, -Im x)
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) {
+            const int w = base + j * kThreads + tid;
+            if (w < W) win[w] = T2{(T)v[j].x, reflect ? -(T)v[j].y : (T)v[j].y};
+            if (w < nh) {
+                go[w] = o[j];
+                xs[w] = T2{p[j].x, -p[j].y};
+            }
+        }
+    }
+    __syncthreads();
+    const int R = P.rows, S = kThreads / P.rows;
+    const int r = tid % R, sub = tid / R;
+    const int gk = row_offset(P, min(k_first + r, P.NR - 1)) + P.c0 - lo;
+    T re = 0, im = 0;
+#pragma unroll 8
+    for (int w = sub; w < nh; w += S) {
+        const T2 a = win[gk - go[w]];
+        const T2 x = xs[w];
+        re = fma(a.x, x.x, re);
+        re = fma(-a.y, x.y, re);
+        im = fma(a.x, x.y, im);
+        im = fma(a.y, x.x, im);
+    }
+    red[tid] = T2{re, im};
+    __syncthreads();
+    if (sub == 0 && k_first + r <= k_last) {
+        T sr = red[r].x, si = red[r].y;
+        for (int q = 1; q < S; ++q) {
+            sr += red[q * R + r].x;
+            si += red[q * R + r].y;
+        }
+        T* yp = reinterpret_cast<T*>(ptr.part) + ((size_t)sk_i * P.rt * P.rows + k_first + r) * P.nrr;
+        yp[0] = sr;
+        yp[1] = si;
+    }
+}
+
 // One instance of a batch: its plan, its pointers and the first global tile
 // index of the instance within its launch.
 template <typename T>
@@ -1536,8 +1618,25 @@ prony_status_t launch_toeplitz_mm(prony_handle_t h, const PencilPlan& P, const d
     }
     if ((st = check_launch(h, "pencil_pack")) != PRONY_OK) return st;
     const TilePtrs<T> ptr{reinterpret_cast<const double2*>(f), vp, nullptr, gt, part, nullptr, nullptr};
-    if ((st = dispatch_mm<T>(h, P, ptr)) != PRONY_OK) return st;
-    if ((st = check_launch(h, "toeplitz_mm_tiles")) != PRONY_OK) return st;
+    // one column: the vector kernel on the same plan (window, h offsets and x of a
+    // chunk, and one partial sum per thread, in LDS)
+    const size_t mv_lds = align_up(sizeof(T2) * (size_t)P.win_cap, 16) + align_up(4 * (size_t)P.kc, 16) +
+                          sizeof(T2) * ((size_t)P.kc + kThreads);
+    if (P.CB == 1 && P.rows <= kThreads && mv_lds <= h->lds_per_block) {
+        if (mv_lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&toeplitz_mv<T>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)mv_lds);
+            if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+        }
+        {
+            ProfileScope prof(h, "toeplitz_mv");
+            toeplitz_mv<T><<<P.nwg, kThreads, mv_lds, h->stream>>>(P, ptr);
+        }
+        if ((st = check_launch(h, "toeplitz_mv")) != PRONY_OK) return st;
+    } else {
+        if ((st = dispatch_mm<T>(h, P, ptr)) != PRONY_OK) return st;
+        if ((st = check_launch(h, "toeplitz_mm_tiles")) != PRONY_OK) return st;
+    }
     {
         ProfileScope prof(h, "toeplitz_mm_finish");
         const int outs = P.N * P.C;

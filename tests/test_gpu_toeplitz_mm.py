@@ -30,7 +30,10 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("d,n,r", [(1, 1, 1), (1, 63, 40), (2, 3, 5), (2, 15, 10), (2, 40, 40), (3, 3, 8),
-                                   (3, 7, 33), (2, 5, 64), (1, 200, 17)])
+                                   (3, 7, 33), (2, 5, 64), (1, 200, 17),
+                                   # one column (the vector kernel): one and several row tiles and
+                                   # chunks, ragged tails
+                                   (1, 200, 1), (2, 40, 1), (2, 63, 1), (3, 7, 1), (3, 12, 1)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_products_match_oracle(d, n, r, prec):
     rng = np.random.Generator(np.random.PCG64(3000 + 100 * d + n + r))
@@ -121,3 +124,22 @@ def test_solve_with_gpu_lanczos_recovers_c0():
     sol = host.solve(f, d, n, m, inst.mu, prec="fp64", start_blocks=(p1, restarts), svd="lanczos")
     dt, dc = O.recovery_errors(dict(t=sol.t, c=sol.c), inst.t, inst.c)
     assert dt < 1e-12 and dc < 1e-10, (dt, dc)
+
+
+def test_one_column_strided_and_repeatable():
+    # the one-column product reads a strided column and writes only its own column
+    rng = np.random.Generator(np.random.PCG64(37))
+    d, n = 2, 20
+    N = (n + 1) ** d
+    grid = rng.standard_normal((2 * n + 2) ** d) + 1j * rng.standard_normal((2 * n + 2) ** d)
+    big = _dev(rng.standard_normal((N, 3)) + 1j * rng.standard_normal((N, 3)))
+    X = big[:, 1:2]                               # leading dimension 3
+    out = torch.zeros((N, 2), dtype=torch.complex128, device=DEV)
+    Y = out[:, :1]                                # leading dimension 2
+    for adjoint in (False, True):
+        api.toeplitz_mm(_dev(grid), d, n, X, adjoint=adjoint, out=Y)
+        ref = O.toeplitz_product(grid, d, n, X.cpu().numpy(), adjoint)
+        assert_close(Y.cpu().numpy(), ref, TOL["fp64"], f"one column, adjoint={adjoint}")
+        assert torch.count_nonzero(out[:, 1:]) == 0
+        again = api.toeplitz_mm(_dev(grid), d, n, X, adjoint=adjoint)
+        assert torch.equal(again, Y)              # fixed-order sums: bitwise repeatable
