@@ -319,7 +319,8 @@ prony_status_t prony_build_S_adjoint(prony_handle_t handle, int d, int n, int m,
    X:    N x r complex128, row-major with leading dimension ldx >= r (device).
    Y:    N x r complex128 output, row-major with leading dimension ldy >= r; must not
          overlap X.
-   prec: MFMA and tile-accumulation type (FP32 or FP64); the chunk partials are added
+   prec: arithmetic and tile-accumulation type (FP32 or FP64): MFMA tiles, or vector
+         FMAs when r = 1 (one Lanczos step's product); the chunk partials are added
          in FP64 in a fixed order (bitwise reproducible). Requires 1 <= r <= 64.
    Uses the handle's workspace (grown as needed; PRONY_ECAPTURE if it must grow
    under stream capture). */
