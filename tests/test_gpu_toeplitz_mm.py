@@ -143,3 +143,28 @@ def test_one_column_strided_and_repeatable():
         assert torch.count_nonzero(out[:, 1:]) == 0
         again = api.toeplitz_mm(_dev(grid), d, n, X, adjoint=adjoint)
         assert torch.equal(again, Y)              # fixed-order sums: bitwise repeatable
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_one_column_at_the_paper_size_sampled_rows(prec):
+    # d = 3, n = 20 (N = 9261, the paper's workload; the products of one Lanczos step):
+    # sampled rows of T x and T^* x against rows of T formed one by one from the oracle's
+    # index set and grid indexing (T[k, h] = f(k - h); (T^*)[k, h] = conj f(h - k))
+    d, n = 3, 20
+    rng = np.random.Generator(np.random.PCG64(41))
+    N = (n + 1) ** d
+    grid = rng.standard_normal((2 * n + 2) ** d) + 1j * rng.standard_normal((2 * n + 2) ** d)
+    x = rng.standard_normal((N, 1)) + 1j * rng.standard_normal((N, 1))
+    I = O.index_set(d, n)
+    rows = np.unique(np.concatenate([[0, N - 1], rng.choice(N, 62, replace=False)]))
+    print(f"toeplitz_mm one column d={d} n={n} {prec}", flush=True)
+    for adjoint in (False, True):
+        got = api.toeplitz_mm(_dev(grid), d, n, _dev(x), adjoint=adjoint, prec=prec).cpu().numpy()[rows, 0]
+        ref = np.empty(rows.size, dtype=complex)
+        for i, k in enumerate(rows):
+            if adjoint:
+                trow = grid[O.grid_flat_index(I - I[k][None, :], n)].conj()
+            else:
+                trow = grid[O.grid_flat_index(I[k][None, :] - I, n)]
+            ref[i] = trow @ x[:, 0]
+        assert_close(got, ref, TOL[prec], f"sampled rows, adjoint={adjoint}")
