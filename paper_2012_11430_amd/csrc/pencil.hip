@@ -1047,8 +1047,9 @@ __global__ __launch_bounds__(256) void toeplitz_mm_finish(PencilPlan P, const T*
 // the MFMA tiles, which would use 2 of their 16 columns. Same plan, packing and
 // partial-row layout as toeplitz_mm_tiles: a workgroup stages its tile's window and
 // its chunk's h offsets and x values in LDS; thread t accumulates row t mod R of the
-// tile (R = 64 rf rows) over every S-th h of the chunk (S = 256 / R), the S shares
-// are added in order through LDS, and toeplitz_mm_finish sums the chunks.
+// tile (R = 64 rf rows) over the t / R-th of S contiguous shares of the chunk
+// (S = 256 / R), the S shares are added in order through LDS, and
+// toeplitz_mm_finish sums the chunks.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void toeplitz_mv(PencilPlan P, TilePtrs<T> ptr) {
     using T2 = pair_t<T>;
@@ -1097,18 +1098,30 @@ __global__ __launch_bounds__(kThreads) void toeplitz_mv(PencilPlan P, TilePtrs<T
         }
     }
     __syncthreads();
-    const int R = P.rows, S = kThreads / P.rows;
+    const int R = P.rows, S = kThreads / P.rows;   // R is a multiple of 64: sub is uniform per wave
     const int r = tid % R, sub = tid / R;
     const int gk = row_offset(P, min(k_first + r, P.NR - 1)) + P.c0 - lo;
+    // share sub: a contiguous range of the chunk. Along a line of I_n the h offset
+    // grows by one, so the window index of the next h is one lower; after a line's
+    // last h it is read from the offsets (one read per line instead of per h).
+    const int per = (nh + S - 1) / S;
+    const int w0 = __builtin_amdgcn_readfirstlane(min(sub * per, nh));
+    const int w1 = __builtin_amdgcn_readfirstlane(min(w0 + per, nh));
     T re = 0, im = 0;
+    // runs of consecutive h along one line: window indices pos, pos - 1, ...
+    for (int w = w0, j = (h_first + w0) % (P.n + 1); w < w1; j = 0) {
+        const int run = min(P.n + 1 - j, w1 - w);
+        const int pos = gk - go[w];
 #pragma unroll 8
-    for (int w = sub; w < nh; w += S) {
-        const T2 a = win[gk - go[w]];
-        const T2 x = xs[w];
-        re = fma(a.x, x.x, re);
-        re = fma(-a.y, x.y, re);
-        im = fma(a.x, x.y, im);
-        im = fma(a.y, x.x, im);
+        for (int t = 0; t < run; ++t) {
+            const T2 a = win[pos - t];
+            const T2 x = xs[w + t];
+            re = fma(a.x, x.x, re);
+            re = fma(-a.y, x.y, re);
+            im = fma(a.x, x.y, im);
+            im = fma(a.y, x.x, im);
+        }
+        w += run;
     }
     red[tid] = T2{re, im};
     __syncthreads();
@@ -1230,7 +1243,7 @@ int tuned_fragments(prony_handle_t h, int d, int n, int m, int prec, int batched
 // form alone, e.g. 5 instead of 6 at m = 20 and 6 instead of 8 at m = 30).
 prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, size_t tsize, PencilPlan& P,
                          int target_wgs = 0, int rf_req = 0, int mode = 0, bool split = false,
-                         bool allow_gauss = false) {
+                         bool allow_gauss = false, int kal_req = 0) {
     P = PencilPlan{};
     P.d = d;
     P.n = n;
@@ -1274,7 +1287,9 @@ prony_status_t make_plan(prony_handle_t h, int d, int n, int m, bool with_s0, si
     P.bbufs = 2;
     const int target = target_wgs > 0 ? target_wgs : 4 * h->num_cus;
     const int sk_target = std::max(1, target / P.rt);
-    const size_t kal = split ? kSplitK : 16;   // chunk granularity: K blocks of the MFMA loop
+    // chunk granularity: K blocks of the MFMA loop, or kal_req (whole lines or planes of
+    // I_n for the one-column product, whose windows are then the narrowest)
+    const size_t kal = kal_req > 0 ? (size_t)kal_req : split ? kSplitK : 16;
     int kc = (int)align_up((size_t)((P.kb + sk_target - 1) / sk_target), kal);
     kc = std::max(kc, std::min(128, (int)align_up((size_t)P.kb, kal)));
     const int kc0 = kc;
@@ -1599,6 +1614,19 @@ prony_status_t dispatch_mm(prony_handle_t h, const PencilPlan& P, const TilePtrs
     return launch_mm_tiles<T, 1, 1>(h, P, ptr);
 }
 
+// LDS of toeplitz_mv under plan P: the window, the chunk's h offsets and x values,
+// one partial sum per thread.
+size_t mv_lds_bytes(const PencilPlan& P, size_t tsize) {
+    return align_up(2 * tsize * (size_t)P.win_cap, 16) + align_up(4 * (size_t)P.kc, 16) +
+           2 * tsize * ((size_t)P.kc + kThreads);
+}
+
+// Whether a product plan runs on toeplitz_mv (one column, rows per tile at most the
+// threads of a workgroup, LDS within the device limit).
+bool mv_fits(prony_handle_t h, const PencilPlan& P, size_t tsize) {
+    return P.CB == 1 && P.rows <= kThreads && mv_lds_bytes(P, tsize) <= h->lds_per_block;
+}
+
 template <typename T>
 prony_status_t launch_toeplitz_mm(prony_handle_t h, const PencilPlan& P, const double* f, const double* X,
                                   int64_t ldx, double* Y, int64_t ldy) {
@@ -1620,9 +1648,8 @@ prony_status_t launch_toeplitz_mm(prony_handle_t h, const PencilPlan& P, const d
     const TilePtrs<T> ptr{reinterpret_cast<const double2*>(f), vp, nullptr, gt, part, nullptr, nullptr};
     // one column: the vector kernel on the same plan (window, h offsets and x of a
     // chunk, and one partial sum per thread, in LDS)
-    const size_t mv_lds = align_up(sizeof(T2) * (size_t)P.win_cap, 16) + align_up(4 * (size_t)P.kc, 16) +
-                          sizeof(T2) * ((size_t)P.kc + kThreads);
-    if (P.CB == 1 && P.rows <= kThreads && mv_lds <= h->lds_per_block) {
+    const size_t mv_lds = mv_lds_bytes(P, sizeof(T));
+    if (mv_fits(h, P, sizeof(T))) {
         if (mv_lds > 65536) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&toeplitz_mv<T>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)mv_lds);
@@ -1634,6 +1661,7 @@ prony_status_t launch_toeplitz_mm(prony_handle_t h, const PencilPlan& P, const d
         }
         if ((st = check_launch(h, "toeplitz_mv")) != PRONY_OK) return st;
     } else {
+        if (P.kc % 16) return fail(h, PRONY_ENOTSUP, "prony_toeplitz_mm: chunk not a multiple of 16");
         if ((st = dispatch_mm<T>(h, P, ptr)) != PRONY_OK) return st;
         if ((st = check_launch(h, "toeplitz_mm_tiles")) != PRONY_OK) return st;
     }
@@ -2345,9 +2373,14 @@ extern "C" prony_status_t prony_toeplitz_mm(prony_handle_t h, int d, int n, int 
     PencilPlan P;
     const size_t ts = prec == PRONY_FP32 ? sizeof(float) : sizeof(double);
     // one column (toeplitz_mv): eight workgroups per CU, whose smaller windows let more
-    // of them share a CU (d = 3, n = 20: 75 -> 57 us per product against four)
+    // of them share a CU (d = 3, n = 20: 75 -> 57 us per product against four), and
+    // chunks of whole planes of I_n (d >= 3) or whole lines (d = 2)
     const int target = r == 1 ? 8 * h->num_cus : 0;
-    if ((st = make_plan(h, d, n, r, false, ts, P, target, 0, 1, false, true)) != PRONY_OK) return st;
+    const int kal = r == 1 && d >= 2 ? (int)ipow(n + 1, d >= 3 ? d - 1 : 1) : 0;
+    st = make_plan(h, d, n, r, false, ts, P, target, 0, 1, false, true, kal);
+    if (kal > 0 && (st != PRONY_OK || !mv_fits(h, P, ts)))   // chunks of multiples of 16 instead
+        st = make_plan(h, d, n, r, false, ts, P, target, 0, 1, false, true);
+    if (st != PRONY_OK) return st;
     P.conj_grid = adjoint;
     return prec == PRONY_FP32 ? launch_toeplitz_mm<float>(h, P, f, X, ldx, Y, ldy)
                               : launch_toeplitz_mm<double>(h, P, f, X, ldx, Y, ldy);
