@@ -1,6 +1,8 @@
 """GPU products with the multilevel Toeplitz matrix (Y = T X, T^* X) for the block
-power SVD (Sec. 2.2, Algorithm 3), against the oracle's dense T; the block power SVD
-driven by them against LAPACK; Algorithm 1 end to end without forming T.
+power SVD (Sec. 2.2, Algorithm 3), against the oracle's dense T, and the one-column
+products of the Lanczos bidiagonalization (Sec. 2.1, Algorithm 2; the vector kernel),
+also at the paper's size on sampled rows; the block power SVD driven by them against
+LAPACK; Algorithm 1 end to end without forming T.
 
 Tolerances: 1e-12 (FP64 products), 1e-5 (FP32 products), normwise and entry by
 entry; singular values 1e-10 relative."""
